@@ -1,0 +1,30 @@
+"""FP64 CPU oracle for the complex Ginzburg--Landau exponential stepper.
+
+TEST INFRASTRUCTURE ONLY.  This package is a plain, slow, obviously correct
+NumPy/SciPy implementation of what the GPU library computes, written from
+the paper (Caliari & Cassini, "Efficient simulation of complex
+Ginzburg--Landau equations using high-order exponential-type methods").
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import it.  It shares no code with the HIP library and never
+imports it; the library never imports this package.
+
+Contents (each function cites the passage it follows):
+
+* ``operators``  -- 1-D finite-difference operators A_mu (eq. ODEs), their
+  exponentials by the closed-form sine/cosine eigen-decomposition and by
+  ``scipy.linalg.expm``.
+* ``tensor``     -- mu-mode product, Tucker operator (eq. Tucker), Kronecker
+  sum K (eq. ODEs) for brute-force checks, K u via eq. (kronsumv).
+* ``nonlinear``  -- g(u) of eq. (cqCGL), the exact cubic and quintic flows
+  (eq. exsolcub and its quintic analogue in Section 4.3), one classical RK4
+  step of u' = g(u) (eq. RK4 with K = 0) as the cubic-quintic sub-flow.
+* ``steppers``   -- Strang (eq. Strang) and Lawson4 (eq. lawson4) exactly as
+  written (six exponential actions per Lawson4 step), plus a time loop.
+* ``metrics``    -- relative 2-norm / infinity-norm errors and the observed
+  order of convergence used in the paper's tables.
+* ``split``      -- bf16 term split and an FP32-accumulation emulator of the
+  split-precision mode product (predicts its rounding error).
+* ``surrogate``  -- FP64 residual CNN forward/backward (3x3 convolutions).
+
+All arithmetic is complex128 / float64 unless a function says otherwise.
+"""

@@ -1,0 +1,93 @@
+"""1-D operators A_mu and their exponentials (oracle; test infrastructure only).
+
+The semi-discretised system is u' = K u + g(u) with K the Kronecker sum of
+A_mu ~ (a1 + i b1) d^2/dx_mu^2 + a2/d (eq. ODEs and the display after it).
+The workloads use 2nd-order central differences:
+
+* Dirichlet, interior nodes, h = (b-a)/(n+1):  D2 = tridiag(1, -2, 1) / h^2.
+* Neumann, vertex grid, h = (b-a)/(n-1): interior rows (1, -2, 1)/h^2; the
+  boundary rows use the ghost value of the centred u' = 0 condition, which
+  gives (-2, 2)/h^2 in the first row and (2, -2)/h^2 in the last row.
+
+The exponentials exp(t A_mu) are needed once per run (Section 3.1: computed
+once and for all when the step size is constant).  Two independent routes:
+
+* ``exp_closed_form``: the textbook eigen-decomposition of the 2nd-order
+  Laplacian (sine basis for Dirichlet, cosine basis for Neumann).
+* ``exp_scipy``: ``scipy.linalg.expm`` (Pade with scaling and squaring, the
+  method the paper cites for its small exponentials).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg
+
+DIRICHLET = 0
+NEUMANN = 1
+
+
+def spacing(n: int, a: float, b: float, bc: int) -> float:
+    if bc == DIRICHLET:
+        return (b - a) / (n + 1)
+    if bc == NEUMANN:
+        return (b - a) / (n - 1)
+    raise ValueError("bc")
+
+
+def laplacian_2nd(n: int, a: float, b: float, bc: int) -> np.ndarray:
+    """Dense n x n 2nd-order finite-difference second derivative (real)."""
+    h = spacing(n, a, b, bc)
+    D = np.zeros((n, n))
+    for j in range(n):
+        D[j, j] = -2.0
+        if j > 0:
+            D[j, j - 1] = 1.0
+        if j < n - 1:
+            D[j, j + 1] = 1.0
+    if bc == NEUMANN:
+        # ghost node u_{-1} = u_{1} (and u_{n} = u_{n-2}) from the centred u' = 0
+        D[0, 1] = 2.0
+        D[n - 1, n - 2] = 2.0
+    return D / (h * h)
+
+
+def operator_A(n: int, a: float, b: float, bc: int, coeffs, d: int) -> np.ndarray:
+    """A_mu = (a1 + i b1) D2 + (a2/d) I, complex128 (display after eq. ODEs)."""
+    a1, b1, a2 = coeffs[0], coeffs[1], coeffs[2]
+    D = laplacian_2nd(n, a, b, bc)
+    return (complex(a1, b1) * D + (a2 / d) * np.eye(n)).astype(np.complex128)
+
+
+def eigen_2nd(n: int, a: float, b: float, bc: int):
+    """Eigenvalues and eigenvector matrix of ``laplacian_2nd``.
+
+    Dirichlet: V_jk = sqrt(2/(n+1)) sin(pi j k/(n+1)), j,k = 1..n (orthogonal,
+    symmetric), lambda_k = -(4/h^2) sin^2(pi k / (2(n+1))).
+    Neumann (vertex grid): C_jk = cos(pi j k/(n-1)), j,k = 0..n-1,
+    lambda_k = -(4/h^2) sin^2(pi k / (2(n-1))).
+    """
+    h = spacing(n, a, b, bc)
+    if bc == DIRICHLET:
+        j = np.arange(1, n + 1)
+        V = np.sqrt(2.0 / (n + 1)) * np.sin(np.pi * np.outer(j, j) / (n + 1))
+        lam = -(4.0 / (h * h)) * np.sin(np.pi * j / (2.0 * (n + 1))) ** 2
+        return lam, V
+    j = np.arange(0, n)
+    C = np.cos(np.pi * np.outer(j, j) / (n - 1))
+    lam = -(4.0 / (h * h)) * np.sin(np.pi * j / (2.0 * (n - 1))) ** 2
+    return lam, C
+
+
+def exp_closed_form(n: int, a: float, b: float, bc: int, coeffs, d: int, t: float) -> np.ndarray:
+    """exp(t A_mu) from the eigen-decomposition: V diag(exp(t((a1+ib1) lam + a2/d))) V^{-1}."""
+    a1, b1, a2 = coeffs[0], coeffs[1], coeffs[2]
+    lam, V = eigen_2nd(n, a, b, bc)
+    w = np.exp(t * (complex(a1, b1) * lam + a2 / d))
+    if bc == DIRICHLET:
+        return (V * w) @ V.T
+    return (V * w) @ np.linalg.inv(V)
+
+
+def exp_scipy(A: np.ndarray, t: float) -> np.ndarray:
+    """exp(t A) by scipy.linalg.expm (any dense A)."""
+    return scipy.linalg.expm(t * np.asarray(A, dtype=np.complex128))
