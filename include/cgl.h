@@ -1,0 +1,171 @@
+/*
+ * cgl.h -- C ABI of an MI355X (gfx950) exponential time stepper for the
+ * cubic and cubic-quintic complex Ginzburg--Landau equation
+ *
+ *   d_t u = (a1 + i b1) Lap u + a2 u + (a3 + i b3)|u|^2 u + (a4 + i b4)|u|^4 u
+ *
+ * (Caliari & Cassini, eq. cqCGL) on Cartesian grids with homogeneous
+ * Dirichlet or Neumann boundaries.  After a finite-difference
+ * semi-discretisation the system is u' = K u + g(u) with K the Kronecker sum
+ * of the 1-D operators A_mu (eq. ODEs).  The action of exp(t K) is computed as
+ * the Tucker operator U x_1 exp(t A_1) x_2 ... x_d exp(t A_d) (eq. Tucker) of
+ * dense mu-mode products; it is interleaved with the pointwise nonlinear flow
+ * inside Strang (eq. Strang) and Lawson4 (eq. lawson4) steps with a constant
+ * step size tau, so the small exponentials are computed once per plan
+ * (Section 3.1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Status codes are returned; nothing aborts.  Argument errors are detected
+ *   synchronously on the host.  Conditions that arise on the device
+ *   (non-finite state, exact-flow domain violated) are latched in a device
+ *   flag and reported by cgl_run at its check points and by cgl_status.
+ * - State tensors are device pointers to interleaved complex numbers, index 1
+ *   fastest (the column-stacking vec of eq. kronsumv): element (i1,..,id)
+ *   lives at i1 + n1*(i2 + n2*(i3 ...)).  Their type follows the plan's
+ *   precision: complex128 (double re, double im) for CGL_FP64; complex64
+ *   (float re, float im) for CGL_SPLIT_BF16, or complex128 when that plan was
+ *   made with CGL_FLAG_FP64_MASTER.  The caller owns state memory; the plan
+ *   owns everything else (operators, stage tensors, graphs, flags).
+ * - Matrices passed on the host are complex128, column-major, n x n
+ *   (element (i, j) at 2*(i + n*j) re, +1 im).
+ * - All device work is enqueued on the plan's HIP stream (the one given to
+ *   cgl_plan; NULL means the legacy default stream) and is stream-ordered;
+ *   only cgl_run check points, cgl_status, cgl_get_operator of device data and
+ *   cgl_destroy synchronise.  One plan must not be used from two host threads
+ *   at once.
+ */
+#ifndef CGL_ABI_H_
+#define CGL_ABI_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cgl_plan_s* cgl_plan_t;
+
+/* Coefficients of eq. (cqCGL).  a4 = b4 = 0 is the cubic equation.  The
+ * paper assumes a1 > 0 (Section 1); cgl_plan rejects a1 <= 0. */
+typedef struct {
+  double a1, b1, a2, a3, b3, a4, b4;
+} cgl_coeffs;
+
+enum {
+  CGL_OK = 0,
+  CGL_EINVAL = -1,     /* bad argument (sizes, pointers, tau, mu, method) */
+  CGL_ENOMEM = -2,     /* host or device allocation failed */
+  CGL_EDEVICE = -3,    /* a HIP runtime call failed */
+  CGL_ENOTREADY = -4,  /* a step was requested before every mu has operators */
+  CGL_ENONFINITE = -5, /* the state became NaN/Inf (the paper's "x" entries) */
+  CGL_EBLOWUP = -6,    /* 1 - 2 a3 |u|^2 t <= 0 in the exact cubic flow */
+  CGL_EGATE = -7       /* a surrogate jump failed its a-posteriori check */
+};
+
+enum { CGL_FP64 = 0, CGL_SPLIT_BF16 = 1 };         /* precision form */
+enum { CGL_STRANG = 0, CGL_LAWSON4 = 1 };          /* time stepper */
+enum { CGL_DIRICHLET = 0, CGL_NEUMANN = 1 };       /* boundary type */
+enum { CGL_E = 0, CGL_H = 1 };                     /* exp(tau A) or exp(tau A / 2) */
+
+/* plan flags */
+#define CGL_FLAG_FP64_MASTER 1u /* split form: the caller's state is complex128 and
+                                   every step's final update is made in FP64 */
+#define CGL_FLAG_RK4_FLOW 2u    /* Strang: use the RK4 sub-flow even when the
+                                   nonlinearity is cubic (default: exact flow) */
+
+/* Create a plan for a d-dimensional grid n[0..d-1] (n[mu] >= 3, d in 1..3),
+ * coefficients c, constant step tau > 0 and a precision form.  hip_stream is
+ * a hipStream_t (may be NULL).  On success *out receives the plan; the plan is
+ * not ready to step until cgl_set_operators was called for every mu.
+ * Errors: CGL_EINVAL (d, n, tau, a1 <= 0, precision, flags, null pointers),
+ * CGL_ENOMEM, CGL_EDEVICE. */
+int cgl_plan(cgl_plan_t* out, int d, const int64_t* n, const cgl_coeffs* c, double tau,
+             int precision, unsigned flags, void* hip_stream);
+
+/* Give the 1-D operator A_mu (host, complex128 column-major n_mu x n_mu;
+ * copied).  The plan computes E_mu = exp(tau A_mu) and H_mu = exp(tau A_mu/2)
+ * in FP64 by Pade approximation with scaling and squaring (the route the
+ * paper uses for its small exponentials, Section 3.1), converts them to the
+ * plan's device form and uploads them on the plan stream.  mu is 0-based.
+ * Errors: CGL_EINVAL (mu out of range, null A, non-finite A), CGL_EDEVICE. */
+int cgl_set_operators(cgl_plan_t p, int mu, const double* A);
+
+/* Give exp(tau A_mu) and exp(tau A_mu / 2) directly (host, complex128
+ * column-major), bypassing the Pade route.  Same errors as cgl_set_operators. */
+int cgl_set_exponentials(cgl_plan_t p, int mu, const double* E, const double* H);
+
+/* Build the 2nd-order central finite-difference operator
+ * A = (a1 + i b1) D2 + (a2/d) I of one direction (display after eq. ODEs):
+ * Dirichlet on interior nodes, h = (b-a)/(n+1), D2 = tridiag(1,-2,1)/h^2;
+ * Neumann on the vertex grid, h = (b-a)/(n-1), boundary rows (-2,2)/h^2 and
+ * (2,-2)/h^2 from the centred u' = 0 ghost value.  A_out: host, 2*n*n
+ * doubles, complex128 column-major.  Errors: CGL_EINVAL. */
+int cgl_fd_operator(int64_t n, double a, double b, int bc, const cgl_coeffs* c, int d,
+                    double* A_out);
+
+/* exp(t A) of a host complex128 column-major n x n matrix by the plan's Pade
+ * routine (no plan needed).  out: host, 2*n*n doubles.  Errors: CGL_EINVAL. */
+int cgl_expm(int64_t n, const double* A, double t, double* out);
+
+/* Copy the FP64 exponential the plan holds for direction mu (which = CGL_E
+ * or CGL_H) to out_host (2*n_mu*n_mu doubles, complex128 column-major).
+ * Errors: CGL_EINVAL, CGL_ENOTREADY. */
+int cgl_get_operator(cgl_plan_t p, int mu, int which, double* out_host);
+
+/* One mu-mode product out = in x_mu M with M = E_mu or H_mu (Section 3.1):
+ * out[.., i_mu, ..] = sum_j M[i_mu, j] in[.., j, ..].  in_dev/out_dev are
+ * device state tensors of the plan's stage type (complex128 for CGL_FP64,
+ * complex64 for CGL_SPLIT_BF16); they must not overlap.  Asynchronous.
+ * Errors: CGL_EINVAL, CGL_ENOTREADY, CGL_EDEVICE. */
+int cgl_mode_product(cgl_plan_t p, int mu, int which, const void* in_dev, void* out_dev);
+
+/* The Tucker operator out = in x_1 M_1 ... x_d M_d (eq. Tucker), i.e.
+ * exp(tau K) (which = CGL_E) or exp(tau K/2) (CGL_H) applied to in.  Same
+ * types and errors as cgl_mode_product; in_dev may equal out_dev. */
+int cgl_tucker(cgl_plan_t p, int which, const void* in_dev, void* out_dev);
+
+/* Advance u_dev in place by nsteps >= 0 Strang steps (eq. Strang),
+ * u <- phi_{tau/2}(exp(tau K) phi_{tau/2}(u)).  phi is the exact cubic flow
+ * (eq. exsolcub) when a4 = b4 = 0 and CGL_FLAG_RK4_FLOW is not set, otherwise
+ * one classical RK4 step of u' = g(u) (eq. RK4 with K = 0).  Asynchronous;
+ * device conditions are latched (see cgl_status).
+ * Errors: CGL_EINVAL, CGL_ENOTREADY, CGL_EDEVICE. */
+int cgl_step_strang(cgl_plan_t p, void* u_dev, int64_t nsteps);
+
+/* Advance u_dev in place by nsteps Lawson4 steps (eq. lawson4).  The six
+ * exponential actions of the scheme are evaluated as four actions of
+ * exp(tau K/2) in two rounds over tensor pairs, using
+ * exp(tau K) = exp(tau K/2) exp(tau K/2).  Same errors as cgl_step_strang. */
+int cgl_step_lawson4(cgl_plan_t p, void* u_dev, int64_t nsteps);
+
+/* Advance u_dev by nsteps steps of method (CGL_STRANG / CGL_LAWSON4),
+ * replaying a captured HIP graph of check_every steps (check_every <= 0:
+ * one chunk of nsteps).  After every chunk the device flags are read; the
+ * run stops early and returns CGL_ENONFINITE or CGL_EBLOWUP when one is set.
+ * Synchronises the plan stream at each check point.  Since tau is constant
+ * and the plan holds the exponentials, (u, step count) is a complete
+ * checkpoint: a stopped run can be resumed by calling again. */
+int cgl_run(cgl_plan_t p, int method, void* u_dev, int64_t nsteps, int64_t check_every);
+
+/* Synchronise the plan stream and return the latched device condition
+ * (CGL_OK, CGL_ENONFINITE or CGL_EBLOWUP); clears it. */
+int cgl_status(cgl_plan_t p);
+
+/* Enqueue a clear of the latched device condition on the plan stream. */
+int cgl_clear_status(cgl_plan_t p);
+
+/* Synchronise and free everything the plan owns.  NULL is accepted. */
+void cgl_destroy(cgl_plan_t p);
+
+/* Static message for a status code. */
+const char* cgl_strerror(int status);
+
+/* Number of bf16 terms used per operator entry by a CGL_SPLIT_BF16 plan. */
+int cgl_split_terms(cgl_plan_t p, int* op_terms, int* state_terms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CGL_ABI_H_ */

@@ -67,13 +67,17 @@ def eigen_2nd(n: int, a: float, b: float, bc: int):
     lambda_k = -(4/h^2) sin^2(pi k / (2(n-1))).
     """
     h = spacing(n, a, b, bc)
+    # sin / cos are 2 pi periodic: reduce the integer j*k modulo the period
+    # before scaling, so large arguments lose no accuracy
     if bc == DIRICHLET:
         j = np.arange(1, n + 1)
-        V = np.sqrt(2.0 / (n + 1)) * np.sin(np.pi * np.outer(j, j) / (n + 1))
+        jk = np.outer(j, j) % (2 * (n + 1))
+        V = np.sqrt(2.0 / (n + 1)) * np.sin(np.pi * jk / (n + 1))
         lam = -(4.0 / (h * h)) * np.sin(np.pi * j / (2.0 * (n + 1))) ** 2
         return lam, V
     j = np.arange(0, n)
-    C = np.cos(np.pi * np.outer(j, j) / (n - 1))
+    jk = np.outer(j, j) % (2 * (n - 1))
+    C = np.cos(np.pi * jk / (n - 1))
     lam = -(4.0 / (h * h)) * np.sin(np.pi * j / (2.0 * (n - 1))) ** 2
     return lam, C
 
@@ -85,7 +89,12 @@ def exp_closed_form(n: int, a: float, b: float, bc: int, coeffs, d: int, t: floa
     w = np.exp(t * (complex(a1, b1) * lam + a2 / d))
     if bc == DIRICHLET:
         return (V * w) @ V.T
-    return (V * w) @ np.linalg.inv(V)
+    # inverse of the cosine basis: C^{-1} = (2/(n-1)) W C W, W = diag(1/2, 1, ..., 1, 1/2)
+    # (discrete orthogonality of cos(pi j k/(n-1)) with trapezoid weights)
+    W = np.ones(n)
+    W[0] = W[-1] = 0.5
+    Cinv = (2.0 / (n - 1)) * (W[:, None] * V * W[None, :])
+    return (V * w) @ Cinv
 
 
 def exp_scipy(A: np.ndarray, t: float) -> np.ndarray:

@@ -1,0 +1,164 @@
+"""Thin Python binding of the CGL stepper (same names as the C ABI).
+
+PyTorch provides device memory and the stream; the library does all of the
+work.  State tensors are 1-D complex torch tensors of N = prod(n) elements
+holding the column-stacked (index 1 fastest) grid function; ``to_device`` /
+``to_host`` convert from / to NumPy arrays of shape n.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import CGLError, check
+
+PRECISIONS = {"fp64": L.FP64, "split": L.SPLIT_BF16}
+METHODS = {"strang": L.STRANG, "lawson4": L.LAWSON4}
+
+
+def _coeffs(c) -> L.Coeffs:
+    v = tuple(float(x) for x in (c.as_tuple() if hasattr(c, "as_tuple") else c))
+    v = v + (0.0,) * (7 - len(v))
+    return L.Coeffs(*v)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def fd_operator(n: int, a: float, b: float, bc: int, coeffs, d: int) -> np.ndarray:
+    """cgl_fd_operator: 2nd-order FD A_mu as a complex128 (n, n) array."""
+    out = np.zeros((n, n), dtype=np.complex128, order="F")
+    c = _coeffs(coeffs)
+    check(L.lib().cgl_fd_operator(n, a, b, bc, C.byref(c), d, _dptr(out)), "cgl_fd_operator")
+    return out
+
+
+def expm(A: np.ndarray, t: float) -> np.ndarray:
+    """cgl_expm: the library's Pade exponential of a host matrix."""
+    A = np.asfortranarray(A, dtype=np.complex128)
+    out = np.zeros_like(A, order="F")
+    check(L.lib().cgl_expm(A.shape[0], _dptr(A), float(t), _dptr(out)), "cgl_expm")
+    return out
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def current_stream_handle() -> int:
+    torch = _torch()
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Plan:
+    """cgl_plan + the calls that take it."""
+
+    def __init__(self, n: Sequence[int], coeffs, tau: float, precision: str = "fp64",
+                 master: bool = False, rk4_flow: bool = False, stream: Optional[int] = None):
+        self.n = tuple(int(v) for v in n)
+        self.d = len(self.n)
+        self.N = int(np.prod(self.n))
+        self.tau = float(tau)
+        self.precision = precision
+        self.master = bool(master)
+        flags = (L.FLAG_FP64_MASTER if master else 0) | (L.FLAG_RK4_FLOW if rk4_flow else 0)
+        if stream is None:
+            stream = current_stream_handle()
+        self._stream = stream
+        arr = (C.c_int64 * self.d)(*self.n)
+        c = _coeffs(coeffs)
+        h = C.c_void_p()
+        check(L.lib().cgl_plan(C.byref(h), self.d, arr, C.byref(c), self.tau,
+                               PRECISIONS[precision], flags, C.c_void_p(stream)), "cgl_plan")
+        self._h = h
+
+    # -- element types -------------------------------------------------------
+    @property
+    def state_dtype(self):
+        torch = _torch()
+        return torch.complex128 if (self.precision == "fp64" or self.master) else torch.complex64
+
+    @property
+    def stage_dtype(self):
+        torch = _torch()
+        return torch.complex128 if self.precision == "fp64" else torch.complex64
+
+    def to_device(self, u: np.ndarray, dtype=None):
+        torch = _torch()
+        flat = np.ascontiguousarray(np.asarray(u).reshape(-1, order="F"))
+        return torch.from_numpy(flat.astype(np.complex128)).to(
+            device="cuda", dtype=dtype or self.state_dtype)
+
+    def to_host(self, t) -> np.ndarray:
+        return t.detach().to("cpu").numpy().astype(np.complex128).reshape(self.n, order="F")
+
+    # -- setup ---------------------------------------------------------------
+    def set_operators(self, mu: int, A: np.ndarray) -> None:
+        A = np.asfortranarray(A, dtype=np.complex128)
+        check(L.lib().cgl_set_operators(self._h, mu, _dptr(A)), "cgl_set_operators")
+
+    def set_exponentials(self, mu: int, E: np.ndarray, H: np.ndarray) -> None:
+        E = np.asfortranarray(E, dtype=np.complex128)
+        H = np.asfortranarray(H, dtype=np.complex128)
+        check(L.lib().cgl_set_exponentials(self._h, mu, _dptr(E), _dptr(H)), "cgl_set_exponentials")
+
+    def set_fd_operators(self, a: float, b: float, bc: int, coeffs) -> None:
+        for mu, nm in enumerate(self.n):
+            self.set_operators(mu, fd_operator(nm, a, b, bc, coeffs, self.d))
+
+    def get_operator(self, mu: int, which: int) -> np.ndarray:
+        nm = self.n[mu]
+        out = np.zeros((nm, nm), dtype=np.complex128, order="F")
+        check(L.lib().cgl_get_operator(self._h, mu, which, _dptr(out)), "cgl_get_operator")
+        return out
+
+    def split_terms(self):
+        a, b = C.c_int(), C.c_int()
+        check(L.lib().cgl_split_terms(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    # -- device work ---------------------------------------------------------
+    def mode_product(self, mu: int, which: int, x, out) -> None:
+        check(L.lib().cgl_mode_product(self._h, mu, which, C.c_void_p(x.data_ptr()),
+                                       C.c_void_p(out.data_ptr())), "cgl_mode_product")
+
+    def tucker(self, which: int, x, out) -> None:
+        check(L.lib().cgl_tucker(self._h, which, C.c_void_p(x.data_ptr()),
+                                 C.c_void_p(out.data_ptr())), "cgl_tucker")
+
+    def step_strang(self, u, nsteps: int = 1) -> None:
+        check(L.lib().cgl_step_strang(self._h, C.c_void_p(u.data_ptr()), int(nsteps)), "cgl_step_strang")
+
+    def step_lawson4(self, u, nsteps: int = 1) -> None:
+        check(L.lib().cgl_step_lawson4(self._h, C.c_void_p(u.data_ptr()), int(nsteps)),
+              "cgl_step_lawson4")
+
+    def run(self, method: str, u, nsteps: int, check_every: int = 0) -> int:
+        """cgl_run; returns the status code (CGL_ENONFINITE etc. are not raised)."""
+        st = L.lib().cgl_run(self._h, METHODS[method], C.c_void_p(u.data_ptr()), int(nsteps),
+                             int(check_every))
+        if st not in (L.OK, L.ENONFINITE, L.EBLOWUP):
+            raise CGLError(st, "cgl_run")
+        return st
+
+    def status(self) -> int:
+        return L.lib().cgl_status(self._h)
+
+    def clear_status(self) -> None:
+        check(L.lib().cgl_clear_status(self._h))
+
+    def destroy(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.lib().cgl_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

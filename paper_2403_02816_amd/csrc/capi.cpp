@@ -1,0 +1,511 @@
+// C ABI of the CGL exponential stepper: plans, operator setup, pass
+// sequencing of the Tucker operator inside Strang and Lawson4 steps, and
+// graph-captured runs with flag checks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "../../include/cgl.h"
+#include "host_numerics.hpp"
+#include "kernels.hpp"
+#include "split_layout.hpp"
+
+using namespace cgl;
+
+namespace {
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+struct DeviceOp {
+  void* ptr = nullptr;  // FP64 embedding (double) or bf16 term planes (uint16_t)
+  int Pp = 0, Kp = 0;
+};
+
+struct GraphKey {
+  int method;
+  void* u;
+  int64_t k;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(method, u, k) < std::tie(o.method, o.u, o.k);
+  }
+};
+
+}  // namespace
+
+struct cgl_plan_s {
+  int d = 0;
+  int64_t n[3] = {1, 1, 1};
+  int64_t N = 0;
+  cgl_coeffs c{};
+  double tau = 0.0;
+  int precision = CGL_FP64;
+  unsigned flags = 0;
+  hipStream_t ustream = nullptr;  // caller's stream
+  hipStream_t gstream = nullptr;  // plan-owned stream used for graph capture/replay
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  bool have_ops[3] = {false, false, false};
+  CMat E[3], H[3];
+  DeviceOp dE[3], dH[3];
+  void* stage[4] = {nullptr, nullptr, nullptr, nullptr};
+  unsigned* dflag = nullptr;
+  unsigned* hflag = nullptr;  // pinned
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  NlParams nl{};
+};
+
+namespace {
+
+bool ready(const cgl_plan_s* p) {
+  for (int mu = 0; mu < p->d; ++mu)
+    if (!p->have_ops[mu]) return false;
+  return true;
+}
+
+size_t stage_bytes(const cgl_plan_s* p) {
+  return static_cast<size_t>(p->N) * (p->precision == CGL_FP64 ? 16 : 8);
+}
+
+bool master(const cgl_plan_s* p) {
+  return p->precision == CGL_SPLIT_BF16 && (p->flags & CGL_FLAG_FP64_MASTER);
+}
+
+size_t user_bytes(const cgl_plan_s* p) {
+  return static_cast<size_t>(p->N) * ((p->precision == CGL_FP64 || master(p)) ? 16 : 8);
+}
+
+void free_op(DeviceOp& o) {
+  if (o.ptr) (void)hipFree(o.ptr);
+  o.ptr = nullptr;
+}
+
+// Upload one exponential in the plan's device form.
+int upload_op(cgl_plan_s* p, const CMat& M, DeviceOp& dst) {
+  const int64_t n = M.n;
+  free_op(dst);
+  if (p->precision == CGL_FP64) {
+    const int Pp = static_cast<int>(round_up(2 * n, F64_PT));
+    const int Kp = static_cast<int>(round_up(2 * n, F64_KC));
+    std::vector<double> h(static_cast<size_t>(Pp) * Kp, 0.0);
+    // embedding rows p' = 2m + c', columns k' = 2k + c of [[Re, -Im], [Im, Re]],
+    // stored with k' as the row index and p' fastest
+    for (int64_t k = 0; k < n; ++k)
+      for (int64_t m = 0; m < n; ++m) {
+        const double re = M.re[m + n * k], im = M.im[m + n * k];
+        h[(2 * k) * Pp + 2 * m] = re;
+        h[(2 * k) * Pp + 2 * m + 1] = im;
+        h[(2 * k + 1) * Pp + 2 * m] = -im;
+        h[(2 * k + 1) * Pp + 2 * m + 1] = re;
+      }
+    if (hipMalloc(&dst.ptr, h.size() * sizeof(double)) != hipSuccess) return CGL_ENOMEM;
+    if (hipMemcpyAsync(dst.ptr, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice,
+                       p->ustream) != hipSuccess)
+      return CGL_EDEVICE;
+    if (hipStreamSynchronize(p->ustream) != hipSuccess) return CGL_EDEVICE;
+    dst.Pp = Pp;
+    dst.Kp = Kp;
+    return CGL_OK;
+  }
+  std::vector<uint16_t> h;
+  int Pp = 0, Kp = 0;
+  build_split_operator(M, h, Pp, Kp);
+  if (hipMalloc(&dst.ptr, h.size() * sizeof(uint16_t)) != hipSuccess) return CGL_ENOMEM;
+  if (hipMemcpyAsync(dst.ptr, h.data(), h.size() * sizeof(uint16_t), hipMemcpyHostToDevice,
+                     p->ustream) != hipSuccess)
+    return CGL_EDEVICE;
+  if (hipStreamSynchronize(p->ustream) != hipSuccess) return CGL_EDEVICE;
+  dst.Pp = Pp;
+  dst.Kp = Kp;
+  return CGL_OK;
+}
+
+// One mu-mode pass over one or two tensors.
+int pass(cgl_plan_s* p, int mu, int which, const void* in0, const void* in1, void* out0,
+         void* out1, int pro, int epi, int nt, bool in_f64, bool out_f64, hipStream_t s) {
+  const DeviceOp& op = (which == CGL_E) ? p->dE[mu] : p->dH[mu];
+  int64_t R = 1;
+  for (int nu = 0; nu < mu; ++nu) R *= p->n[nu];
+  const int n = static_cast<int>(p->n[mu]);
+  hipError_t e;
+  if (p->precision == CGL_FP64) {
+    PassF64 a{};
+    a.in0 = static_cast<const double*>(in0);
+    a.in1 = static_cast<const double*>(in1);
+    a.out0 = static_cast<double*>(out0);
+    a.out1 = static_cast<double*>(out1);
+    a.op = static_cast<const double*>(op.ptr);
+    a.R = R;
+    a.F = p->N / n;
+    a.n = n;
+    a.Pp = op.Pp;
+    a.Kp = op.Kp;
+    a.pro = pro;
+    a.epi = epi;
+    a.nl = p->nl;
+    a.flag = p->dflag;
+    e = launch_pass_f64(a, nt, s);
+  } else {
+    PassSplit a{};
+    a.in0 = in0;
+    a.in1 = in1;
+    a.out0 = out0;
+    a.out1 = out1;
+    a.op = static_cast<const uint16_t*>(op.ptr);
+    a.R = R;
+    a.F = p->N / n;
+    a.n = n;
+    a.Pp = op.Pp;
+    a.Kp = op.Kp;
+    a.pro = pro;
+    a.epi = epi;
+    a.in_f64 = in_f64 ? 1 : 0;
+    a.out_f64 = out_f64 ? 1 : 0;
+    a.nl = p->nl;
+    a.flag = p->dflag;
+    e = launch_pass_split(a, nt, s);
+  }
+  return e == hipSuccess ? CGL_OK : CGL_EDEVICE;
+}
+
+// d passes of one exponential action over one or two tensors.  Stage pairs
+// (stage[0], stage[1]) and (stage[2], stage[3]) alternate; a pass never reads
+// and writes the same buffer.  out0/out1 receive the last pass's result.
+int action(cgl_plan_s* p, int which, const void* in0, const void* in1, void* out0, void* out1,
+           int pro, int epi, int nt, bool in_f64, bool out_f64, hipStream_t s) {
+  void* pairs[2][2] = {{p->stage[0], p->stage[1]}, {p->stage[2], p->stage[3]}};
+  const int first = (in0 == pairs[0][0]) ? 1 : 0;
+  const void* c0 = in0;
+  const void* c1 = in1;
+  bool cf64 = in_f64;
+  for (int mu = 0; mu < p->d; ++mu) {
+    const bool last = (mu == p->d - 1);
+    void* d0 = last ? out0 : pairs[(first + mu) & 1][0];
+    void* d1 = last ? out1 : pairs[(first + mu) & 1][1];
+    bool tmp_copy = false;
+    if (last && (d0 == c0 || (nt == 2 && d1 == c1))) {
+      // the destination is the source (d = 1 in place): go through a stage buffer
+      d0 = pairs[(first + mu) & 1][0];
+      d1 = pairs[(first + mu) & 1][1];
+      tmp_copy = true;
+    }
+    const bool of64 = last ? out_f64 : false;
+    int st = pass(p, mu, which, c0, c1, d0, d1, mu == 0 ? pro : PRO_NONE, last ? epi : EPI_NONE,
+                  nt, cf64, of64, s);
+    if (st != CGL_OK) return st;
+    if (tmp_copy) {
+      // stage buffers are sized for the caller's element type (see cgl_plan)
+      const size_t bytes = of64 ? static_cast<size_t>(p->N) * 16 : stage_bytes(p);
+      if (hipMemcpyAsync(out0, d0, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return CGL_EDEVICE;
+      if (nt == 2 && epi != EPI_L4_R2 &&
+          hipMemcpyAsync(out1, d1, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return CGL_EDEVICE;
+    }
+    c0 = d0;
+    c1 = d1;
+    cf64 = of64;
+  }
+  return CGL_OK;
+}
+
+int enqueue_strang(cgl_plan_s* p, void* u, hipStream_t s) {
+  const bool m = master(p) || p->precision == CGL_FP64;
+  return action(p, CGL_E, u, nullptr, u, nullptr, PRO_FLOW, EPI_FLOW, 1,
+                p->precision == CGL_FP64 ? false : m, p->precision == CGL_FP64 ? false : m, s);
+}
+
+int enqueue_lawson4(cgl_plan_s* p, void* u, hipStream_t s) {
+  const bool m = p->precision == CGL_SPLIT_BF16 && master(p);
+  // round 1: (u, g(u)) -> (P, Q) -> (X, Y) in the stage pair the alternation ends on
+  const int d = p->d;
+  void* pairs[2][2] = {{p->stage[0], p->stage[1]}, {p->stage[2], p->stage[3]}};
+  void* x = pairs[(d - 1) & 1][0];
+  void* y = pairs[(d - 1) & 1][1];
+  int st = action(p, CGL_H, u, nullptr, x, y, PRO_LAWSON_G, EPI_L4_R1, 2, m, false, s);
+  if (st != CGL_OK) return st;
+  // round 2: (X, Y) -> (H X, H Y) -> u_{n+1}
+  return action(p, CGL_H, x, y, u, nullptr, PRO_NONE, EPI_L4_R2, 2, false, m, s);
+}
+
+int check_u(cgl_plan_s* p, void* u) {
+  if (!p || !u) return CGL_EINVAL;
+  if (!ready(p)) return CGL_ENOTREADY;
+  return CGL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cgl_strerror(int status) {
+  switch (status) {
+    case CGL_OK: return "ok";
+    case CGL_EINVAL: return "invalid argument";
+    case CGL_ENOMEM: return "out of memory";
+    case CGL_EDEVICE: return "HIP runtime error";
+    case CGL_ENOTREADY: return "operators not set for every direction";
+    case CGL_ENONFINITE: return "state became non-finite";
+    case CGL_EBLOWUP: return "exact cubic flow left its domain (blow-up)";
+    case CGL_EGATE: return "surrogate jump failed its a-posteriori check";
+    default: return "unknown status";
+  }
+}
+
+int cgl_fd_operator(int64_t n, double a, double b, int bc, const cgl_coeffs* c, int d,
+                    double* A_out) {
+  if (!c || !A_out || n < 3 || d < 1 || d > 3 || !(b > a)) return CGL_EINVAL;
+  if (bc != CGL_DIRICHLET && bc != CGL_NEUMANN) return CGL_EINVAL;
+  const CMat A = fd_operator_2nd(n, a, b, bc, c->a1, c->b1, c->a2, d);
+  A.to_interleaved(A_out);
+  return CGL_OK;
+}
+
+int cgl_expm(int64_t n, const double* A, double t, double* out) {
+  if (!A || !out || n < 1 || !std::isfinite(t)) return CGL_EINVAL;
+  const CMat M = CMat::from_interleaved(n, A);
+  CMat R;
+  if (!expm_pade13(M, t, R)) return CGL_EINVAL;
+  R.to_interleaved(out);
+  return CGL_OK;
+}
+
+int cgl_plan(cgl_plan_t* out, int d, const int64_t* n, const cgl_coeffs* c, double tau,
+             int precision, unsigned flags, void* hip_stream) {
+  if (!out) return CGL_EINVAL;
+  *out = nullptr;
+  if (!n || !c || d < 1 || d > 3) return CGL_EINVAL;
+  if (!(tau > 0.0) || !std::isfinite(tau)) return CGL_EINVAL;
+  if (!(c->a1 > 0.0)) return CGL_EINVAL;
+  if (precision != CGL_FP64 && precision != CGL_SPLIT_BF16) return CGL_EINVAL;
+  if (flags & ~(CGL_FLAG_FP64_MASTER | CGL_FLAG_RK4_FLOW)) return CGL_EINVAL;
+  if ((flags & CGL_FLAG_FP64_MASTER) && precision != CGL_SPLIT_BF16) return CGL_EINVAL;
+  const double cv[7] = {c->a1, c->b1, c->a2, c->a3, c->b3, c->a4, c->b4};
+  for (double v : cv)
+    if (!std::isfinite(v)) return CGL_EINVAL;
+  int64_t N = 1;
+  for (int mu = 0; mu < d; ++mu) {
+    if (n[mu] < 3 || n[mu] > 4096) return CGL_EINVAL;
+    N *= n[mu];
+  }
+  if (N > (int64_t(1) << 31)) return CGL_EINVAL;
+  cgl_plan_s* p = new (std::nothrow) cgl_plan_s();
+  if (!p) return CGL_ENOMEM;
+  p->d = d;
+  for (int mu = 0; mu < d; ++mu) p->n[mu] = n[mu];
+  p->N = N;
+  p->c = *c;
+  p->tau = tau;
+  p->precision = precision;
+  p->flags = flags;
+  p->ustream = static_cast<hipStream_t>(hip_stream);
+  p->nl.tau = tau;
+  p->nl.a3 = c->a3;
+  p->nl.b3 = c->b3;
+  p->nl.a4 = c->a4;
+  p->nl.b4 = c->b4;
+  p->nl.exact = (c->a4 == 0.0 && c->b4 == 0.0 && !(flags & CGL_FLAG_RK4_FLOW)) ? 1 : 0;
+  int st = CGL_OK;
+  if (hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev_out, hipEventDisableTiming) != hipSuccess)
+    st = CGL_EDEVICE;
+  for (int i = 0; i < 4 && st == CGL_OK; ++i)
+    if (hipMalloc(&p->stage[i], std::max(stage_bytes(p), user_bytes(p))) != hipSuccess)
+      st = CGL_ENOMEM;
+  if (st == CGL_OK && hipMalloc(reinterpret_cast<void**>(&p->dflag), 256) != hipSuccess)
+    st = CGL_ENOMEM;
+  if (st == CGL_OK && hipHostMalloc(reinterpret_cast<void**>(&p->hflag), 64) != hipSuccess)
+    st = CGL_ENOMEM;
+  if (st == CGL_OK && hipMemsetAsync(p->dflag, 0, 256, p->ustream) != hipSuccess)
+    st = CGL_EDEVICE;
+  if (st == CGL_OK && hipStreamSynchronize(p->ustream) != hipSuccess) st = CGL_EDEVICE;
+  if (st != CGL_OK) {
+    cgl_destroy(p);
+    return st;
+  }
+  *out = p;
+  return CGL_OK;
+}
+
+int cgl_set_exponentials(cgl_plan_t p, int mu, const double* E, const double* H) {
+  if (!p || !E || !H || mu < 0 || mu >= p->d) return CGL_EINVAL;
+  const int64_t n = p->n[mu];
+  for (int64_t k = 0; k < 2 * n * n; ++k)
+    if (!std::isfinite(E[k]) || !std::isfinite(H[k])) return CGL_EINVAL;
+  p->E[mu] = CMat::from_interleaved(n, E);
+  p->H[mu] = CMat::from_interleaved(n, H);
+  int st = upload_op(p, p->E[mu], p->dE[mu]);
+  if (st == CGL_OK) st = upload_op(p, p->H[mu], p->dH[mu]);
+  p->have_ops[mu] = (st == CGL_OK);
+  // graphs captured before hold the old operator pointers
+  for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+  p->graphs.clear();
+  return st;
+}
+
+int cgl_set_operators(cgl_plan_t p, int mu, const double* A) {
+  if (!p || !A || mu < 0 || mu >= p->d) return CGL_EINVAL;
+  const int64_t n = p->n[mu];
+  for (int64_t k = 0; k < 2 * n * n; ++k)
+    if (!std::isfinite(A[k])) return CGL_EINVAL;
+  const CMat M = CMat::from_interleaved(n, A);
+  CMat E, H;
+  if (!expm_pade13(M, p->tau, E) || !expm_pade13(M, 0.5 * p->tau, H)) return CGL_EINVAL;
+  std::vector<double> e(2 * n * n), h(2 * n * n);
+  E.to_interleaved(e.data());
+  H.to_interleaved(h.data());
+  return cgl_set_exponentials(p, mu, e.data(), h.data());
+}
+
+int cgl_get_operator(cgl_plan_t p, int mu, int which, double* out_host) {
+  if (!p || !out_host || mu < 0 || mu >= p->d || (which != CGL_E && which != CGL_H))
+    return CGL_EINVAL;
+  if (!p->have_ops[mu]) return CGL_ENOTREADY;
+  (which == CGL_E ? p->E[mu] : p->H[mu]).to_interleaved(out_host);
+  return CGL_OK;
+}
+
+int cgl_split_terms(cgl_plan_t p, int* op_terms, int* state_terms) {
+  if (!p) return CGL_EINVAL;
+  if (op_terms) *op_terms = p->precision == CGL_SPLIT_BF16 ? SP_TERMS : 0;
+  if (state_terms) *state_terms = p->precision == CGL_SPLIT_BF16 ? SP_TERMS : 0;
+  return CGL_OK;
+}
+
+int cgl_mode_product(cgl_plan_t p, int mu, int which, const void* in_dev, void* out_dev) {
+  if (!p || !in_dev || !out_dev || mu < 0 || mu >= p->d || in_dev == out_dev) return CGL_EINVAL;
+  if (which != CGL_E && which != CGL_H) return CGL_EINVAL;
+  if (!p->have_ops[mu]) return CGL_ENOTREADY;
+  return pass(p, mu, which, in_dev, nullptr, out_dev, nullptr, PRO_NONE, EPI_NONE, 1, false, false,
+              p->ustream);
+}
+
+int cgl_tucker(cgl_plan_t p, int which, const void* in_dev, void* out_dev) {
+  if (!p || !in_dev || !out_dev || (which != CGL_E && which != CGL_H)) return CGL_EINVAL;
+  if (!ready(p)) return CGL_ENOTREADY;
+  return action(p, which, in_dev, nullptr, out_dev, nullptr, PRO_NONE, EPI_NONE, 1, false, false,
+                p->ustream);
+}
+
+int cgl_step_strang(cgl_plan_t p, void* u_dev, int64_t nsteps) {
+  int st = check_u(p, u_dev);
+  if (st != CGL_OK) return st;
+  if (nsteps < 0) return CGL_EINVAL;
+  for (int64_t i = 0; i < nsteps && st == CGL_OK; ++i) st = enqueue_strang(p, u_dev, p->ustream);
+  return st;
+}
+
+int cgl_step_lawson4(cgl_plan_t p, void* u_dev, int64_t nsteps) {
+  int st = check_u(p, u_dev);
+  if (st != CGL_OK) return st;
+  if (nsteps < 0) return CGL_EINVAL;
+  for (int64_t i = 0; i < nsteps && st == CGL_OK; ++i) st = enqueue_lawson4(p, u_dev, p->ustream);
+  return st;
+}
+
+int cgl_clear_status(cgl_plan_t p) {
+  if (!p) return CGL_EINVAL;
+  return launch_clear_flag(p->dflag, p->ustream) == hipSuccess ? CGL_OK : CGL_EDEVICE;
+}
+
+static int read_flag(cgl_plan_t p, hipStream_t s, bool clear) {
+  if (hipMemcpyAsync(p->hflag, p->dflag, sizeof(unsigned), hipMemcpyDeviceToHost, s) !=
+      hipSuccess)
+    return CGL_EDEVICE;
+  if (clear && launch_clear_flag(p->dflag, s) != hipSuccess) return CGL_EDEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return CGL_EDEVICE;
+  const unsigned f = *p->hflag;
+  if (f & FLAG_NONFINITE) return CGL_ENONFINITE;
+  if (f & FLAG_BLOWUP) return CGL_EBLOWUP;
+  return CGL_OK;
+}
+
+int cgl_status(cgl_plan_t p) {
+  if (!p) return CGL_EINVAL;
+  return read_flag(p, p->ustream, true);
+}
+
+static int get_graph(cgl_plan_t p, int method, void* u, int64_t k, hipGraphExec_t* out) {
+  const GraphKey key{method, u, k};
+  auto it = p->graphs.find(key);
+  if (it != p->graphs.end()) {
+    *out = it->second;
+    return CGL_OK;
+  }
+  if (hipStreamBeginCapture(p->gstream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return CGL_EDEVICE;
+  int st = CGL_OK;
+  for (int64_t i = 0; i < k && st == CGL_OK; ++i)
+    st = (method == CGL_STRANG) ? enqueue_strang(p, u, p->gstream)
+                                : enqueue_lawson4(p, u, p->gstream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(p->gstream, &g);
+  if (st != CGL_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return st != CGL_OK ? st : CGL_EDEVICE;
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e2 != hipSuccess) return CGL_EDEVICE;
+  p->graphs[key] = ex;
+  *out = ex;
+  return CGL_OK;
+}
+
+int cgl_run(cgl_plan_t p, int method, void* u_dev, int64_t nsteps, int64_t check_every) {
+  int st = check_u(p, u_dev);
+  if (st != CGL_OK) return st;
+  if (nsteps < 0 || (method != CGL_STRANG && method != CGL_LAWSON4)) return CGL_EINVAL;
+  if (nsteps == 0) return CGL_OK;
+  const int64_t k = (check_every <= 0 || check_every > nsteps) ? nsteps : check_every;
+  // join the caller's stream; conditions latched before this run were
+  // reported already (or are the caller's to read with cgl_status first)
+  if (hipEventRecord(p->ev_in, p->ustream) != hipSuccess) return CGL_EDEVICE;
+  if (hipStreamWaitEvent(p->gstream, p->ev_in, 0) != hipSuccess) return CGL_EDEVICE;
+  if (launch_clear_flag(p->dflag, p->gstream) != hipSuccess) return CGL_EDEVICE;
+  int64_t done = 0;
+  while (done < nsteps && st == CGL_OK) {
+    const int64_t chunk = std::min(k, nsteps - done);
+    hipGraphExec_t ex = nullptr;
+    st = get_graph(p, method, u_dev, chunk, &ex);
+    if (st != CGL_OK) break;
+    if (hipGraphLaunch(ex, p->gstream) != hipSuccess) {
+      st = CGL_EDEVICE;
+      break;
+    }
+    done += chunk;
+    if (check_every > 0 || done == nsteps) st = read_flag(p, p->gstream, false);
+  }
+  if (hipEventRecord(p->ev_out, p->gstream) != hipSuccess) return CGL_EDEVICE;
+  if (hipStreamWaitEvent(p->ustream, p->ev_out, 0) != hipSuccess) return CGL_EDEVICE;
+  return st;
+}
+
+void cgl_destroy(cgl_plan_t p) {
+  if (!p) return;
+  if (p->ustream) (void)hipStreamSynchronize(p->ustream);
+  if (p->gstream) (void)hipStreamSynchronize(p->gstream);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (int mu = 0; mu < 3; ++mu) {
+    free_op(p->dE[mu]);
+    free_op(p->dH[mu]);
+  }
+  for (void* s : p->stage)
+    if (s) (void)hipFree(s);
+  if (p->dflag) (void)hipFree(p->dflag);
+  if (p->hflag) (void)hipHostFree(p->hflag);
+  if (p->ev_in) (void)hipEventDestroy(p->ev_in);
+  if (p->ev_out) (void)hipEventDestroy(p->ev_out);
+  if (p->gstream) (void)hipStreamDestroy(p->gstream);
+  delete p;
+}
+
+}  // extern "C"

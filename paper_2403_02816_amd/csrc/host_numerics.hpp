@@ -1,0 +1,43 @@
+// Host-side FP64 numerics of the plan: finite-difference operators, the
+// matrix exponential of the small 1-D operators, bf16 term splitting and the
+// real block embedding of complex operators used by the device kernels.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace cgl {
+
+// Complex n x n matrix, column-major, stored as separate real and imaginary
+// planes (element (i, j) at i + n*j).
+struct CMat {
+  int64_t n = 0;
+  std::vector<double> re, im;
+  CMat() = default;
+  explicit CMat(int64_t n_) : n(n_), re(n_ * n_, 0.0), im(n_ * n_, 0.0) {}
+  static CMat identity(int64_t n);
+  static CMat from_interleaved(int64_t n, const double* z);  // complex128 col-major
+  void to_interleaved(double* z) const;
+  double norm1() const;  // max column sum of |a_ij|
+};
+
+void cmat_mul(const CMat& A, const CMat& B, CMat& C);  // C = A B (C must not alias)
+
+// exp(t A) by the [13/13] Pade approximant with scaling and squaring
+// (Higham, SIAM J. Matrix Anal. Appl. 26 (2005); the Pade route the paper cites
+// for its small exponentials).  Returns false on a singular denominator.
+bool expm_pade13(const CMat& A, double t, CMat& out);
+
+// 2nd-order central FD operator A = (a1 + i b1) D2 + (a2/d) I (see cgl.h).
+CMat fd_operator_2nd(int64_t n, double a, double b, int bc, double a1, double b1, double a2,
+                     int d);
+
+// Round-to-nearest-even float -> bf16 bits and back.
+uint16_t f32_to_bf16_rne(float x);
+float bf16_to_f32(uint16_t h);
+
+// Split a double into k bf16 terms t_0 + t_1 + ... (each term is the bf16
+// rounding of what the previous terms left over).
+void split_bf16(double x, int k, uint16_t* terms);
+
+}  // namespace cgl

@@ -1,0 +1,98 @@
+// Device-side interfaces of the mu-mode product kernels (internal to libcgl).
+//
+// One pass computes out = in x_mu M for one direction mu of a column-major
+// (index 1 fastest) complex tensor.  With R = n_1...n_{mu-1} and n = n_mu,
+// fibre f = (r, b) (r = f mod R, b = f div R) starts at complex offset
+// r + b R n and steps by R; F = N / n fibres.  The complex product is run as
+// the real product of the 2n x 2n block embedding
+//   [[Re M, -Im M], [Im M, Re M]]
+// with real rows/columns interleaved (2m + c, c = 0 real, 1 imaginary), so that
+// a complex number's two parts sit in adjacent rows of the MFMA accumulators.
+//
+// Pointwise work of the time steppers is fused into the first pass (prologue,
+// applied to the input as it is staged) and the last pass (epilogue, applied
+// to the accumulators before the store).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace cgl {
+
+// prologue codes (first pass of an exponential action)
+enum Prologue : int {
+  PRO_NONE = 0,
+  PRO_FLOW = 1,      // x <- phi_{tau/2}(x)                     (Strang)
+  PRO_LAWSON_G = 2,  // tensor 0 <- u, tensor 1 <- g(u)          (Lawson4 round 1)
+};
+
+// epilogue codes (last pass of an exponential action)
+enum Epilogue : int {
+  EPI_NONE = 0,
+  EPI_FLOW = 1,   // y <- phi_{tau/2}(y), check finite           (Strang)
+  EPI_L4_R1 = 2,  // (P, Q) -> (X, Y)                            (Lawson4 round 1)
+  EPI_L4_R2 = 3,  // (H X, H Y) -> u_{n+1} = H Y + tau/6 g(H X)   (Lawson4 round 2)
+};
+
+// latched device conditions
+enum : unsigned { FLAG_NONFINITE = 1u, FLAG_BLOWUP = 2u };
+
+struct NlParams {
+  double tau;  // full step
+  double a3, b3, a4, b4;
+  int exact;  // 1: exact cubic sub-flow, 0: one RK4 step of u' = g(u)
+};
+
+// FP64 pass: complex128 tensors, FP64 operator embedding.
+struct PassF64 {
+  const double* in0;
+  const double* in1;
+  double* out0;
+  double* out1;
+  const double* op;  // embedding, rows k' (Kp of them), p' fastest (Pp per row)
+  int64_t R;
+  int64_t F;
+  int n;
+  int Pp;
+  int Kp;
+  int pro;
+  int epi;
+  NlParams nl;
+  unsigned* flag;
+};
+
+// FP64 kernel tiling (see kernels_f64.hip)
+constexpr int F64_PT = 64;  // real output rows per workgroup
+constexpr int F64_FT = 64;  // fibres per workgroup
+constexpr int F64_KC = 16;  // real contraction rows per LDS stage
+
+hipError_t launch_pass_f64(const PassF64& a, int ntensors, hipStream_t s);
+hipError_t launch_clear_flag(unsigned* flag, hipStream_t s);
+
+// Split-precision pass: complex64 stage tensors (optionally complex128 master
+// state at the pass ends), bf16 operator terms, FP32 accumulation.
+struct PassSplit {
+  const void* in0;
+  const void* in1;
+  void* out0;
+  void* out1;
+  const uint16_t* op;  // bf16 terms of the embedding, see kernels_split.hip
+  int64_t R;
+  int64_t F;
+  int n;
+  int Pp;
+  int Kp;
+  int pro;
+  int epi;
+  int in_f64;   // inputs are complex128 (master state) instead of complex64
+  int out_f64;  // outputs are complex128
+  NlParams nl;
+  unsigned* flag;
+};
+
+constexpr int SP_FT = 64;    // fibres per workgroup (rows/stage sizes: split_layout.hpp)
+constexpr int SP_TERMS = 3;  // bf16 terms per operand
+
+hipError_t launch_pass_split(const PassSplit& a, int ntensors, hipStream_t s);
+
+}  // namespace cgl

@@ -1,0 +1,29 @@
+// Device layout of the bf16 term planes of one complex exponential M (n x n)
+// for the split-precision mu-mode kernel.
+//
+// The complex product y = M x is evaluated as four real products
+//   Re y = Re M Re x - Im M Im x,   Im y = Im M Re x + Re M Im x,
+// each operand given as a sum of three bf16 terms.  Layout, in bf16 units:
+//   [p-tile pt < Pp/SPK_P][k-stage ks < Kp/SPK_K][plane q < 6][row < SPK_P][k < SPK_K]
+// with planes q = 0,1,2: terms of Re M; q = 3,4,5: terms of Im M, row = output
+// index m (within the p-tile), k = contraction index j (within the stage);
+// entries beyond n are zero.  One (pt, ks) block is contiguous, so a
+// workgroup copies one stage of its p-tile with plain 16-byte loads.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "host_numerics.hpp"
+
+namespace cgl {
+
+constexpr int SPK_P = 64;  // complex output rows per p-tile
+constexpr int SPK_K = 16;  // complex contraction indices per stage
+constexpr int SPK_Q = 6;   // planes per stage block
+
+// Builds the planes of M (3 bf16 terms of Re and Im of every entry); Pp, Kp
+// receive the padded row / contraction counts.
+void build_split_operator(const CMat& M, std::vector<uint16_t>& out, int& Pp, int& Kp);
+
+}  // namespace cgl

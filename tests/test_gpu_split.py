@@ -1,0 +1,132 @@
+"""GPU parity of the split-precision form (bf16x3 terms, FP32 accumulation)
+against the FP64 oracle.
+
+Kernel level (relative 2-norm): one mu-mode product / Tucker operator on the
+complex64 input, compared with the FP64 product of the same input; the
+error budget is the FP32 rounding of the result (~6e-8) plus the dropped
+term products (~1e-7), so the bound is 1e-6.
+Step level: one Strang / Lawson4 step from an identical input must stay
+within 1e-6 of the FP64 oracle step (the split form's accuracy target);
+trajectory errors over many steps are reported, not gated.
+"""
+import numpy as np
+import pytest
+
+import cgl_inputs as ci
+from oracle import tensor
+from tests._util import log, make_plan, oracle_run, plan_ops, rel_l2, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(150,), (64, 45), (130, 70), (20, 33, 17), (64, 64, 40), (3, 5, 4), (128, 33, 9)]
+
+
+def _c64(u):
+    return u.astype(np.complex64).astype(np.complex128)
+
+
+def _random_plan(shape, seed, master=False):
+    from paper_2403_02816_amd import cgl
+    p = cgl.Plan(shape, ci.C0.coeffs, 0.01, precision="split", master=master)
+    Es, Hs = [], []
+    for mu, n in enumerate(shape):
+        E = ci.random_complex((n, n), seed + 10 * mu) / np.sqrt(n)
+        H = ci.random_complex((n, n), seed + 10 * mu + 1) / np.sqrt(n)
+        p.set_exponentials(mu, E, H)
+        Es.append(E)
+        Hs.append(H)
+    return p, Es, Hs
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_split_mode_product_every_mu(shape):
+    torch = require_gpu()
+    p, Es, Hs = _random_plan(shape, 300)
+    U = _c64(ci.random_complex(shape, 17))
+    x = p.to_device(U, dtype=torch.complex64)
+    out = torch.empty_like(x)
+    for mu in range(len(shape)):
+        for which, Ms in ((0, Es), (1, Hs)):
+            log(f"split mode_product shape={shape} mu={mu} which={which}")
+            p.mode_product(mu, which, x, out)
+            torch.cuda.synchronize()
+            err = rel_l2(p.to_host(out), tensor.mode_product(U, Ms[mu], mu))
+            assert err < 1e-6, (shape, mu, which, err)
+    p.destroy()
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_split_tucker(shape):
+    torch = require_gpu()
+    p, Es, Hs = _random_plan(shape, 400)
+    U = _c64(ci.random_complex(shape, 18))
+    x = p.to_device(U, dtype=torch.complex64)
+    out = torch.empty_like(x)
+    p.tucker(1, x, out)
+    torch.cuda.synchronize()
+    err = rel_l2(p.to_host(out), tensor.tucker(U, Hs))
+    log(f"split tucker {shape} {err:.2e}")
+    assert err < 1e-6
+
+
+def _one_step_gate(p, method, master=False, rk4_flow=False, steps=1):
+    torch = require_gpu()
+    plan = make_plan(p, "split", master=master, rk4_flow=rk4_flow)
+    u0 = ci.initial_state(p)
+    if not master:
+        u0 = _c64(u0)
+    u = plan.to_device(u0)
+    if method == "strang":
+        plan.step_strang(u, steps)
+    else:
+        plan.step_lawson4(u, steps)
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    E, H = plan_ops(plan)
+    ref = oracle_run(p, u0, method, steps, E, H, rk4_flow=rk4_flow)
+    err = rel_l2(plan.to_host(u), ref)
+    log(f"split {p.name} {method} master={master} steps={steps} rel-L2 {err:.3e}")
+    plan.destroy()
+    return err
+
+
+@pytest.mark.parametrize("method", ["strang", "lawson4"])
+def test_split_one_step_gate_c0(method):
+    assert _one_step_gate(ci.C0, method) < 1e-6
+
+
+@pytest.mark.parametrize("method", ["strang", "lawson4"])
+@pytest.mark.parametrize("master", [False, True])
+def test_split_one_step_gate_c1_shape(method, master):
+    assert _one_step_gate(ci.scaled(ci.C1, (40, 36, 44)), method, master=master) < 1e-6
+
+
+@pytest.mark.parametrize("method", ["strang", "lawson4"])
+def test_split_one_step_gate_c2_shape(method):
+    assert _one_step_gate(ci.scaled(ci.C2, (48, 40, 52)), method) < 1e-6
+
+
+def test_split_one_step_gate_c1_full_size():
+    assert _one_step_gate(ci.C1, "lawson4") < 1e-6
+
+
+def test_split_trajectory_error_is_reported():
+    p = ci.scaled(ci.C1, (32, 32, 32))
+    err = _one_step_gate(p, "lawson4", steps=40)
+    errm = _one_step_gate(p, "lawson4", master=True, steps=40)
+    log(f"split 32^3 Lawson4 40 steps: c64 state {err:.3e}, FP64 master {errm:.3e}")
+    assert err < 1e-3 and errm < 1e-3
+
+
+def test_split_graph_replay_equals_eager_bitwise():
+    torch = require_gpu()
+    p = ci.scaled(ci.C1, (20, 18, 22))
+    plan = make_plan(p, "split")
+    u0 = ci.initial_state(p)
+    a = plan.to_device(u0)
+    b = plan.to_device(u0)
+    plan.step_lawson4(a, 12)
+    assert plan.run("lawson4", b, 12, 5) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    plan.destroy()

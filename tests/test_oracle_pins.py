@@ -63,7 +63,7 @@ def test_exp_closed_form_vs_scipy_expm(bc, n, t):
     A = ops.operator_A(n, -10.0, 10.0, bc, COEF3, 3)
     E1 = ops.exp_closed_form(n, -10.0, 10.0, bc, COEF3, 3, t)
     E2 = ops.exp_scipy(A, t)
-    assert np.linalg.norm(E1 - E2) / np.linalg.norm(E2) < 5e-14
+    assert np.linalg.norm(E1 - E2) / np.linalg.norm(E2) < 5e-15
 
 
 # ---------------------------------------------------------------- tensors
