@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the CGL exponential stepper on one MI355X.
+
+Workload (default): 3-D cubic-quintic CGL on a 128^3 Neumann vertex grid on
+(-15,15)^3, 2nd-order FD, Lawson4 with tau = 5e-3, seeded Gaussian vortex
+ring u0.  One step = one Lawson4 step of the whole grid (four actions of
+e^{tau K/2} in two rounds of three mu-mode passes over a tensor pair, with the
+nonlinear stages fused into the pass epilogues/prologues).
+
+The timed form is the split-precision form (complex64 stage tensors,
+bf16x3 operands, FP32 accumulation); the FP64 form is timed beside it.
+Inputs are resident in HBM before the timed region; the steps are replayed
+from a captured HIP graph (cgl_run).  Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MI355X_PEAK_BF16_TFLOPS = 2500.0  # dense MFMA
+MI355X_PEAK_FP64_TFLOPS = 78.6
+MI355X_PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2_strang", "c2_lawson4"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    return ap.parse_args()
+
+
+def workload(name):
+    import cgl_inputs as ci
+    if name == "c1":
+        return ci.C1, "lawson4"
+    if name == "c2_strang":
+        return ci.C2, "strang"
+    return ci.C2, "lawson4"
+
+
+def launches_per_step(method, d):
+    return d if method == "strang" else 2 * d
+
+
+def tensors_per_launch(method):
+    return 1 if method == "strang" else 2
+
+
+def time_form(p, method, precision, steps, warmup, u0):
+    import torch
+    from paper_2403_02816_amd import cgl
+    plan = cgl.Plan(p.n, p.coeffs, p.tau, precision=precision)
+    plan.set_fd_operators(p.a, p.b, p.bc, p.coeffs)
+    u = plan.to_device(u0)
+    # warm-up: also captures the graph of `steps` steps used below
+    if warmup > 0:
+        st = plan.run(method, u, warmup, warmup)
+        assert st == 0, st
+    st = plan.run(method, u, steps, steps)  # graph capture of the timed chunk size
+    assert st == 0, st
+    u.copy_(plan.to_device(u0))
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()  # events on the plan's stream: the default stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(torch.cuda.current_stream())
+    t0 = time.perf_counter()
+    st = plan.run(method, u, steps, steps)
+    ev1.record(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assert st == 0, st
+    ms = ev0.elapsed_time(ev1)
+    del s
+    return plan, u, ms, wall
+
+
+def one_step_gate(p, method, plan):
+    """Relative 2-norm of one split step vs the FP64 oracle step (same input)."""
+    import torch
+    import cgl_inputs as ci
+    from oracle import metrics, steppers
+    u0 = ci.initial_state(p).astype(np.complex64).astype(np.complex128)
+    u = plan.to_device(u0)
+    (plan.step_strang if method == "strang" else plan.step_lawson4)(u, 1)
+    torch.cuda.synchronize()
+    E = [plan.get_operator(mu, 0) for mu in range(p.d)]
+    H = [plan.get_operator(mu, 1) for mu in range(p.d)]
+    if method == "lawson4":
+        E = [h @ h for h in H]
+    nl = steppers.CGLNonlinearity(p.coeffs.as_tuple())
+    ref = steppers.make_step(method, E, H, p.tau, nl)(u0)
+    return metrics.rel_l2(plan.to_host(u), ref)
+
+
+def cpu_baseline(p, method, nsteps):
+    """The FP64 oracle (as written: six exponential actions per Lawson4 step)
+    timed on the host cores on a bounded sample of steps."""
+    import cgl_inputs as ci
+    from oracle import steppers
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    E = steppers.operators_for(p, p.tau)
+    H = steppers.operators_for(p, 0.5 * p.tau)
+    nl = steppers.CGLNonlinearity(p.coeffs.as_tuple())
+    step = steppers.make_step(method, E, H, p.tau, nl)
+    u = ci.initial_state(p)
+    u = step(u)  # warm-up step
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        u = step(u)
+    dt = time.perf_counter() - t0
+    return {"value": p.N * nsteps / dt, "unit": "grid-point-steps/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": f"{nsteps} {method} steps of the full {'x'.join(map(str, p.n))} grid "
+                      f"(numpy FP64, literal scheme), after 1 warm-up step; {dt:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import cgl_inputs as ci
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    p, method = workload(args.workload)
+    u0 = ci.initial_state(p)
+    K, W = args.steps, args.warmup
+
+    plan, u, ms, wall = time_form(p, method, "split", K, W, u0)
+    ms_step = ms / K
+    value = p.N * K / (ms * 1e-3)
+    nl = launches_per_step(method, p.d)
+    nt = tensors_per_launch(method)
+    launch_ms = ms / (K * nl)
+    # algorithmic work of one launch: every grid point of nt tensors gets one
+    # complex mu-mode product of length n (8 n real flops); the split form
+    # issues 6 bf16 term products for each, so its MFMA work is 6x that
+    n_mu = p.n[0]
+    alg_flops = 8.0 * p.N * n_mu * nt
+    mfma_flops = 6.0 * alg_flops
+    alg_bytes = nt * p.N * (8 + 8)
+    achieved_tf = mfma_flops / (launch_ms * 1e-3) / 1e12
+    gate = one_step_gate(p, method, plan)
+    split_state = u.clone()
+    plan.destroy()
+
+    fp64 = None
+    traj = None
+    if not args.no_fp64:
+        plan64, u64, ms64, _ = time_form(p, method, "fp64", K, W, u0)
+        traj = float(torch.linalg.vector_norm(split_state.to(torch.complex128) - u64).item()
+                     / torch.linalg.vector_norm(u64).item())
+        fp64 = {"value": p.N * K / (ms64 * 1e-3), "ms_per_step": ms64 / K,
+                "mfma_tflops": alg_flops / ((ms64 / (K * nl)) * 1e-3) / 1e12,
+                "peak_tflops": MI355X_PEAK_FP64_TFLOPS}
+        fp64["frac"] = fp64["mfma_tflops"] / MI355X_PEAK_FP64_TFLOPS
+        plan64.destroy()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(p, method, args.cpu_sample_steps)
+
+    rec = {
+        "metric": "grid-point-steps/s at rel-L2 <=1e-6 vs FP64 oracle; MFMA util % of peak",
+        "value": value,
+        "unit": "grid-point-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3->f32 (split), state c64",
+        "data": "synthetic",
+        "config": {"workload": f"{p.name}: 3-D cubic-quintic CGL {'x'.join(map(str, p.n))} "
+                               f"{'Neumann' if p.bc else 'Dirichlet'}, {method}, tau={p.tau}, "
+                               f"split-precision form",
+                   "grid": list(p.n), "method": method, "tau": p.tau, "parallelism": "single-gpu"},
+        "roofline": {"bound": "mfma", "achieved": achieved_tf, "peak": MI355X_PEAK_BF16_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved_tf / MI355X_PEAK_BF16_TFLOPS,
+                     "traffic": None,
+                     "kernel": "k_pass_split (all mu-mode passes of a step)",
+                     "launch_ms": launch_ms,
+                     "hbm_gbs": alg_bytes / (launch_ms * 1e-3) / 1e9},
+        "accuracy": {"one_step_rel_l2_vs_fp64_oracle": gate, "gate": 1e-6,
+                     "trajectory_rel_l2_vs_fp64_form": traj, "trajectory_steps": K + W},
+        "fp64_form": fp64,
+        "cpu_baseline": cpu,
+        "wall_s_timed_region": wall,
+    }
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

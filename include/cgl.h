@@ -135,8 +135,11 @@ int cgl_step_strang(cgl_plan_t p, void* u_dev, int64_t nsteps);
 
 /* Advance u_dev in place by nsteps Lawson4 steps (eq. lawson4).  The six
  * exponential actions of the scheme are evaluated as four actions of
- * exp(tau K/2) in two rounds over tensor pairs, using
- * exp(tau K) = exp(tau K/2) exp(tau K/2).  Same errors as cgl_step_strang. */
+ * exp(tau K/2), using exp(tau K) = exp(tau K/2) exp(tau K/2):
+ * P = e^{tau K/2} u and Q = e^{tau K/2} g(u), from which the stages
+ * X = P + tau g(u3), Y = P + tau/6 Q + tau/3 (g(u2) + g(u3)) are formed in
+ * the last pass; then u4 = e^{tau K/2} X and
+ * u_{n+1} = e^{tau K/2} Y + tau/6 g(u4).  Same errors as cgl_step_strang. */
 int cgl_step_lawson4(cgl_plan_t p, void* u_dev, int64_t nsteps);
 
 /* Advance u_dev by nsteps steps of method (CGL_STRANG / CGL_LAWSON4),

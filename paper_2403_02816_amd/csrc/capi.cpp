@@ -53,7 +53,7 @@ struct cgl_plan_s {
   bool have_ops[3] = {false, false, false};
   CMat E[3], H[3];
   DeviceOp dE[3], dH[3];
-  void* stage[4] = {nullptr, nullptr, nullptr, nullptr};
+  void* stage[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   unsigned* dflag = nullptr;
   unsigned* hflag = nullptr;  // pinned
   std::map<GraphKey, hipGraphExec_t> graphs;
@@ -93,15 +93,22 @@ int upload_op(cgl_plan_s* p, const CMat& M, DeviceOp& dst) {
     const int Pp = static_cast<int>(round_up(2 * n, F64_PT));
     const int Kp = static_cast<int>(round_up(2 * n, F64_KC));
     std::vector<double> h(static_cast<size_t>(Pp) * Kp, 0.0);
-    // embedding rows p' = 2m + c', columns k' = 2k + c of [[Re, -Im], [Im, Re]],
-    // stored with k' as the row index and p' fastest
+    // embedding [[Re, -Im], [Im, Re]] with columns k' = 2k + c and rows
+    // permuted within 16-row blocks so that the FP64 MFMA accumulator of one
+    // lane (rows g, g+4, g+8, g+12 of a block) holds (re, im) of two complex
+    // outputs: block b, lane group g, register r <-> m = 8b + g + 4(r/2),
+    // part r%2.  Stored with k' as the row index and p' fastest.
+    auto prow = [](int64_t m, int c) {
+      const int64_t ml = m % 8;
+      return 16 * (m / 8) + (ml % 4) + 4 * (2 * (ml / 4) + c);
+    };
     for (int64_t k = 0; k < n; ++k)
       for (int64_t m = 0; m < n; ++m) {
         const double re = M.re[m + n * k], im = M.im[m + n * k];
-        h[(2 * k) * Pp + 2 * m] = re;
-        h[(2 * k) * Pp + 2 * m + 1] = im;
-        h[(2 * k + 1) * Pp + 2 * m] = -im;
-        h[(2 * k + 1) * Pp + 2 * m + 1] = re;
+        h[(2 * k) * Pp + prow(m, 0)] = re;
+        h[(2 * k) * Pp + prow(m, 1)] = im;
+        h[(2 * k + 1) * Pp + prow(m, 0)] = -im;
+        h[(2 * k + 1) * Pp + prow(m, 1)] = re;
       }
     if (hipMalloc(&dst.ptr, h.size() * sizeof(double)) != hipSuccess) return CGL_ENOMEM;
     if (hipMemcpyAsync(dst.ptr, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice,
@@ -125,9 +132,10 @@ int upload_op(cgl_plan_s* p, const CMat& M, DeviceOp& dst) {
   return CGL_OK;
 }
 
-// One mu-mode pass over one or two tensors.
-int pass(cgl_plan_s* p, int mu, int which, const void* in0, const void* in1, void* out0,
-         void* out1, int pro, int epi, int nt, bool in_f64, bool out_f64, hipStream_t s) {
+// One mu-mode pass: out0 (, out1) = epilogue(in0 x_mu M, aux), with the
+// prologue applied to in0 as it is staged.
+int pass(cgl_plan_s* p, int mu, int which, const void* in0, const void* aux, void* out0,
+         void* out1, int pro, int epi, bool in_f64, bool out_f64, hipStream_t s) {
   const DeviceOp& op = (which == CGL_E) ? p->dE[mu] : p->dH[mu];
   int64_t R = 1;
   for (int nu = 0; nu < mu; ++nu) R *= p->n[nu];
@@ -136,7 +144,7 @@ int pass(cgl_plan_s* p, int mu, int which, const void* in0, const void* in1, voi
   if (p->precision == CGL_FP64) {
     PassF64 a{};
     a.in0 = static_cast<const double*>(in0);
-    a.in1 = static_cast<const double*>(in1);
+    a.aux = static_cast<const double*>(aux);
     a.out0 = static_cast<double*>(out0);
     a.out1 = static_cast<double*>(out1);
     a.op = static_cast<const double*>(op.ptr);
@@ -149,11 +157,11 @@ int pass(cgl_plan_s* p, int mu, int which, const void* in0, const void* in1, voi
     a.epi = epi;
     a.nl = p->nl;
     a.flag = p->dflag;
-    e = launch_pass_f64(a, nt, s);
+    e = launch_pass_f64(a, s);
   } else {
     PassSplit a{};
     a.in0 = in0;
-    a.in1 = in1;
+    a.aux = aux;
     a.out0 = out0;
     a.out1 = out1;
     a.op = static_cast<const uint16_t*>(op.ptr);
@@ -168,69 +176,59 @@ int pass(cgl_plan_s* p, int mu, int which, const void* in0, const void* in1, voi
     a.out_f64 = out_f64 ? 1 : 0;
     a.nl = p->nl;
     a.flag = p->dflag;
-    e = launch_pass_split(a, nt, s);
+    e = launch_pass_split(a, s);
   }
   return e == hipSuccess ? CGL_OK : CGL_EDEVICE;
 }
 
-// d passes of one exponential action over one or two tensors.  Stage pairs
-// (stage[0], stage[1]) and (stage[2], stage[3]) alternate; a pass never reads
-// and writes the same buffer.  out0/out1 receive the last pass's result.
-int action(cgl_plan_s* p, int which, const void* in0, const void* in1, void* out0, void* out1,
-           int pro, int epi, int nt, bool in_f64, bool out_f64, hipStream_t s) {
-  void* pairs[2][2] = {{p->stage[0], p->stage[1]}, {p->stage[2], p->stage[3]}};
-  const int first = (in0 == pairs[0][0]) ? 1 : 0;
-  const void* c0 = in0;
-  const void* c1 = in1;
+// d passes of one exponential action.  Intermediate results alternate between
+// the ping-pong buffers stage[0] / stage[1]; the last pass applies the
+// epilogue and writes out0 (and out1).  A pass never reads and writes the same
+// buffer: with d = 1 and out0 == in0 the result goes through stage[0].
+int action(cgl_plan_s* p, int which, const void* in0, const void* aux, void* out0, void* out1,
+           int pro, int epi, bool in_f64, bool out_f64, hipStream_t s) {
+  const void* cur = in0;
   bool cf64 = in_f64;
   for (int mu = 0; mu < p->d; ++mu) {
     const bool last = (mu == p->d - 1);
-    void* d0 = last ? out0 : pairs[(first + mu) & 1][0];
-    void* d1 = last ? out1 : pairs[(first + mu) & 1][1];
-    bool tmp_copy = false;
-    if (last && (d0 == c0 || (nt == 2 && d1 == c1))) {
-      // the destination is the source (d = 1 in place): go through a stage buffer
-      d0 = pairs[(first + mu) & 1][0];
-      d1 = pairs[(first + mu) & 1][1];
-      tmp_copy = true;
-    }
+    void* dst = last ? out0 : p->stage[mu & 1];
+    const bool via_tmp = last && dst == cur;
+    if (via_tmp) dst = p->stage[0];
     const bool of64 = last ? out_f64 : false;
-    int st = pass(p, mu, which, c0, c1, d0, d1, mu == 0 ? pro : PRO_NONE, last ? epi : EPI_NONE,
-                  nt, cf64, of64, s);
+    int st = pass(p, mu, which, cur, aux, dst, out1, mu == 0 ? pro : PRO_NONE,
+                  last ? epi : EPI_NONE, cf64, of64, s);
     if (st != CGL_OK) return st;
-    if (tmp_copy) {
+    if (via_tmp) {
       // stage buffers are sized for the caller's element type (see cgl_plan)
       const size_t bytes = of64 ? static_cast<size_t>(p->N) * 16 : stage_bytes(p);
-      if (hipMemcpyAsync(out0, d0, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return CGL_EDEVICE;
-      if (nt == 2 && epi != EPI_L4_R2 &&
-          hipMemcpyAsync(out1, d1, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      if (hipMemcpyAsync(out0, dst, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return CGL_EDEVICE;
     }
-    c0 = d0;
-    c1 = d1;
+    cur = dst;
     cf64 = of64;
   }
   return CGL_OK;
 }
 
 int enqueue_strang(cgl_plan_s* p, void* u, hipStream_t s) {
-  const bool m = master(p) || p->precision == CGL_FP64;
-  return action(p, CGL_E, u, nullptr, u, nullptr, PRO_FLOW, EPI_FLOW, 1,
-                p->precision == CGL_FP64 ? false : m, p->precision == CGL_FP64 ? false : m, s);
+  const bool m = master(p);
+  return action(p, CGL_E, u, nullptr, u, nullptr, PRO_FLOW, EPI_FLOW, m, m, s);
 }
 
+// Lawson4 (eq. lawson4) with e^{tau K} = e^{tau K/2} e^{tau K/2}: four
+// actions of e^{tau K/2},
+//   P = H u,  Q = H g(u) -> (X, Y) in the epilogue,  H X,  H Y -> u_{n+1},
+// where the stage combinations run in the last-pass epilogues.
 int enqueue_lawson4(cgl_plan_s* p, void* u, hipStream_t s) {
-  const bool m = p->precision == CGL_SPLIT_BF16 && master(p);
-  // round 1: (u, g(u)) -> (P, Q) -> (X, Y) in the stage pair the alternation ends on
-  const int d = p->d;
-  void* pairs[2][2] = {{p->stage[0], p->stage[1]}, {p->stage[2], p->stage[3]}};
-  void* x = pairs[(d - 1) & 1][0];
-  void* y = pairs[(d - 1) & 1][1];
-  int st = action(p, CGL_H, u, nullptr, x, y, PRO_LAWSON_G, EPI_L4_R1, 2, m, false, s);
-  if (st != CGL_OK) return st;
-  // round 2: (X, Y) -> (H X, H Y) -> u_{n+1}
-  return action(p, CGL_H, x, y, u, nullptr, PRO_NONE, EPI_L4_R2, 2, false, m, s);
+  const bool m = master(p);
+  void* B0 = p->stage[2];
+  void* B1 = p->stage[3];
+  void* B2 = p->stage[4];
+  int st = action(p, CGL_H, u, nullptr, B0, nullptr, PRO_NONE, EPI_NONE, m, false, s);
+  if (st == CGL_OK) st = action(p, CGL_H, u, B0, B1, B2, PRO_G, EPI_L4_R1, m, false, s);
+  if (st == CGL_OK) st = action(p, CGL_H, B1, nullptr, B0, nullptr, PRO_NONE, EPI_NONE, false, false, s);
+  if (st == CGL_OK) st = action(p, CGL_H, B2, B0, u, nullptr, PRO_NONE, EPI_L4_R2, false, m, s);
+  return st;
 }
 
 int check_u(cgl_plan_s* p, void* u) {
@@ -315,7 +313,7 @@ int cgl_plan(cgl_plan_t* out, int d, const int64_t* n, const cgl_coeffs* c, doub
       hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&p->ev_out, hipEventDisableTiming) != hipSuccess)
     st = CGL_EDEVICE;
-  for (int i = 0; i < 4 && st == CGL_OK; ++i)
+  for (int i = 0; i < 5 && st == CGL_OK; ++i)
     if (hipMalloc(&p->stage[i], std::max(stage_bytes(p), user_bytes(p))) != hipSuccess)
       st = CGL_ENOMEM;
   if (st == CGL_OK && hipMalloc(reinterpret_cast<void**>(&p->dflag), 256) != hipSuccess)
@@ -382,14 +380,14 @@ int cgl_mode_product(cgl_plan_t p, int mu, int which, const void* in_dev, void* 
   if (!p || !in_dev || !out_dev || mu < 0 || mu >= p->d || in_dev == out_dev) return CGL_EINVAL;
   if (which != CGL_E && which != CGL_H) return CGL_EINVAL;
   if (!p->have_ops[mu]) return CGL_ENOTREADY;
-  return pass(p, mu, which, in_dev, nullptr, out_dev, nullptr, PRO_NONE, EPI_NONE, 1, false, false,
+  return pass(p, mu, which, in_dev, nullptr, out_dev, nullptr, PRO_NONE, EPI_NONE, false, false,
               p->ustream);
 }
 
 int cgl_tucker(cgl_plan_t p, int which, const void* in_dev, void* out_dev) {
   if (!p || !in_dev || !out_dev || (which != CGL_E && which != CGL_H)) return CGL_EINVAL;
   if (!ready(p)) return CGL_ENOTREADY;
-  return action(p, which, in_dev, nullptr, out_dev, nullptr, PRO_NONE, EPI_NONE, 1, false, false,
+  return action(p, which, in_dev, nullptr, out_dev, nullptr, PRO_NONE, EPI_NONE, false, false,
                 p->ustream);
 }
 

@@ -22,16 +22,17 @@ namespace cgl {
 // prologue codes (first pass of an exponential action)
 enum Prologue : int {
   PRO_NONE = 0,
-  PRO_FLOW = 1,      // x <- phi_{tau/2}(x)                     (Strang)
-  PRO_LAWSON_G = 2,  // tensor 0 <- u, tensor 1 <- g(u)          (Lawson4 round 1)
+  PRO_FLOW = 1,  // x <- phi_{tau/2}(x)                          (Strang)
+  PRO_G = 2,     // x <- g(x)                                    (Lawson4: Q = e^{tau K/2} g(u))
 };
 
-// epilogue codes (last pass of an exponential action)
+// epilogue codes (last pass of an exponential action); "aux" is a second
+// tensor read at the same grid point
 enum Epilogue : int {
   EPI_NONE = 0,
-  EPI_FLOW = 1,   // y <- phi_{tau/2}(y), check finite           (Strang)
-  EPI_L4_R1 = 2,  // (P, Q) -> (X, Y)                            (Lawson4 round 1)
-  EPI_L4_R2 = 3,  // (H X, H Y) -> u_{n+1} = H Y + tau/6 g(H X)   (Lawson4 round 2)
+  EPI_FLOW = 1,   // y <- phi_{tau/2}(y), check finite            (Strang)
+  EPI_L4_R1 = 2,  // acc = Q, aux = P:  out0 <- X, out1 <- Y        (Lawson4 round 1)
+  EPI_L4_R2 = 3,  // acc = H Y, aux = H X:  out0 <- H Y + tau/6 g(H X), check finite
 };
 
 // latched device conditions
@@ -46,7 +47,7 @@ struct NlParams {
 // FP64 pass: complex128 tensors, FP64 operator embedding.
 struct PassF64 {
   const double* in0;
-  const double* in1;
+  const double* aux;
   double* out0;
   double* out1;
   const double* op;  // embedding, rows k' (Kp of them), p' fastest (Pp per row)
@@ -66,14 +67,14 @@ constexpr int F64_PT = 64;  // real output rows per workgroup
 constexpr int F64_FT = 64;  // fibres per workgroup
 constexpr int F64_KC = 16;  // real contraction rows per LDS stage
 
-hipError_t launch_pass_f64(const PassF64& a, int ntensors, hipStream_t s);
+hipError_t launch_pass_f64(const PassF64& a, hipStream_t s);
 hipError_t launch_clear_flag(unsigned* flag, hipStream_t s);
 
 // Split-precision pass: complex64 stage tensors (optionally complex128 master
 // state at the pass ends), bf16 operator terms, FP32 accumulation.
 struct PassSplit {
   const void* in0;
-  const void* in1;
+  const void* aux;  // complex64 stage tensor
   void* out0;
   void* out1;
   const uint16_t* op;  // bf16 terms of the embedding, see kernels_split.hip
@@ -84,8 +85,8 @@ struct PassSplit {
   int Kp;
   int pro;
   int epi;
-  int in_f64;   // inputs are complex128 (master state) instead of complex64
-  int out_f64;  // outputs are complex128
+  int in_f64;   // in0 is complex128 (master state) instead of complex64
+  int out_f64;  // out0/out1 are complex128
   NlParams nl;
   unsigned* flag;
 };
@@ -93,6 +94,6 @@ struct PassSplit {
 constexpr int SP_FT = 64;    // fibres per workgroup (rows/stage sizes: split_layout.hpp)
 constexpr int SP_TERMS = 3;  // bf16 terms per operand
 
-hipError_t launch_pass_split(const PassSplit& a, int ntensors, hipStream_t s);
+hipError_t launch_pass_split(const PassSplit& a, hipStream_t s);
 
 }  // namespace cgl

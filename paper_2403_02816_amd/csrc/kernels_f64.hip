@@ -1,15 +1,15 @@
 // FP64 mu-mode product on CDNA4 FP64 MFMA (v_mfma_f64_16x16x4_f64).
 //
 // One workgroup (4 waves) computes a 64 (real rows of the 2n x 2n embedding,
-// i.e. 32 complex outputs) x 64 (fibres) tile of  out = M_emb * in_emb  for
-// one or two tensors that share the operator (the Lawson4 rounds apply the
-// same e^{tau K/2} to a pair of tensors).  The contraction runs in stages of
-// 16 real rows (8 complex) staged in LDS:
+// i.e. 32 complex outputs) x 64 (fibres) tile of  out = M_emb * in_emb.  The
+// contraction runs in stages of 16 real rows (8 complex) staged in LDS:
 //   - operator stage: 16 x 64 doubles of the embedding (rows k', p' fastest),
 //   - input stage: 8 complex elements of 64 fibres, loaded with 16-byte
 //     loads that are coalesced along the contiguous direction (along the
 //     fibre when mu = 1, across fibres when mu > 1), split into re/im rows.
-// Each wave owns a 32 x 32 sub-tile = 2 x 2 MFMA blocks per tensor.
+// Each wave owns a 32 x 32 sub-tile = 2 x 2 MFMA blocks.  The accumulator of
+// lane l holds rows l/16 + 4r (r < 4) of a 16-row block; the host orders the
+// embedding's rows so that these are two whole complex numbers.
 // Workgroups are remapped so that the P-tiles sharing one input tile run on
 // the same XCD (its L2 keeps the input tile for all of them).
 #include "kernels.hpp"
@@ -35,10 +35,10 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned h, unsigned G) {
   return ((G & 7u) == 0u) ? (h & 7u) * (G >> 3) + (h >> 3) : h;
 }
 
-template <int NT, bool CONTIG>
+template <bool CONTIG>
 __global__ __launch_bounds__(256) void k_pass_f64(PassF64 a) {
   __shared__ double sOp[KC][LDP];
-  __shared__ double sIn[NT][KC][LDF];
+  __shared__ double sIn[KC][LDF];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void k_pass_f64(PassF64 a) {
   const int64_t f0 = static_cast<int64_t>(w / nP) * FT;
   const int p0 = pt * PT;
 
-  // staging assignment: two complex elements per tensor per stage
+  // staging assignment: two complex elements per stage
   int fl[2], kl[2];
   int64_t gbase[2];
 #pragma unroll
@@ -68,13 +68,11 @@ __global__ __launch_bounds__(256) void k_pass_f64(PassF64 a) {
     gbase[j] = (f < a.F) ? fibre_base(f, a.R, a.n) : -1;
   }
 
-  f64x4 acc[NT][2][2];
+  f64x4 acc[2][2];
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) acc[t][i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
   unsigned flag = 0;
 
   for (int k0 = 0; k0 < a.Kp; k0 += KC) {
@@ -92,84 +90,74 @@ __global__ __launch_bounds__(256) void k_pass_f64(PassF64 a) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int k = kc0 + kl[j];
-      cd x0 = {0.0, 0.0}, x1 = {0.0, 0.0};
+      cd x = {0.0, 0.0};
       if (gbase[j] >= 0 && k < a.n) {
         const int64_t off = gbase[j] + a.R * (int64_t)k;
         const double2 v = *reinterpret_cast<const double2*>(a.in0 + 2 * off);
-        x0 = {v.x, v.y};
-        if (a.pro == PRO_FLOW) x0 = half_flow(x0, a.nl, flag);
-        if (NT == 2) {
-          if (a.pro == PRO_LAWSON_G) {
-            x1 = g_cgl(x0, a.nl);
-          } else {
-            const double2 u = *reinterpret_cast<const double2*>(a.in1 + 2 * off);
-            x1 = {u.x, u.y};
-          }
+        x = {v.x, v.y};
+        if (a.pro == PRO_FLOW) {
+          x = half_flow(x, a.nl, flag);
+        } else if (a.pro == PRO_G) {
+          x = g_cgl(x, a.nl);
         }
       }
-      sIn[0][2 * kl[j]][fl[j]] = x0.re;
-      sIn[0][2 * kl[j] + 1][fl[j]] = x0.im;
-      if (NT == 2) {
-        sIn[NT - 1][2 * kl[j]][fl[j]] = x1.re;
-        sIn[NT - 1][2 * kl[j] + 1][fl[j]] = x1.im;
-      }
+      sIn[2 * kl[j]][fl[j]] = x.re;
+      sIn[2 * kl[j] + 1][fl[j]] = x.im;
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       const int kr = kk + (lane >> 4);
-      double av[2], bv[NT][2];
+      double av[2], bv[2];
 #pragma unroll
       for (int pb = 0; pb < 2; ++pb) av[pb] = sOp[kr][wp * 32 + pb * 16 + (lane & 15)];
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
+      for (int fb = 0; fb < 2; ++fb) bv[fb] = sIn[kr][wf * 32 + fb * 16 + (lane & 15)];
 #pragma unroll
-        for (int fb = 0; fb < 2; ++fb) bv[t][fb] = sIn[t][kr][wf * 32 + fb * 16 + (lane & 15)];
+      for (int pb = 0; pb < 2; ++pb)
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int pb = 0; pb < 2; ++pb)
-#pragma unroll
-          for (int fb = 0; fb < 2; ++fb)
-            acc[t][pb][fb] =
-                __builtin_amdgcn_mfma_f64_16x16x4f64(av[pb], bv[t][fb], acc[t][pb][fb], 0, 0, 0);
+        for (int fb = 0; fb < 2; ++fb)
+          acc[pb][fb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[pb], bv[fb], acc[pb][fb], 0, 0, 0);
     }
     __syncthreads();
   }
 
-  // epilogue: lane holds rows prow..prow+3 (two complex outputs) of fibre f
+  // epilogue: the accumulator of lane l holds rows g + 4r (g = l/16, r < 4)
+  // of a 16-row block b; the host's row permutation makes registers (0, 1)
+  // the (re, im) of output m = 8b + g and registers (2, 3) those of m + 4
 #pragma unroll
   for (int pb = 0; pb < 2; ++pb) {
 #pragma unroll
     for (int fb = 0; fb < 2; ++fb) {
-      const int prow = p0 + wp * 32 + pb * 16 + 4 * (lane >> 4);
+      const int mblk = 8 * ((p0 + wp * 32 + pb * 16) >> 4) + (lane >> 4);
       const int64_t f = f0 + wf * 32 + fb * 16 + (lane & 15);
       if (f >= a.F) continue;
       const int64_t base = fibre_base(f, a.R, a.n);
 #pragma unroll
       for (int hh = 0; hh < 2; ++hh) {
-        const int m = (prow >> 1) + hh;
+        const int m = mblk + 4 * hh;
         if (m >= a.n) continue;
         const int64_t off = 2 * (base + a.R * (int64_t)m);
-        const cd y0 = {acc[0][pb][fb][2 * hh], acc[0][pb][fb][2 * hh + 1]};
-        cd y1 = {0.0, 0.0};
-        if (NT == 2) y1 = {acc[NT - 1][pb][fb][2 * hh], acc[NT - 1][pb][fb][2 * hh + 1]};
+        const cd y = {acc[pb][fb][2 * hh], acc[pb][fb][2 * hh + 1]};
         if (a.epi == EPI_NONE) {
-          *reinterpret_cast<double2*>(a.out0 + off) = double2{y0.re, y0.im};
-          if (NT == 2) *reinterpret_cast<double2*>(a.out1 + off) = double2{y1.re, y1.im};
+          *reinterpret_cast<double2*>(a.out0 + off) = double2{y.re, y.im};
         } else if (a.epi == EPI_FLOW) {
-          const cd z = half_flow(y0, a.nl, flag);
+          const cd z = half_flow(y, a.nl, flag);
           if (!finite2(z)) flag |= FLAG_NONFINITE;
           *reinterpret_cast<double2*>(a.out0 + off) = double2{z.re, z.im};
-        } else if (a.epi == EPI_L4_R1) {
-          cd X, Y;
-          lawson_r1(y0, y1, a.nl, X, Y);
-          *reinterpret_cast<double2*>(a.out0 + off) = double2{X.re, X.im};
-          *reinterpret_cast<double2*>(a.out1 + off) = double2{Y.re, Y.im};
-        } else {  // EPI_L4_R2
-          const cd z = lawson_r2(y0, y1, a.nl);
-          if (!finite2(z)) flag |= FLAG_NONFINITE;
-          *reinterpret_cast<double2*>(a.out0 + off) = double2{z.re, z.im};
+        } else {
+          const double2 q = *reinterpret_cast<const double2*>(a.aux + off);
+          const cd x = {q.x, q.y};
+          if (a.epi == EPI_L4_R1) {  // y = Q, x = P
+            cd X, Y;
+            lawson_r1(x, y, a.nl, X, Y);
+            *reinterpret_cast<double2*>(a.out0 + off) = double2{X.re, X.im};
+            *reinterpret_cast<double2*>(a.out1 + off) = double2{Y.re, Y.im};
+          } else {  // EPI_L4_R2: y = H Y, x = H X
+            const cd z = lawson_r2(x, y, a.nl);
+            if (!finite2(z)) flag |= FLAG_NONFINITE;
+            *reinterpret_cast<double2*>(a.out0 + off) = double2{z.re, z.im};
+          }
         }
       }
     }
@@ -183,28 +171,20 @@ __global__ void k_clear_flag(unsigned* flag) {
 
 }  // namespace
 
-hipError_t launch_pass_f64(const PassF64& a, int ntensors, hipStream_t s) {
+hipError_t launch_pass_f64(const PassF64& a, hipStream_t s) {
   if (a.Pp % PT != 0 || a.Kp % KC != 0 || a.Kp < 2 * a.n || a.Pp < 2 * a.n || a.F <= 0)
     return hipErrorInvalidValue;
-  if (ntensors != 1 && ntensors != 2) return hipErrorInvalidValue;
-  if (a.pro == PRO_LAWSON_G && ntensors != 2) return hipErrorInvalidValue;
-  if ((a.epi == EPI_L4_R1 || a.epi == EPI_L4_R2) && ntensors != 2) return hipErrorInvalidValue;
+  if (!a.in0 || !a.out0 || !a.op || !a.flag) return hipErrorInvalidValue;
+  if ((a.epi == EPI_L4_R1 || a.epi == EPI_L4_R2) && !a.aux) return hipErrorInvalidValue;
+  if (a.epi == EPI_L4_R1 && !a.out1) return hipErrorInvalidValue;
   const int64_t nF = (a.F + FT - 1) / FT;
   const int64_t G = nF * (a.Pp / PT);
   if (G > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 grid(static_cast<unsigned>(G)), block(256);
-  const bool contig = (a.R == 1);
-  if (ntensors == 1) {
-    if (contig)
-      hipLaunchKernelGGL((k_pass_f64<1, true>), grid, block, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_pass_f64<1, false>), grid, block, 0, s, a);
-  } else {
-    if (contig)
-      hipLaunchKernelGGL((k_pass_f64<2, true>), grid, block, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_pass_f64<2, false>), grid, block, 0, s, a);
-  }
+  if (a.R == 1)
+    hipLaunchKernelGGL(k_pass_f64<true>, grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL(k_pass_f64<false>, grid, block, 0, s, a);
   return hipGetLastError();
 }
 

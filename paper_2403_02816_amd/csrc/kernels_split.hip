@@ -12,12 +12,11 @@
 // is split on the fly while it is staged into LDS (the state arrives as
 // complex64, or complex128 when the plan keeps an FP64 master state).
 //
-// Tiling: a workgroup (4 waves) owns 64 complex output rows x 64 fibres of
-// one or two tensors sharing the operator; each wave owns one 32 x 32 block
-// (one accumulator for the real part, one for the imaginary part, per
-// tensor).  A stage covers 16 complex contraction indices: 6 operator planes
-// (64 rows x 16) and 6 state planes per tensor (64 fibres x 16), rows padded
-// to 48 bytes so the 16-byte MFMA operand reads hit distinct LDS banks.
+// Tiling: a workgroup (4 waves) owns 64 complex output rows x 64 fibres;
+// each wave owns one 32 x 32 block (one accumulator for the real part, one
+// for the imaginary part).  A stage covers 16 complex contraction indices:
+// 6 operator planes (64 rows x 16) and 6 state planes (64 fibres x 16), rows
+// padded to 48 bytes so the 16-byte MFMA operand reads hit distinct LDS banks.
 #include "kernels.hpp"
 #include "pointwise.hpp"
 #include "split_layout.hpp"
@@ -91,10 +90,10 @@ __device__ __forceinline__ bf16x8 neg8(bf16x8 v) {
   return __builtin_bit_cast(bf16x8, u);
 }
 
-template <int NT, bool CONTIG>
+template <bool CONTIG>
 __global__ __launch_bounds__(256) void k_pass_split(PassSplit a) {
   __shared__ __attribute__((aligned(16))) unsigned short sA[6][PT][PITCH];
-  __shared__ __attribute__((aligned(16))) unsigned short sB[NT][6][FT][PITCH];
+  __shared__ __attribute__((aligned(16))) unsigned short sB[6][FT][PITCH];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -129,14 +128,11 @@ __global__ __launch_bounds__(256) void k_pass_split(PassSplit a) {
   }
   const bool pairF = (!CONTIG) && gb[0] >= 0 && gb[1] == gb[0] + 1;
 
-  f32x16 accr[NT], acci[NT];
+  f32x16 accr, acci;
 #pragma unroll
-  for (int x = 0; x < NT; ++x) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      accr[x][r] = 0.0f;
-      acci[x][r] = 0.0f;
-    }
+  for (int r = 0; r < 16; ++r) {
+    accr[r] = 0.0f;
+    acci[r] = 0.0f;
   }
   unsigned flag = 0;
 
@@ -157,7 +153,7 @@ __global__ __launch_bounds__(256) void k_pass_split(PassSplit a) {
         *reinterpret_cast<u32x4*>(&sA[q][r][h]) = v;
       }
     }
-    // ---- state stage: 4 complex values per tensor per thread
+    // ---- state stage: 4 complex values per thread
     {
       const int k = ks * KS + 2 * kp;
       cd v[2][2];  // [fibre i][k offset]
@@ -186,102 +182,55 @@ __global__ __launch_bounds__(256) void k_pass_split(PassSplit a) {
           }
         }
       }
-      cd v1[2][2];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int kk = 0; kk < 2; ++kk) {
-          if (a.pro == PRO_FLOW) v[i][kk] = half_flow(v[i][kk], a.nl, flag);
-          v1[i][kk] = cd{0.0, 0.0};
-        }
-      if (NT == 2) {
-        if (a.pro == PRO_LAWSON_G) {
-#pragma unroll
-          for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int kk = 0; kk < 2; ++kk) v1[i][kk] = g_cgl(v[i][kk], a.nl);
-        } else {
-          if (CONTIG) {
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-              if (gb[i] < 0) continue;
-              if (k + 1 < a.n) {
-                load_c2(a.in1, gb[i] + k, false, v1[i][0], v1[i][1]);
-              } else if (k < a.n) {
-                v1[i][0] = load_c(a.in1, gb[i] + k, false);
-              }
-            }
-          } else {
-#pragma unroll
-            for (int kk = 0; kk < 2; ++kk) {
-              if (k + kk >= a.n) continue;
-              if (pairF) {
-                load_c2(a.in1, gb[0] + a.R * (int64_t)(k + kk), false, v1[0][kk], v1[1][kk]);
-              } else {
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-                  if (gb[i] >= 0) v1[i][kk] = load_c(a.in1, gb[i] + a.R * (int64_t)(k + kk), false);
-              }
-            }
+          if (a.pro == PRO_FLOW) {
+            v[i][kk] = half_flow(v[i][kk], a.nl, flag);
+          } else if (a.pro == PRO_G) {
+            v[i][kk] = g_cgl(v[i][kk], a.nl);
           }
         }
-      }
       // split and write: plane q (0..2 re terms, 3..5 im terms), two k per u32
 #pragma unroll
-      for (int x = 0; x < NT; ++x) {
+      for (int i = 0; i < 2; ++i) {
+        unsigned short r0[3], r1[3], i0[3], i1[3];
+        split3(v[i][0].re, r0);
+        split3(v[i][1].re, r1);
+        split3(v[i][0].im, i0);
+        split3(v[i][1].im, i1);
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          const cd e0 = (x == 0) ? v[i][0] : v1[i][0];
-          const cd e1 = (x == 0) ? v[i][1] : v1[i][1];
-          unsigned short r0[3], r1[3], i0[3], i1[3];
-          split3(e0.re, r0);
-          split3(e1.re, r1);
-          split3(e0.im, i0);
-          split3(e1.im, i1);
-#pragma unroll
-          for (int t = 0; t < 3; ++t) {
-            *reinterpret_cast<unsigned*>(&sB[x][t][fl[i]][2 * kp]) =
-                static_cast<unsigned>(r0[t]) | (static_cast<unsigned>(r1[t]) << 16);
-            *reinterpret_cast<unsigned*>(&sB[x][3 + t][fl[i]][2 * kp]) =
-                static_cast<unsigned>(i0[t]) | (static_cast<unsigned>(i1[t]) << 16);
-          }
+        for (int t = 0; t < 3; ++t) {
+          *reinterpret_cast<unsigned*>(&sB[t][fl[i]][2 * kp]) =
+              static_cast<unsigned>(r0[t]) | (static_cast<unsigned>(r1[t]) << 16);
+          *reinterpret_cast<unsigned*>(&sB[3 + t][fl[i]][2 * kp]) =
+              static_cast<unsigned>(i0[t]) | (static_cast<unsigned>(i1[t]) << 16);
         }
       }
     }
     __syncthreads();
-    // ---- MFMA: 6 term products x 4 real products per tensor
+    // ---- MFMA: 6 term products x 4 real products
     {
-      bf16x8 ar[3], ai[3], an[3];
+      bf16x8 ar[3], ai[3], an[3], br[3], bi[3];
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
         ar[t] = *reinterpret_cast<const bf16x8*>(&sA[t][wp * 32 + row][kh]);
         ai[t] = *reinterpret_cast<const bf16x8*>(&sA[3 + t][wp * 32 + row][kh]);
         an[t] = neg8(ai[t]);
+        br[t] = *reinterpret_cast<const bf16x8*>(&sB[t][wf * 32 + row][kh]);
+        bi[t] = *reinterpret_cast<const bf16x8*>(&sB[3 + t][wf * 32 + row][kh]);
       }
-      bf16x8 br[NT][3], bi[NT][3];
-#pragma unroll
-      for (int x = 0; x < NT; ++x)
-#pragma unroll
-        for (int t = 0; t < 3; ++t) {
-          br[x][t] = *reinterpret_cast<const bf16x8*>(&sB[x][t][wf * 32 + row][kh]);
-          bi[x][t] = *reinterpret_cast<const bf16x8*>(&sB[x][3 + t][wf * 32 + row][kh]);
-        }
       // term pairs (i, j) with i + j <= 2, smallest first
       constexpr int PI[6] = {2, 1, 0, 1, 0, 0};
       constexpr int PJ[6] = {0, 1, 2, 0, 1, 0};
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
         const int ti = PI[q], tj = PJ[q];
-#pragma unroll
-        for (int x = 0; x < NT; ++x) {
-          accr[x] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ti], br[x][tj], accr[x], 0, 0, 0);
-          acci[x] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ai[ti], br[x][tj], acci[x], 0, 0, 0);
-        }
-#pragma unroll
-        for (int x = 0; x < NT; ++x) {
-          accr[x] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an[ti], bi[x][tj], accr[x], 0, 0, 0);
-          acci[x] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ti], bi[x][tj], acci[x], 0, 0, 0);
-        }
+        accr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ti], br[tj], accr, 0, 0, 0);
+        acci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ai[ti], br[tj], acci, 0, 0, 0);
+        accr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an[ti], bi[tj], accr, 0, 0, 0);
+        acci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ti], bi[tj], acci, 0, 0, 0);
       }
     }
     __syncthreads();
@@ -296,25 +245,25 @@ __global__ __launch_bounds__(256) void k_pass_split(PassSplit a) {
       const int m = pt * PT + wp * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
       if (m >= a.n) continue;
       const int64_t off = base + a.R * (int64_t)m;
-      const cd y0 = {static_cast<double>(accr[0][r]), static_cast<double>(acci[0][r])};
-      cd y1 = {0.0, 0.0};
-      if (NT == 2) y1 = {static_cast<double>(accr[NT - 1][r]), static_cast<double>(acci[NT - 1][r])};
+      const cd y = {static_cast<double>(accr[r]), static_cast<double>(acci[r])};
       if (a.epi == EPI_NONE) {
-        store_c(a.out0, off, of64, y0);
-        if (NT == 2) store_c(a.out1, off, of64, y1);
+        store_c(a.out0, off, of64, y);
       } else if (a.epi == EPI_FLOW) {
-        const cd z = half_flow(y0, a.nl, flag);
+        const cd z = half_flow(y, a.nl, flag);
         if (!finite2(z)) flag |= FLAG_NONFINITE;
         store_c(a.out0, off, of64, z);
-      } else if (a.epi == EPI_L4_R1) {
-        cd X, Y;
-        lawson_r1(y0, y1, a.nl, X, Y);
-        store_c(a.out0, off, of64, X);
-        store_c(a.out1, off, of64, Y);
       } else {
-        const cd z = lawson_r2(y0, y1, a.nl);
-        if (!finite2(z)) flag |= FLAG_NONFINITE;
-        store_c(a.out0, off, of64, z);
+        const cd x = load_c(a.aux, off, false);
+        if (a.epi == EPI_L4_R1) {  // y = Q, x = P
+          cd X, Y;
+          lawson_r1(x, y, a.nl, X, Y);
+          store_c(a.out0, off, of64, X);
+          store_c(a.out1, off, of64, Y);
+        } else {  // EPI_L4_R2: y = H Y, x = H X
+          const cd z = lawson_r2(x, y, a.nl);
+          if (!finite2(z)) flag |= FLAG_NONFINITE;
+          store_c(a.out0, off, of64, z);
+        }
       }
     }
   }
@@ -323,28 +272,20 @@ __global__ __launch_bounds__(256) void k_pass_split(PassSplit a) {
 
 }  // namespace
 
-hipError_t launch_pass_split(const PassSplit& a, int ntensors, hipStream_t s) {
+hipError_t launch_pass_split(const PassSplit& a, hipStream_t s) {
   if (a.Pp % PT != 0 || a.Kp % KS != 0 || a.Kp < a.n || a.Pp < a.n || a.F <= 0)
     return hipErrorInvalidValue;
-  if (ntensors != 1 && ntensors != 2) return hipErrorInvalidValue;
-  if (a.pro == PRO_LAWSON_G && ntensors != 2) return hipErrorInvalidValue;
-  if ((a.epi == EPI_L4_R1 || a.epi == EPI_L4_R2) && ntensors != 2) return hipErrorInvalidValue;
+  if (!a.in0 || !a.out0 || !a.op || !a.flag) return hipErrorInvalidValue;
+  if ((a.epi == EPI_L4_R1 || a.epi == EPI_L4_R2) && !a.aux) return hipErrorInvalidValue;
+  if (a.epi == EPI_L4_R1 && !a.out1) return hipErrorInvalidValue;
   const int64_t nF = (a.F + FT - 1) / FT;
   const int64_t G = nF * (a.Pp / PT);
   if (G > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 grid(static_cast<unsigned>(G)), block(256);
-  const bool contig = (a.R == 1);
-  if (ntensors == 1) {
-    if (contig)
-      hipLaunchKernelGGL((k_pass_split<1, true>), grid, block, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_pass_split<1, false>), grid, block, 0, s, a);
-  } else {
-    if (contig)
-      hipLaunchKernelGGL((k_pass_split<2, true>), grid, block, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_pass_split<2, false>), grid, block, 0, s, a);
-  }
+  if (a.R == 1)
+    hipLaunchKernelGGL(k_pass_split<true>, grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL(k_pass_split<false>, grid, block, 0, s, a);
   return hipGetLastError();
 }
 

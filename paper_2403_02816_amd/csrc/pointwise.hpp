@@ -5,7 +5,7 @@
 //  phi^c_t   = exact flow of u' = (a3 + i b3)|u|^2 u          (eq. exsolcub)
 //  phi_t     = one classical RK4 step of u' = g(u) (eq. RK4 with K = 0) when
 //              there is no exact flow (cubic-quintic case, Section 4.3)
-//  Lawson4 stage combinations of eq. (lawson4), regrouped into two rounds of
+//  Lawson4 stage combinations of eq. (lawson4), regrouped around four
 //  half-step exponential actions.
 #pragma once
 
@@ -74,7 +74,7 @@ __device__ __forceinline__ cd half_flow(cd u, const NlParams& p, unsigned& flag)
 
 __device__ __forceinline__ bool finite2(cd u) { return isfinite(u.re) && isfinite(u.im); }
 
-// Lawson4 round 1 epilogue: from P = e^{tau K/2} u and Q = e^{tau K/2} g(u)
+// Lawson4 round 1 combination: from P = e^{tau K/2} u and Q = e^{tau K/2} g(u)
 //   u2 = P + tau/2 Q,  u3 = P + tau/2 g(u2),
 //   X = P + tau g(u3),  Y = P + tau/6 Q + tau/3 (g(u2) + g(u3)),
 // so that u4 = e^{tau K/2} X and u_{n+1} = e^{tau K/2} Y + tau/6 g(u4).
@@ -88,7 +88,7 @@ __device__ __forceinline__ void lawson_r1(cd P, cd Q, const NlParams& p, cd& X, 
   Y = caxpy(t / 3.0, cadd(g2, g3), caxpy(t / 6.0, Q, P));
 }
 
-// Lawson4 round 2 epilogue: u_{n+1} = HY + tau/6 g(HX)
+// Lawson4 round 2 combination: u_{n+1} = HY + tau/6 g(HX)
 __device__ __forceinline__ cd lawson_r2(cd HX, cd HY, const NlParams& p) {
   return caxpy(p.tau / 6.0, g_cgl(HX, p), HY);
 }

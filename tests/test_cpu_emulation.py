@@ -1,0 +1,26 @@
+"""Runs the library's host code and HIP kernels on the CPU (emulated HIP
+runtime, one host thread per lane, emulated MFMA) under AddressSanitizer and
+UndefinedBehaviorSanitizer: every entry point, both precisions, every kernel
+variant (mu = 1 contiguous, mu > 1 strided, ragged tiles), d = 1..3, graph
+replay.  Fails on any out-of-bounds access, UB, or a mode product / Tucker
+result off the naive reference."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.mark.skipif(not os.path.exists("/opt/rocm/llvm/bin/clang++"), reason="needs ROCm clang++")
+def test_library_under_cpu_emulation_with_sanitizers():
+    from tests.cpu_emu import build as emu_build
+    exe = emu_build.build()
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    r = subprocess.run([exe, "quick"], capture_output=True, text=True, timeout=900, env=env)
+    print(r.stdout[-4000:])
+    print(r.stderr[-4000:])
+    assert r.returncode == 0
+    assert "PASSED (0 failures)" in r.stdout
