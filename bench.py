@@ -52,11 +52,9 @@ def workload(name):
 
 
 def launches_per_step(method, d):
-    return d if method == "strang" else 2 * d
-
-
-def tensors_per_launch(method):
-    return 1 if method == "strang" else 2
+    """mu-mode pass launches per step: one exponential action (d passes) for
+    Strang, four actions of e^{tau K/2} for Lawson4."""
+    return d if method == "strang" else 4 * d
 
 
 def time_form(p, method, precision, steps, warmup, u0):
@@ -149,15 +147,14 @@ def main():
     ms_step = ms / K
     value = p.N * K / (ms * 1e-3)
     nl = launches_per_step(method, p.d)
-    nt = tensors_per_launch(method)
     launch_ms = ms / (K * nl)
-    # algorithmic work of one launch: every grid point of nt tensors gets one
-    # complex mu-mode product of length n (8 n real flops); the split form
-    # issues 6 bf16 term products for each, so its MFMA work is 6x that
+    # algorithmic work of one launch: every grid point gets one complex
+    # mu-mode product of length n (8 n real flops); the split form issues 6
+    # bf16 term products for each, so its MFMA work is 6x that
     n_mu = p.n[0]
-    alg_flops = 8.0 * p.N * n_mu * nt
+    alg_flops = 8.0 * p.N * n_mu
     mfma_flops = 6.0 * alg_flops
-    alg_bytes = nt * p.N * (8 + 8)
+    alg_bytes = p.N * (8 + 8)
     achieved_tf = mfma_flops / (launch_ms * 1e-3) / 1e12
     gate = one_step_gate(p, method, plan)
     split_state = u.clone()
