@@ -3,9 +3,9 @@
 
 Workload (default): 3-D cubic-quintic CGL on a 128^3 Neumann vertex grid on
 (-15,15)^3, 2nd-order FD, Lawson4 with tau = 5e-3, seeded Gaussian vortex
-ring u0.  One step = one Lawson4 step of the whole grid (four actions of
-e^{tau K/2} in two rounds of three mu-mode passes over a tensor pair, with the
-nonlinear stages fused into the pass epilogues/prologues).
+ring u0.  One step = one Lawson4 step of the whole grid: four actions of
+e^{tau K/2} (three mu-mode passes each), with g and the Lawson4 stage
+combinations fused into the first-pass prologues and last-pass epilogues.
 
 The timed form is the split-precision form (complex64 stage tensors,
 bf16x3 operands, FP32 accumulation); the FP64 form is timed beside it.
@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 256 MiB device-to-device copy (a kernel of known "
+                         "traffic for scaling HBM counters)")
     return ap.parse_args()
 
 
@@ -142,6 +145,12 @@ def main():
     p, method = workload(args.workload)
     u0 = ci.initial_state(p)
     K, W = args.steps, args.warmup
+    if args.calibrate_copy:
+        a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        b = torch.ones_like(a)
+        a.copy_(b)
+        torch.cuda.synchronize()
+        del a, b
 
     plan, u, ms, wall = time_form(p, method, "split", K, W, u0)
     ms_step = ms / K
