@@ -134,12 +134,15 @@ int upload_op(cgl_plan_s* p, const CMat& M, DeviceOp& dst) {
 
 // One mu-mode pass: out0 (, out1) = epilogue(in0 x_mu M, aux), with the
 // prologue applied to in0 as it is staged.
+// rotated: the input's contraction axis is its fastest one and the output is
+// written with that axis moved to the slowest position (split form only).
 int pass(cgl_plan_s* p, int mu, int which, const void* in0, const void* aux, void* out0,
-         void* out1, int pro, int epi, bool in_f64, bool out_f64, hipStream_t s) {
+         void* out1, int pro, int epi, bool in_f64, bool out_f64, bool rotated, hipStream_t s) {
   const DeviceOp& op = (which == CGL_E) ? p->dE[mu] : p->dH[mu];
   int64_t R = 1;
   for (int nu = 0; nu < mu; ++nu) R *= p->n[nu];
   const int n = static_cast<int>(p->n[mu]);
+  if (rotated && p->precision != CGL_SPLIT_BF16) return CGL_EINVAL;
   hipError_t e;
   if (p->precision == CGL_FP64) {
     PassF64 a{};
@@ -165,7 +168,8 @@ int pass(cgl_plan_s* p, int mu, int which, const void* in0, const void* aux, voi
     a.out0 = out0;
     a.out1 = out1;
     a.op = static_cast<const uint16_t*>(op.ptr);
-    a.R = R;
+    a.R = rotated ? 1 : R;
+    a.R_out = rotated ? p->N / n : R;
     a.F = p->N / n;
     a.n = n;
     a.Pp = op.Pp;
@@ -187,6 +191,9 @@ int pass(cgl_plan_s* p, int mu, int which, const void* in0, const void* aux, voi
 // buffer: with d = 1 and out0 == in0 the result goes through stage[0].
 int action(cgl_plan_s* p, int which, const void* in0, const void* aux, void* out0, void* out1,
            int pro, int epi, bool in_f64, bool out_f64, hipStream_t s) {
+  // the split form rotates the axis order by one per pass (back to the
+  // original after d passes); the FP64 form contracts in place
+  const bool rotated = p->precision == CGL_SPLIT_BF16;
   const void* cur = in0;
   bool cf64 = in_f64;
   for (int mu = 0; mu < p->d; ++mu) {
@@ -196,7 +203,7 @@ int action(cgl_plan_s* p, int which, const void* in0, const void* aux, void* out
     if (via_tmp) dst = p->stage[0];
     const bool of64 = last ? out_f64 : false;
     int st = pass(p, mu, which, cur, aux, dst, out1, mu == 0 ? pro : PRO_NONE,
-                  last ? epi : EPI_NONE, cf64, of64, s);
+                  last ? epi : EPI_NONE, cf64, of64, rotated, s);
     if (st != CGL_OK) return st;
     if (via_tmp) {
       // stage buffers are sized for the caller's element type (see cgl_plan)
@@ -381,7 +388,7 @@ int cgl_mode_product(cgl_plan_t p, int mu, int which, const void* in_dev, void* 
   if (which != CGL_E && which != CGL_H) return CGL_EINVAL;
   if (!p->have_ops[mu]) return CGL_ENOTREADY;
   return pass(p, mu, which, in_dev, nullptr, out_dev, nullptr, PRO_NONE, EPI_NONE, false, false,
-              p->ustream);
+              false, p->ustream);
 }
 
 int cgl_tucker(cgl_plan_t p, int which, const void* in_dev, void* out_dev) {

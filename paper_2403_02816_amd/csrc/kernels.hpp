@@ -3,7 +3,11 @@
 // One pass computes out = in x_mu M for one direction mu of a column-major
 // (index 1 fastest) complex tensor.  With R = n_1...n_{mu-1} and n = n_mu,
 // fibre f = (r, b) (r = f mod R, b = f div R) starts at complex offset
-// r + b R n and steps by R; F = N / n fibres.  The complex product is run as
+// r + b R n and steps by R; F = N / n fibres.  Input and output may use
+// different R: the exponential actions of the time steppers run every pass
+// on a tensor whose contraction axis is the fastest one (R_in = 1) and write
+// its result with that axis moved to the slowest position (R_out = F), so
+// after d passes the axis order is the original one again.  The complex product is run as
 // the real product of the 2n x 2n block embedding
 //   [[Re M, -Im M], [Im M, Re M]]
 // with real rows/columns interleaved (2m + c, c = 0 real, 1 imaginary), so that
@@ -74,11 +78,12 @@ hipError_t launch_clear_flag(unsigned* flag, hipStream_t s);
 // state at the pass ends), bf16 operator terms, FP32 accumulation.
 struct PassSplit {
   const void* in0;
-  const void* aux;  // complex64 stage tensor
+  const void* aux;  // complex64 stage tensor, in the output's layout
   void* out0;
   void* out1;
   const uint16_t* op;  // bf16 terms of the embedding, see kernels_split.hip
-  int64_t R;
+  int64_t R;       // input: contraction stride
+  int64_t R_out;   // output: contraction stride
   int64_t F;
   int n;
   int Pp;

@@ -2,21 +2,24 @@
 // with FP32 accumulation.
 //
 // Every operand is a sum of three bf16 terms (hi + mid + lo, each the bf16
-// rounding of what the previous terms left over), which carries ~24
-// significant bits.  Of the nine term products the six with i + j <= 2 are
-// kept (the dropped ones are below FP32 rounding of the result).  The complex
-// product is split into four real products,
+// rounding of what the previous terms left over), which carries the 24
+// significant bits of an FP32 value.  Of the nine term products the six with
+// i + j <= 2 are kept (the dropped ones are below FP32 rounding of the
+// result).  The complex product is split into four real products,
 //   Re y += Re M Re x - Im M Im x,   Im y += Im M Re x + Re M Im x,
-// so one workgroup tile costs 6 x 4 MFMAs per 16-deep contraction step.
+// so one 32 x 32 output block costs 6 x 4 MFMAs per 16-deep contraction step.
 // Operator planes come pre-split from the host (split_layout.hpp); the state
-// is split on the fly while it is staged into LDS (the state arrives as
-// complex64, or complex128 when the plan keeps an FP64 master state).
+// is split on the fly (packed FP32 -> bf16 conversions) while it is staged
+// into LDS.  The state arrives as complex64, or complex128 when the plan
+// keeps an FP64 master state.
 //
-// Tiling: a workgroup (4 waves) owns 64 complex output rows x 64 fibres;
-// each wave owns one 32 x 32 block (one accumulator for the real part, one
-// for the imaginary part).  A stage covers 16 complex contraction indices:
-// 6 operator planes (64 rows x 16) and 6 state planes (64 fibres x 16), rows
-// padded to 48 bytes so the 16-byte MFMA operand reads hit distinct LDS banks.
+// Tiling: a workgroup (4 waves) owns 64 complex output rows x 64 fibres; each
+// wave owns one 32 x 32 block (one FP32 accumulator for the real part, one for
+// the imaginary part).  A stage covers 32 complex contraction indices: 6
+// operator planes (64 rows x 32) and 6 state planes (64 fibres x 32), rows
+// padded to 80 bytes so the 16-byte MFMA operand reads of 16 lanes hit
+// distinct LDS banks.  The next stage's global loads are issued into registers
+// before the current stage's MFMAs, so their latency overlaps the math.
 #include "kernels.hpp"
 #include "pointwise.hpp"
 #include "split_layout.hpp"
@@ -24,16 +27,20 @@
 namespace cgl {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4u __attribute__((ext_vector_type(4), aligned(8)));
 
 namespace {
 
-constexpr int PT = SPK_P;    // 64 complex rows
-constexpr int FT = SP_FT;    // 64 fibres
-constexpr int KS = SPK_K;    // 16 complex contraction indices per stage
-constexpr int PITCH = 24;    // LDS row pitch in bf16 (48 bytes)
+constexpr int PT = SPK_P;   // 64 complex rows
+constexpr int FT = SP_FT;   // 64 fibres
+constexpr int KS = SPK_K;   // 32 complex contraction indices per stage
+constexpr int PITCH = 40;   // LDS row pitch in bf16 (80 bytes)
+constexpr int OPCH = 6 * PT * KS / 8 / 256;  // 16-byte operator chunks per thread per stage
 
 __device__ __forceinline__ int64_t fibre_base(int64_t f, int64_t R, int n) {
   return (R == 1) ? f * (int64_t)n : (f % R) + (f / R) * R * (int64_t)n;
@@ -43,14 +50,38 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned h, unsigned G) {
   return ((G & 7u) == 0u) ? (h & 7u) * (G >> 3) + (h >> 3) : h;
 }
 
-// three bf16 terms of x (RNE at each level; remainders exact in FP64)
-__device__ __forceinline__ void split3(double x, unsigned short t[3]) {
-  double r = x;
+// three bf16 terms of two FP32 values (packed conversion, RNE); the
+// remainders are exact in FP32
+__device__ __forceinline__ void split3x2(float x0, float x1, unsigned t[3]) {
+  f32x2 r = {x0, x1};
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const __bf16 h = static_cast<__bf16>(static_cast<float>(r));
-    t[i] = __builtin_bit_cast(unsigned short, h);
-    r -= static_cast<double>(static_cast<float>(h));
+    const bf16x2 h = __builtin_convertvector(r, bf16x2);
+    t[i] = __builtin_bit_cast(unsigned, h);
+    r = r - __builtin_convertvector(h, f32x2);
+  }
+}
+
+__device__ __forceinline__ cf load_cf(const void* p, int64_t off, bool f64) {
+  if (f64) {
+    const double2 v = reinterpret_cast<const double2*>(p)[off];
+    return {static_cast<float>(v.x), static_cast<float>(v.y)};
+  }
+  const float2 v = reinterpret_cast<const float2*>(p)[off];
+  return {v.x, v.y};
+}
+
+// two adjacent complex elements at off, off+1
+__device__ __forceinline__ void load_cf2(const void* p, int64_t off, bool f64, cf& x, cf& y) {
+  if (f64) {
+    const double2* q = reinterpret_cast<const double2*>(p) + off;
+    const double2 a = q[0], b = q[1];
+    x = {static_cast<float>(a.x), static_cast<float>(a.y)};
+    y = {static_cast<float>(b.x), static_cast<float>(b.y)};
+  } else {
+    const f32x4u v = *reinterpret_cast<const f32x4u*>(reinterpret_cast<const float*>(p) + 2 * off);
+    x = {v[0], v[1]};
+    y = {v[2], v[3]};
   }
 }
 
@@ -61,20 +92,6 @@ __device__ __forceinline__ cd load_c(const void* p, int64_t off, bool f64) {
   }
   const float2 v = reinterpret_cast<const float2*>(p)[off];
   return {static_cast<double>(v.x), static_cast<double>(v.y)};
-}
-
-// two adjacent complex elements at off, off+1
-__device__ __forceinline__ void load_c2(const void* p, int64_t off, bool f64, cd& x, cd& y) {
-  if (f64) {
-    const double2* q = reinterpret_cast<const double2*>(p) + off;
-    const double2 a = q[0], b = q[1];
-    x = {a.x, a.y};
-    y = {b.x, b.y};
-  } else {
-    const f32x4u v = *reinterpret_cast<const f32x4u*>(reinterpret_cast<const float*>(p) + 2 * off);
-    x = {static_cast<double>(v[0]), static_cast<double>(v[1])};
-    y = {static_cast<double>(v[2]), static_cast<double>(v[3])};
-  }
 }
 
 __device__ __forceinline__ void store_c(void* p, int64_t off, bool f64, cd v) {
@@ -90,8 +107,20 @@ __device__ __forceinline__ bf16x8 neg8(bf16x8 v) {
   return __builtin_bit_cast(bf16x8, u);
 }
 
+// Staging geometry of one thread: FI fibres x KJ consecutive contraction
+// indices.  Contiguous contraction axis: 1 fibre x 8 indices (4 threads cover
+// the 32 indices of a fibre with 64-byte loads); strided: 2 adjacent fibres x
+// 4 indices (32 threads cover 64 adjacent fibres of one index, 16-byte loads).
 template <bool CONTIG>
-__global__ __launch_bounds__(256) void k_pass_split(PassSplit a) {
+struct Stage {
+  static constexpr int FI = CONTIG ? 1 : 2;
+  static constexpr int KJ = CONTIG ? 8 : 4;
+};
+
+template <bool CONTIG, int PRO, bool IN64>
+__global__ __launch_bounds__(256, 2) void k_pass_split(PassSplit a) {
+  constexpr int FI = Stage<CONTIG>::FI;
+  constexpr int KJ = Stage<CONTIG>::KJ;
   __shared__ __attribute__((aligned(16))) unsigned short sA[6][PT][PITCH];
   __shared__ __attribute__((aligned(16))) unsigned short sB[6][FT][PITCH];
 
@@ -105,28 +134,84 @@ __global__ __launch_bounds__(256) void k_pass_split(PassSplit a) {
   const unsigned w = xcd_remap(blockIdx.x, gridDim.x);
   const int pt = static_cast<int>(w % nP);
   const int64_t f0 = static_cast<int64_t>(w / nP) * FT;
-  const unsigned short* opblk = a.op + static_cast<size_t>(pt) * nKS * (6 * PT * KS);
-  const bool if64 = a.in_f64 != 0;
+  const u32x4* opblk =
+      reinterpret_cast<const u32x4*>(a.op + static_cast<size_t>(pt) * nKS * (6 * PT * KS));
   const bool of64 = a.out_f64 != 0;
+  // every fibre of the tile exists and every stage is full: no masks needed
+  const bool full = (f0 + FT <= a.F) && (a.n % KS == 0);
 
-  // staging assignment: two fibres (fl[0], fl[1]) x two contraction indices (2kp, 2kp+1)
-  int fl[2], kp;
+  // this thread's fibres and first contraction index within a stage
+  int fl[FI];
+  int k0t;
   if (CONTIG) {
-    fl[0] = tid >> 3;
-    fl[1] = fl[0] + 32;
-    kp = tid & 7;
+    fl[0] = tid >> 2;
+    k0t = 8 * (tid & 3);
   } else {
     fl[0] = 2 * (tid & 31);
-    fl[1] = fl[0] + 1;
-    kp = tid >> 5;
+    fl[FI - 1] = fl[0] + 1;
+    k0t = 4 * (tid >> 5);
   }
-  int64_t gb[2];
+  int64_t gb[FI];
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < FI; ++i) {
     const int64_t f = f0 + fl[i];
     gb[i] = (f < a.F) ? fibre_base(f, a.R, a.n) : -1;
   }
-  const bool pairF = (!CONTIG) && gb[0] >= 0 && gb[1] == gb[0] + 1;
+  const bool pairF = (!CONTIG) && gb[0] >= 0 && gb[FI - 1] == gb[0] + 1;
+  // contiguous fast path: a running pointer to this thread's first element
+  const char* inp = reinterpret_cast<const char*>(a.in0) +
+                    (CONTIG ? (gb[0] >= 0 ? gb[0] : 0) + k0t : 0) * (IN64 ? 16 : 8);
+
+  u32x4 opr[OPCH];  // prefetched operator chunks
+  cf vin[FI][KJ];   // prefetched state values
+
+  auto load_stage = [&](int ks) {
+    const u32x4* src = opblk + static_cast<size_t>(ks) * (6 * PT * KS / 8);
+#pragma unroll
+    for (int j = 0; j < OPCH; ++j) opr[j] = src[tid + 256 * j];
+    if (CONTIG && full) {
+      const char* q = inp + static_cast<size_t>(ks) * KS * (IN64 ? 16 : 8);
+#pragma unroll
+      for (int j = 0; j < KJ; j += 2) {
+        if (IN64) {
+          const double2 x = reinterpret_cast<const double2*>(q)[j];
+          const double2 y = reinterpret_cast<const double2*>(q)[j + 1];
+          vin[0][j] = cf{static_cast<float>(x.x), static_cast<float>(x.y)};
+          vin[0][j + 1] = cf{static_cast<float>(y.x), static_cast<float>(y.y)};
+        } else {
+          const f32x4u v = reinterpret_cast<const f32x4u*>(q)[j / 2];
+          vin[0][j] = cf{v[0], v[1]};
+          vin[0][j + 1] = cf{v[2], v[3]};
+        }
+      }
+      return;
+    }
+    const int kb = ks * KS + k0t;
+#pragma unroll
+    for (int i = 0; i < FI; ++i)
+#pragma unroll
+      for (int j = 0; j < KJ; ++j) vin[i][j] = cf{0.0f, 0.0f};
+    if (CONTIG) {
+      if (gb[0] >= 0) {
+#pragma unroll
+        for (int j = 0; j < KJ; ++j)
+          if (kb + j < a.n) vin[0][j] = load_cf(a.in0, gb[0] + kb + j, IN64);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < KJ; ++j) {
+        const int k = kb + j;
+        if (k >= a.n) continue;
+        if (pairF) {
+          load_cf2(a.in0, gb[0] + a.R * (int64_t)k, IN64, vin[0][j], vin[FI - 1][j]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < FI; ++i)
+            if (gb[i] >= 0) vin[i][j] = load_cf(a.in0, gb[i] + a.R * (int64_t)k, IN64);
+        }
+      }
+    }
+  };
 
   f32x16 accr, acci;
 #pragma unroll
@@ -135,120 +220,99 @@ __global__ __launch_bounds__(256) void k_pass_split(PassSplit a) {
     acci[r] = 0.0f;
   }
   unsigned flag = 0;
-
   const int row = lane & 31;
   const int kh = (lane >> 5) * 8;
 
+  load_stage(0);
   for (int ks = 0; ks < nKS; ++ks) {
-    // ---- operator stage: 768 chunks of 16 bytes
-    {
-      const u32x4* src = reinterpret_cast<const u32x4*>(opblk + static_cast<size_t>(ks) * (6 * PT * KS));
+    // ---- registers -> LDS: operator planes as they are; state through the
+    // prologue and split into bf16 terms
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        const int c = tid + 256 * j;
-        const u32x4 v = src[c];
-        const int q = c >> 7;
-        const int r = (c >> 1) & 63;
-        const int h = (c & 1) * 8;
-        *reinterpret_cast<u32x4*>(&sA[q][r][h]) = v;
-      }
+    for (int j = 0; j < OPCH; ++j) {
+      const int c = tid + 256 * j;
+      *reinterpret_cast<u32x4*>(&sA[c >> 8][(c >> 2) & 63][8 * (c & 3)]) = opr[j];
     }
-    // ---- state stage: 4 complex values per thread
-    {
-      const int k = ks * KS + 2 * kp;
-      cd v[2][2];  // [fibre i][k offset]
 #pragma unroll
-      for (int i = 0; i < 2; ++i) v[i][0] = v[i][1] = cd{0.0, 0.0};
-      if (CONTIG) {
+    for (int i = 0; i < FI; ++i) {
+      if (PRO == PRO_FLOW) {
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          if (gb[i] < 0) continue;
-          if (k + 1 < a.n) {
-            load_c2(a.in0, gb[i] + k, if64, v[i][0], v[i][1]);
-          } else if (k < a.n) {
-            v[i][0] = load_c(a.in0, gb[i] + k, if64);
-          }
-        }
-      } else {
+        for (int j = 0; j < KJ; ++j) vin[i][j] = half_flow_f(vin[i][j], a.nl, flag);
+      } else if (PRO == PRO_G) {
 #pragma unroll
-        for (int kk = 0; kk < 2; ++kk) {
-          if (k + kk >= a.n) continue;
-          if (pairF) {
-            load_c2(a.in0, gb[0] + a.R * (int64_t)(k + kk), if64, v[0][kk], v[1][kk]);
-          } else {
+        for (int j = 0; j < KJ; ++j) vin[i][j] = g_cgl_f(vin[i][j], a.nl);
+      }
+      unsigned tr[3][KJ / 2], ti[3][KJ / 2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-              if (gb[i] >= 0) v[i][kk] = load_c(a.in0, gb[i] + a.R * (int64_t)(k + kk), if64);
-          }
-        }
+      for (int j = 0; j < KJ; j += 2) {
+        unsigned t3[3];
+        split3x2(vin[i][j].re, vin[i][j + 1].re, t3);
+#pragma unroll
+        for (int t = 0; t < 3; ++t) tr[t][j / 2] = t3[t];
+        split3x2(vin[i][j].im, vin[i][j + 1].im, t3);
+#pragma unroll
+        for (int t = 0; t < 3; ++t) ti[t][j / 2] = t3[t];
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int kk = 0; kk < 2; ++kk) {
-          if (a.pro == PRO_FLOW) {
-            v[i][kk] = half_flow(v[i][kk], a.nl, flag);
-          } else if (a.pro == PRO_G) {
-            v[i][kk] = g_cgl(v[i][kk], a.nl);
-          }
-        }
-      // split and write: plane q (0..2 re terms, 3..5 im terms), two k per u32
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        unsigned short r0[3], r1[3], i0[3], i1[3];
-        split3(v[i][0].re, r0);
-        split3(v[i][1].re, r1);
-        split3(v[i][0].im, i0);
-        split3(v[i][1].im, i1);
-#pragma unroll
-        for (int t = 0; t < 3; ++t) {
-          *reinterpret_cast<unsigned*>(&sB[t][fl[i]][2 * kp]) =
-              static_cast<unsigned>(r0[t]) | (static_cast<unsigned>(r1[t]) << 16);
-          *reinterpret_cast<unsigned*>(&sB[3 + t][fl[i]][2 * kp]) =
-              static_cast<unsigned>(i0[t]) | (static_cast<unsigned>(i1[t]) << 16);
+      for (int t = 0; t < 3; ++t) {
+        if (KJ == 8) {
+          *reinterpret_cast<u32x4*>(&sB[t][fl[i]][k0t]) = u32x4{tr[t][0], tr[t][1], tr[t][2], tr[t][3]};
+          *reinterpret_cast<u32x4*>(&sB[3 + t][fl[i]][k0t]) =
+              u32x4{ti[t][0], ti[t][1], ti[t][2], ti[t][3]};
+        } else {
+          *reinterpret_cast<u32x2*>(&sB[t][fl[i]][k0t]) = u32x2{tr[t][0], tr[t][1]};
+          *reinterpret_cast<u32x2*>(&sB[3 + t][fl[i]][k0t]) = u32x2{ti[t][0], ti[t][1]};
         }
       }
     }
     __syncthreads();
-    // ---- MFMA: 6 term products x 4 real products
-    {
+    if (ks + 1 < nKS) load_stage(ks + 1);
+    // ---- MFMA: two 16-deep steps, 6 term products x 4 real products each
+#pragma unroll
+    for (int kk = 0; kk < KS; kk += 16) {
       bf16x8 ar[3], ai[3], an[3], br[3], bi[3];
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
-        ar[t] = *reinterpret_cast<const bf16x8*>(&sA[t][wp * 32 + row][kh]);
-        ai[t] = *reinterpret_cast<const bf16x8*>(&sA[3 + t][wp * 32 + row][kh]);
+        ar[t] = *reinterpret_cast<const bf16x8*>(&sA[t][wp * 32 + row][kk + kh]);
+        ai[t] = *reinterpret_cast<const bf16x8*>(&sA[3 + t][wp * 32 + row][kk + kh]);
         an[t] = neg8(ai[t]);
-        br[t] = *reinterpret_cast<const bf16x8*>(&sB[t][wf * 32 + row][kh]);
-        bi[t] = *reinterpret_cast<const bf16x8*>(&sB[3 + t][wf * 32 + row][kh]);
+        br[t] = *reinterpret_cast<const bf16x8*>(&sB[t][wf * 32 + row][kk + kh]);
+        bi[t] = *reinterpret_cast<const bf16x8*>(&sB[3 + t][wf * 32 + row][kk + kh]);
       }
       // term pairs (i, j) with i + j <= 2, smallest first
       constexpr int PI[6] = {2, 1, 0, 1, 0, 0};
       constexpr int PJ[6] = {0, 1, 2, 0, 1, 0};
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
-        const int ti = PI[q], tj = PJ[q];
-        accr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ti], br[tj], accr, 0, 0, 0);
-        acci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ai[ti], br[tj], acci, 0, 0, 0);
-        accr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an[ti], bi[tj], accr, 0, 0, 0);
-        acci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ti], bi[tj], acci, 0, 0, 0);
+        const int ti_ = PI[q], tj = PJ[q];
+        accr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ti_], br[tj], accr, 0, 0, 0);
+        acci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ai[ti_], br[tj], acci, 0, 0, 0);
+        accr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an[ti_], bi[tj], accr, 0, 0, 0);
+        acci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ti_], bi[tj], acci, 0, 0, 0);
       }
     }
     __syncthreads();
   }
 
-  // ---- epilogue: lane holds rows 8q + 4(lane/32) + s (q, s < 4) of fibre column lane%32
+  // ---- epilogue: lane holds rows 8q + 4(lane/32) + s (q, s < 4) of fibre
+  // column lane%32; the output (and aux) use the output contraction stride
   const int64_t f = f0 + wf * 32 + (lane & 31);
   if (f < a.F) {
-    const int64_t base = fibre_base(f, a.R, a.n);
+    const int64_t base = fibre_base(f, a.R_out, a.n);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int m = pt * PT + wp * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
       if (m >= a.n) continue;
-      const int64_t off = base + a.R * (int64_t)m;
-      const cd y = {static_cast<double>(accr[r]), static_cast<double>(acci[r])};
+      const int64_t off = base + a.R_out * (int64_t)m;
       if (a.epi == EPI_NONE) {
-        store_c(a.out0, off, of64, y);
-      } else if (a.epi == EPI_FLOW) {
+        if (of64)
+          reinterpret_cast<double2*>(a.out0)[off] =
+              double2{static_cast<double>(accr[r]), static_cast<double>(acci[r])};
+        else
+          reinterpret_cast<float2*>(a.out0)[off] = float2{accr[r], acci[r]};
+        continue;
+      }
+      const cd y = {static_cast<double>(accr[r]), static_cast<double>(acci[r])};
+      if (a.epi == EPI_FLOW) {
         const cd z = half_flow(y, a.nl, flag);
         if (!finite2(z)) flag |= FLAG_NONFINITE;
         store_c(a.out0, off, of64, z);
@@ -270,6 +334,24 @@ __global__ __launch_bounds__(256) void k_pass_split(PassSplit a) {
   if (flag) atomicOr(a.flag, flag);
 }
 
+template <bool CONTIG, int PRO>
+void launch_pro(const PassSplit& a, dim3 grid, hipStream_t s) {
+  if (a.in_f64)
+    hipLaunchKernelGGL((k_pass_split<CONTIG, PRO, true>), grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_pass_split<CONTIG, PRO, false>), grid, dim3(256), 0, s, a);
+}
+
+template <bool CONTIG>
+void launch_contig(const PassSplit& a, dim3 grid, hipStream_t s) {
+  if (a.pro == PRO_FLOW)
+    launch_pro<CONTIG, PRO_FLOW>(a, grid, s);
+  else if (a.pro == PRO_G)
+    launch_pro<CONTIG, PRO_G>(a, grid, s);
+  else
+    launch_pro<CONTIG, PRO_NONE>(a, grid, s);
+}
+
 }  // namespace
 
 hipError_t launch_pass_split(const PassSplit& a, hipStream_t s) {
@@ -281,11 +363,13 @@ hipError_t launch_pass_split(const PassSplit& a, hipStream_t s) {
   const int64_t nF = (a.F + FT - 1) / FT;
   const int64_t G = nF * (a.Pp / PT);
   if (G > 0x7fffffffLL) return hipErrorInvalidValue;
-  const dim3 grid(static_cast<unsigned>(G)), block(256);
+  if (a.R_out < 1 || (a.pro != PRO_NONE && a.pro != PRO_FLOW && a.pro != PRO_G))
+    return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>(G));
   if (a.R == 1)
-    hipLaunchKernelGGL(k_pass_split<true>, grid, block, 0, s, a);
+    launch_contig<true>(a, grid, s);
   else
-    hipLaunchKernelGGL(k_pass_split<false>, grid, block, 0, s, a);
+    launch_contig<false>(a, grid, s);
   return hipGetLastError();
 }
 

@@ -93,4 +93,52 @@ __device__ __forceinline__ cd lawson_r2(cd HX, cd HY, const NlParams& p) {
   return caxpy(p.tau / 6.0, g_cgl(HX, p), HY);
 }
 
+// ---- single-precision versions (prologues of the split-precision passes,
+// whose inputs and outputs are complex64 stage tensors)
+struct cf {
+  float re, im;
+};
+
+__device__ __forceinline__ cf cfaxpy(float s, cf x, cf y) {  // y + s x
+  return {fmaf(s, x.re, y.re), fmaf(s, x.im, y.im)};
+}
+
+__device__ __forceinline__ cf g_cgl_f(cf u, const NlParams& p) {
+  const float r = u.re * u.re + u.im * u.im;
+  const float cr = (static_cast<float>(p.a3) + static_cast<float>(p.a4) * r) * r;
+  const float ci = (static_cast<float>(p.b3) + static_cast<float>(p.b4) * r) * r;
+  return {cr * u.re - ci * u.im, cr * u.im + ci * u.re};
+}
+
+__device__ __forceinline__ cf half_flow_f(cf u, const NlParams& p, unsigned& flag) {
+  const float t = static_cast<float>(0.5 * p.tau);
+  if (p.exact) {
+    const float r = u.re * u.re + u.im * u.im;
+    float mag = 1.0f, ang;
+    if (p.a3 == 0.0) {
+      ang = static_cast<float>(p.b3) * r * t;
+    } else {
+      const float s = -2.0f * static_cast<float>(p.a3) * r * t;
+      float L;
+      if (1.0f + s <= 0.0f) {
+        flag |= FLAG_BLOWUP;
+        L = logf(fabsf(1.0f + s));
+      } else {
+        L = log1pf(s);
+      }
+      mag = expf(-0.5f * L);
+      ang = static_cast<float>(-p.b3 / (2.0 * p.a3)) * L;
+    }
+    float sn, cs;
+    sincosf(ang, &sn, &cs);
+    return {mag * (u.re * cs - u.im * sn), mag * (u.re * sn + u.im * cs)};
+  }
+  const cf k1 = g_cgl_f(u, p);
+  const cf k2 = g_cgl_f(cfaxpy(0.5f * t, k1, u), p);
+  const cf k3 = g_cgl_f(cfaxpy(0.5f * t, k2, u), p);
+  const cf k4 = g_cgl_f(cfaxpy(t, k3, u), p);
+  const cf s = {k1.re + k4.re + 2.0f * (k2.re + k3.re), k1.im + k4.im + 2.0f * (k2.im + k3.im)};
+  return cfaxpy(t / 6.0f, s, u);
+}
+
 }  // namespace cgl

@@ -19,7 +19,7 @@
 namespace cgl {
 
 constexpr int SPK_P = 64;  // complex output rows per p-tile
-constexpr int SPK_K = 16;  // complex contraction indices per stage
+constexpr int SPK_K = 32;  // complex contraction indices per stage
 constexpr int SPK_Q = 6;   // planes per stage block
 
 // Builds the planes of M (3 bf16 terms of Re and Im of every entry); Pp, Kp

@@ -213,10 +213,13 @@ int main(int argc, char** argv) {
       kernel_parity({37}, prec, 1);
       kernel_parity({20, 9, 7}, prec, 3);
       kernel_parity({3, 5, 4}, prec, 4);
+      kernel_parity({32, 64, 3}, prec, 6);  // full tiles: unmasked fast path
     }
     steppers({12, 10, 6}, CGL_FP64, 0, cq, -15, 15, CGL_NEUMANN);
     steppers({9}, CGL_FP64, 0, cub, -10, 10, CGL_DIRICHLET);
     steppers({16, 12}, CGL_SPLIT_BF16, 0, cub, -10, 10, CGL_DIRICHLET);
+    steppers({32, 64}, CGL_SPLIT_BF16, 0, cub, -10, 10, CGL_DIRICHLET);
+    steppers({64, 32}, CGL_SPLIT_BF16, CGL_FLAG_FP64_MASTER, cub, -10, 10, CGL_DIRICHLET);
     steppers({7, 6, 5}, CGL_SPLIT_BF16, CGL_FLAG_FP64_MASTER, cq, -15, 15, CGL_NEUMANN);
     steppers({9}, CGL_SPLIT_BF16, CGL_FLAG_FP64_MASTER, cub, -10, 10, CGL_DIRICHLET);
   }
