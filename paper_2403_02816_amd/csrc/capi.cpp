@@ -8,11 +8,13 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <string>
 #include <new>
 #include <tuple>
 #include <vector>
 
 #include "../../include/cgl.h"
+#include "autotune.hpp"
 #include "host_numerics.hpp"
 #include "kernels.hpp"
 #include "split_layout.hpp"
@@ -23,9 +25,11 @@ namespace {
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// One exponential on the device: the FP64 embedding (slot 0), or the bf16
+// term planes in the layout of every split tile shape (slot = tile index).
 struct DeviceOp {
-  void* ptr = nullptr;  // FP64 embedding (double) or bf16 term planes (uint16_t)
-  int Pp = 0, Kp = 0;
+  void* ptr[SPLIT_NTILES] = {};
+  int Pp[SPLIT_NTILES] = {}, Kp[SPLIT_NTILES] = {};
 };
 
 struct GraphKey {
@@ -53,6 +57,7 @@ struct cgl_plan_s {
   bool have_ops[3] = {false, false, false};
   CMat E[3], H[3];
   DeviceOp dE[3], dH[3];
+  int tile[3] = {-1, -1, -1};  // split tile shape per direction (autotuned)
   void* stage[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   unsigned* dflag = nullptr;
   unsigned* hflag = nullptr;  // pinned
@@ -81,8 +86,18 @@ size_t user_bytes(const cgl_plan_s* p) {
 }
 
 void free_op(DeviceOp& o) {
-  if (o.ptr) (void)hipFree(o.ptr);
-  o.ptr = nullptr;
+  for (auto& q : o.ptr) {
+    if (q) (void)hipFree(q);
+    q = nullptr;
+  }
+}
+
+int upload_bytes(cgl_plan_s* p, const void* h, size_t bytes, void** dst) {
+  if (hipMalloc(dst, bytes) != hipSuccess) return CGL_ENOMEM;
+  if (hipMemcpyAsync(*dst, h, bytes, hipMemcpyHostToDevice, p->ustream) != hipSuccess)
+    return CGL_EDEVICE;
+  if (hipStreamSynchronize(p->ustream) != hipSuccess) return CGL_EDEVICE;
+  return CGL_OK;
 }
 
 // Upload one exponential in the plan's device form.
@@ -110,30 +125,19 @@ int upload_op(cgl_plan_s* p, const CMat& M, DeviceOp& dst) {
         h[(2 * k + 1) * Pp + prow(m, 0)] = -im;
         h[(2 * k + 1) * Pp + prow(m, 1)] = re;
       }
-    if (hipMalloc(&dst.ptr, h.size() * sizeof(double)) != hipSuccess) return CGL_ENOMEM;
-    if (hipMemcpyAsync(dst.ptr, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice,
-                       p->ustream) != hipSuccess)
-      return CGL_EDEVICE;
-    if (hipStreamSynchronize(p->ustream) != hipSuccess) return CGL_EDEVICE;
-    dst.Pp = Pp;
-    dst.Kp = Kp;
-    return CGL_OK;
+    dst.Pp[0] = Pp;
+    dst.Kp[0] = Kp;
+    return upload_bytes(p, h.data(), h.size() * sizeof(double), &dst.ptr[0]);
   }
-  std::vector<uint16_t> h;
-  int Pp = 0, Kp = 0;
-  build_split_operator(M, h, Pp, Kp);
-  if (hipMalloc(&dst.ptr, h.size() * sizeof(uint16_t)) != hipSuccess) return CGL_ENOMEM;
-  if (hipMemcpyAsync(dst.ptr, h.data(), h.size() * sizeof(uint16_t), hipMemcpyHostToDevice,
-                     p->ustream) != hipSuccess)
-    return CGL_EDEVICE;
-  if (hipStreamSynchronize(p->ustream) != hipSuccess) return CGL_EDEVICE;
-  dst.Pp = Pp;
-  dst.Kp = Kp;
+  for (int t = 0; t < SPLIT_NTILES; ++t) {
+    std::vector<uint16_t> h;
+    build_split_operator(M, SPLIT_TILES[t].PT, SPLIT_TILES[t].KS, h, dst.Pp[t], dst.Kp[t]);
+    const int st = upload_bytes(p, h.data(), h.size() * sizeof(uint16_t), &dst.ptr[t]);
+    if (st != CGL_OK) return st;
+  }
   return CGL_OK;
 }
 
-// One mu-mode pass: out0 (, out1) = epilogue(in0 x_mu M, aux), with the
-// prologue applied to in0 as it is staged.
 // rotated: the input's contraction axis is its fastest one and the output is
 // written with that axis moved to the slowest position (split form only).
 int pass(cgl_plan_s* p, int mu, int which, const void* in0, const void* aux, void* out0,
@@ -150,12 +154,12 @@ int pass(cgl_plan_s* p, int mu, int which, const void* in0, const void* aux, voi
     a.aux = static_cast<const double*>(aux);
     a.out0 = static_cast<double*>(out0);
     a.out1 = static_cast<double*>(out1);
-    a.op = static_cast<const double*>(op.ptr);
+    a.op = static_cast<const double*>(op.ptr[0]);
     a.R = R;
     a.F = p->N / n;
     a.n = n;
-    a.Pp = op.Pp;
-    a.Kp = op.Kp;
+    a.Pp = op.Pp[0];
+    a.Kp = op.Kp[0];
     a.pro = pro;
     a.epi = epi;
     a.nl = p->nl;
@@ -167,13 +171,15 @@ int pass(cgl_plan_s* p, int mu, int which, const void* in0, const void* aux, voi
     a.aux = aux;
     a.out0 = out0;
     a.out1 = out1;
-    a.op = static_cast<const uint16_t*>(op.ptr);
+    const int t = p->tile[mu] >= 0 ? p->tile[mu] : 0;
+    a.op = static_cast<const uint16_t*>(op.ptr[t]);
+    a.tile = t;
     a.R = rotated ? 1 : R;
     a.R_out = rotated ? p->N / n : R;
     a.F = p->N / n;
     a.n = n;
-    a.Pp = op.Pp;
-    a.Kp = op.Kp;
+    a.Pp = op.Pp[t];
+    a.Kp = op.Kp[t];
     a.pro = pro;
     a.epi = epi;
     a.in_f64 = in_f64 ? 1 : 0;
@@ -217,6 +223,37 @@ int action(cgl_plan_s* p, int which, const void* in0, const void* aux, void* out
   return CGL_OK;
 }
 
+// Picks the split tile shape of every direction by timing one pass of each
+// candidate on the plan's stream (stage buffers as scratch).  Runs outside
+// any graph capture; a no-op for FP64 plans and directions already tuned.
+int ensure_tuned(cgl_plan_s* p) {
+  if (p->precision != CGL_SPLIT_BF16) return CGL_OK;
+  // CGL_SPLIT_TILE=<index> fixes the tile shape (tests of every shape, tuning studies)
+  const char* forced = std::getenv("CGL_SPLIT_TILE");
+  for (int mu = 0; mu < p->d; ++mu) {
+    if (p->tile[mu] >= 0) continue;
+    if (forced) {
+      const int t = std::atoi(forced);
+      if (t < 0 || t >= SPLIT_NTILES) return CGL_EINVAL;
+      p->tile[mu] = t;
+      continue;
+    }
+    const int64_t n = p->n[mu];
+    const std::string key = device_tag() + ":split:n" + std::to_string(n) + ":F" +
+                            std::to_string(p->N / n);
+    const int saved = p->tile[mu];
+    auto launch = [&](int t) -> hipError_t {
+      p->tile[mu] = t;
+      const int st = pass(p, mu, CGL_H, p->stage[0], nullptr, p->stage[1], nullptr, PRO_NONE,
+                          EPI_NONE, false, false, true, p->ustream);
+      p->tile[mu] = saved;
+      return st == CGL_OK ? hipSuccess : hipErrorInvalidValue;
+    };
+    p->tile[mu] = autotune_pick(key, SPLIT_NTILES, launch, p->ustream, 8);
+  }
+  return CGL_OK;
+}
+
 int enqueue_strang(cgl_plan_s* p, void* u, hipStream_t s) {
   const bool m = master(p);
   return action(p, CGL_E, u, nullptr, u, nullptr, PRO_FLOW, EPI_FLOW, m, m, s);
@@ -241,7 +278,7 @@ int enqueue_lawson4(cgl_plan_s* p, void* u, hipStream_t s) {
 int check_u(cgl_plan_s* p, void* u) {
   if (!p || !u) return CGL_EINVAL;
   if (!ready(p)) return CGL_ENOTREADY;
-  return CGL_OK;
+  return ensure_tuned(p);
 }
 
 }  // namespace
@@ -329,6 +366,10 @@ int cgl_plan(cgl_plan_t* out, int d, const int64_t* n, const cgl_coeffs* c, doub
     st = CGL_ENOMEM;
   if (st == CGL_OK && hipMemsetAsync(p->dflag, 0, 256, p->ustream) != hipSuccess)
     st = CGL_EDEVICE;
+  for (int i = 0; i < 5 && st == CGL_OK; ++i)
+    if (hipMemsetAsync(p->stage[i], 0, std::max(stage_bytes(p), user_bytes(p)), p->ustream) !=
+        hipSuccess)
+      st = CGL_EDEVICE;
   if (st == CGL_OK && hipStreamSynchronize(p->ustream) != hipSuccess) st = CGL_EDEVICE;
   if (st != CGL_OK) {
     cgl_destroy(p);
@@ -386,7 +427,9 @@ int cgl_split_terms(cgl_plan_t p, int* op_terms, int* state_terms) {
 int cgl_mode_product(cgl_plan_t p, int mu, int which, const void* in_dev, void* out_dev) {
   if (!p || !in_dev || !out_dev || mu < 0 || mu >= p->d || in_dev == out_dev) return CGL_EINVAL;
   if (which != CGL_E && which != CGL_H) return CGL_EINVAL;
-  if (!p->have_ops[mu]) return CGL_ENOTREADY;
+  if (!ready(p)) return CGL_ENOTREADY;
+  const int st = ensure_tuned(p);
+  if (st != CGL_OK) return st;
   return pass(p, mu, which, in_dev, nullptr, out_dev, nullptr, PRO_NONE, EPI_NONE, false, false,
               false, p->ustream);
 }
@@ -394,6 +437,8 @@ int cgl_mode_product(cgl_plan_t p, int mu, int which, const void* in_dev, void* 
 int cgl_tucker(cgl_plan_t p, int which, const void* in_dev, void* out_dev) {
   if (!p || !in_dev || !out_dev || (which != CGL_E && which != CGL_H)) return CGL_EINVAL;
   if (!ready(p)) return CGL_ENOTREADY;
+  const int st = ensure_tuned(p);
+  if (st != CGL_OK) return st;
   return action(p, which, in_dev, nullptr, out_dev, nullptr, PRO_NONE, EPI_NONE, false, false,
                 p->ustream);
 }

@@ -92,6 +92,7 @@ struct PassSplit {
   int epi;
   int in_f64;   // in0 is complex128 (master state) instead of complex64
   int out_f64;  // out0/out1 are complex128
+  int tile;     // index into SPLIT_TILES (the operator planes must match it)
   NlParams nl;
   unsigned* flag;
 };

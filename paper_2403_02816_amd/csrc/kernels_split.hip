@@ -13,13 +13,15 @@
 // into LDS.  The state arrives as complex64, or complex128 when the plan
 // keeps an FP64 master state.
 //
-// Tiling: a workgroup (4 waves) owns 64 complex output rows x 64 fibres; each
-// wave owns one 32 x 32 block (one FP32 accumulator for the real part, one for
-// the imaginary part).  A stage covers 32 complex contraction indices: 6
-// operator planes (64 rows x 32) and 6 state planes (64 fibres x 32), rows
-// padded to 80 bytes so the 16-byte MFMA operand reads of 16 lanes hit
-// distinct LDS banks.  The next stage's global loads are issued into registers
-// before the current stage's MFMAs, so their latency overlaps the math.
+// Tiling: a workgroup (4 waves, 2 x 2) owns PT complex output rows x 64
+// fibres; each wave owns PT/64 blocks of 32 x 32 (one FP32 accumulator for the
+// real part, one for the imaginary part, per block).  A stage covers KS
+// complex contraction indices: 6 operator planes (PT rows x KS) and 6 state
+// planes (64 fibres x KS), rows padded by 16 bytes so the 16-byte MFMA operand
+// reads of 16 lanes hit distinct LDS banks.  Two shapes are compiled,
+// (PT, KS) = (64, 32) and (128, 16); the plan's autotuner picks one per
+// direction.  The next stage's global loads are issued into registers before
+// the current stage's MFMAs, so their latency overlaps the math.
 #include "kernels.hpp"
 #include "pointwise.hpp"
 #include "split_layout.hpp"
@@ -36,11 +38,7 @@ typedef float f32x4u __attribute__((ext_vector_type(4), aligned(8)));
 
 namespace {
 
-constexpr int PT = SPK_P;   // 64 complex rows
-constexpr int FT = SP_FT;   // 64 fibres
-constexpr int KS = SPK_K;   // 32 complex contraction indices per stage
-constexpr int PITCH = 40;   // LDS row pitch in bf16 (80 bytes)
-constexpr int OPCH = 6 * PT * KS / 8 / 256;  // 16-byte operator chunks per thread per stage
+constexpr int FT = SP_FT;  // 64 fibres
 
 __device__ __forceinline__ int64_t fibre_base(int64_t f, int64_t R, int n) {
   return (R == 1) ? f * (int64_t)n : (f % R) + (f / R) * R * (int64_t)n;
@@ -108,19 +106,36 @@ __device__ __forceinline__ bf16x8 neg8(bf16x8 v) {
 }
 
 // Staging geometry of one thread: FI fibres x KJ consecutive contraction
-// indices.  Contiguous contraction axis: 1 fibre x 8 indices (4 threads cover
-// the 32 indices of a fibre with 64-byte loads); strided: 2 adjacent fibres x
-// 4 indices (32 threads cover 64 adjacent fibres of one index, 16-byte loads).
-template <bool CONTIG>
+// indices.  Contiguous contraction axis: 1 fibre x KS/4 indices (4 threads
+// cover the KS indices of a fibre); strided: 2 adjacent fibres x KS/8 indices
+// (32 threads cover 64 adjacent fibres of one index with 16-byte loads).
+template <int KS, bool CONTIG>
 struct Stage {
   static constexpr int FI = CONTIG ? 1 : 2;
-  static constexpr int KJ = CONTIG ? 8 : 4;
+  static constexpr int KJ = CONTIG ? KS / 4 : KS / 8;
 };
 
-template <bool CONTIG, int PRO, bool IN64>
+// stores the packed bf16 terms of KJ consecutive indices (KJ/2 u32)
+template <int KJ>
+__device__ __forceinline__ void store_terms(unsigned short* dst, const unsigned* v) {
+  if constexpr (KJ == 8) {
+    *reinterpret_cast<u32x4*>(dst) = u32x4{v[0], v[1], v[2], v[3]};
+  } else if constexpr (KJ == 4) {
+    *reinterpret_cast<u32x2*>(dst) = u32x2{v[0], v[1]};
+  } else {
+    *reinterpret_cast<unsigned*>(dst) = v[0];
+  }
+}
+
+template <int PT, int KS, bool CONTIG, int PRO, bool IN64>
 __global__ __launch_bounds__(256, 2) void k_pass_split(PassSplit a) {
-  constexpr int FI = Stage<CONTIG>::FI;
-  constexpr int KJ = Stage<CONTIG>::KJ;
+  constexpr int FI = Stage<KS, CONTIG>::FI;
+  constexpr int KJ = Stage<KS, CONTIG>::KJ;
+  constexpr int PB = PT / 64;          // 32-row blocks per wave
+  constexpr int PITCH = KS + 8;        // LDS row pitch in bf16
+  constexpr int CPS = PT * KS / 8;     // 16-byte chunks per plane per stage
+  constexpr int OPCH = 6 * CPS / 256;  // operator chunks per thread per stage
+  static_assert(OPCH * 256 == 6 * CPS, "operator stage must split evenly");
   __shared__ __attribute__((aligned(16))) unsigned short sA[6][PT][PITCH];
   __shared__ __attribute__((aligned(16))) unsigned short sB[6][FT][PITCH];
 
@@ -145,11 +160,11 @@ __global__ __launch_bounds__(256, 2) void k_pass_split(PassSplit a) {
   int k0t;
   if (CONTIG) {
     fl[0] = tid >> 2;
-    k0t = 8 * (tid & 3);
+    k0t = KJ * (tid & 3);
   } else {
     fl[0] = 2 * (tid & 31);
     fl[FI - 1] = fl[0] + 1;
-    k0t = 4 * (tid >> 5);
+    k0t = KJ * (tid >> 5);
   }
   int64_t gb[FI];
 #pragma unroll
@@ -166,7 +181,7 @@ __global__ __launch_bounds__(256, 2) void k_pass_split(PassSplit a) {
   cf vin[FI][KJ];   // prefetched state values
 
   auto load_stage = [&](int ks) {
-    const u32x4* src = opblk + static_cast<size_t>(ks) * (6 * PT * KS / 8);
+    const u32x4* src = opblk + static_cast<size_t>(ks) * (6 * CPS);
 #pragma unroll
     for (int j = 0; j < OPCH; ++j) opr[j] = src[tid + 256 * j];
     if (CONTIG && full) {
@@ -213,12 +228,14 @@ __global__ __launch_bounds__(256, 2) void k_pass_split(PassSplit a) {
     }
   };
 
-  f32x16 accr, acci;
+  f32x16 accr[PB], acci[PB];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    accr[r] = 0.0f;
-    acci[r] = 0.0f;
-  }
+  for (int b = 0; b < PB; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      accr[b][r] = 0.0f;
+      acci[b][r] = 0.0f;
+    }
   unsigned flag = 0;
   const int row = lane & 31;
   const int kh = (lane >> 5) * 8;
@@ -230,7 +247,7 @@ __global__ __launch_bounds__(256, 2) void k_pass_split(PassSplit a) {
 #pragma unroll
     for (int j = 0; j < OPCH; ++j) {
       const int c = tid + 256 * j;
-      *reinterpret_cast<u32x4*>(&sA[c >> 8][(c >> 2) & 63][8 * (c & 3)]) = opr[j];
+      *reinterpret_cast<u32x4*>(&sA[c / CPS][(c / (KS / 8)) % PT][8 * (c % (KS / 8))]) = opr[j];
     }
 #pragma unroll
     for (int i = 0; i < FI; ++i) {
@@ -254,79 +271,84 @@ __global__ __launch_bounds__(256, 2) void k_pass_split(PassSplit a) {
       }
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
-        if (KJ == 8) {
-          *reinterpret_cast<u32x4*>(&sB[t][fl[i]][k0t]) = u32x4{tr[t][0], tr[t][1], tr[t][2], tr[t][3]};
-          *reinterpret_cast<u32x4*>(&sB[3 + t][fl[i]][k0t]) =
-              u32x4{ti[t][0], ti[t][1], ti[t][2], ti[t][3]};
-        } else {
-          *reinterpret_cast<u32x2*>(&sB[t][fl[i]][k0t]) = u32x2{tr[t][0], tr[t][1]};
-          *reinterpret_cast<u32x2*>(&sB[3 + t][fl[i]][k0t]) = u32x2{ti[t][0], ti[t][1]};
-        }
+        store_terms<KJ>(&sB[t][fl[i]][k0t], tr[t]);
+        store_terms<KJ>(&sB[3 + t][fl[i]][k0t], ti[t]);
       }
     }
     __syncthreads();
     if (ks + 1 < nKS) load_stage(ks + 1);
-    // ---- MFMA: two 16-deep steps, 6 term products x 4 real products each
+    // ---- MFMA: 16-deep steps, 6 term products x 4 real products per block
 #pragma unroll
     for (int kk = 0; kk < KS; kk += 16) {
-      bf16x8 ar[3], ai[3], an[3], br[3], bi[3];
+      bf16x8 br[3], bi[3];
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
-        ar[t] = *reinterpret_cast<const bf16x8*>(&sA[t][wp * 32 + row][kk + kh]);
-        ai[t] = *reinterpret_cast<const bf16x8*>(&sA[3 + t][wp * 32 + row][kk + kh]);
-        an[t] = neg8(ai[t]);
         br[t] = *reinterpret_cast<const bf16x8*>(&sB[t][wf * 32 + row][kk + kh]);
         bi[t] = *reinterpret_cast<const bf16x8*>(&sB[3 + t][wf * 32 + row][kk + kh]);
       }
-      // term pairs (i, j) with i + j <= 2, smallest first
-      constexpr int PI[6] = {2, 1, 0, 1, 0, 0};
-      constexpr int PJ[6] = {0, 1, 2, 0, 1, 0};
 #pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        const int ti_ = PI[q], tj = PJ[q];
-        accr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ti_], br[tj], accr, 0, 0, 0);
-        acci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ai[ti_], br[tj], acci, 0, 0, 0);
-        accr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an[ti_], bi[tj], accr, 0, 0, 0);
-        acci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ti_], bi[tj], acci, 0, 0, 0);
+      for (int b = 0; b < PB; ++b) {
+        bf16x8 ar[3], ai[3], an[3];
+        const int prow = wp * (PT / 2) + b * 32 + row;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          ar[t] = *reinterpret_cast<const bf16x8*>(&sA[t][prow][kk + kh]);
+          ai[t] = *reinterpret_cast<const bf16x8*>(&sA[3 + t][prow][kk + kh]);
+          an[t] = neg8(ai[t]);
+        }
+        // term pairs (i, j) with i + j <= 2, smallest first
+        constexpr int PI[6] = {2, 1, 0, 1, 0, 0};
+        constexpr int PJ[6] = {0, 1, 2, 0, 1, 0};
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          const int ti_ = PI[q], tj = PJ[q];
+          accr[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ti_], br[tj], accr[b], 0, 0, 0);
+          acci[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ai[ti_], br[tj], acci[b], 0, 0, 0);
+          accr[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an[ti_], bi[tj], accr[b], 0, 0, 0);
+          acci[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ti_], bi[tj], acci[b], 0, 0, 0);
+        }
       }
     }
     __syncthreads();
   }
 
-  // ---- epilogue: lane holds rows 8q + 4(lane/32) + s (q, s < 4) of fibre
-  // column lane%32; the output (and aux) use the output contraction stride
+  // ---- epilogue: in each block, lane holds rows 8q + 4(lane/32) + s (q, s < 4)
+  // of fibre column lane%32; the output (and aux) use the output stride
   const int64_t f = f0 + wf * 32 + (lane & 31);
   if (f < a.F) {
     const int64_t base = fibre_base(f, a.R_out, a.n);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int m = pt * PT + wp * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      if (m >= a.n) continue;
-      const int64_t off = base + a.R_out * (int64_t)m;
-      if (a.epi == EPI_NONE) {
-        if (of64)
-          reinterpret_cast<double2*>(a.out0)[off] =
-              double2{static_cast<double>(accr[r]), static_cast<double>(acci[r])};
-        else
-          reinterpret_cast<float2*>(a.out0)[off] = float2{accr[r], acci[r]};
-        continue;
-      }
-      const cd y = {static_cast<double>(accr[r]), static_cast<double>(acci[r])};
-      if (a.epi == EPI_FLOW) {
-        const cd z = half_flow(y, a.nl, flag);
-        if (!finite2(z)) flag |= FLAG_NONFINITE;
-        store_c(a.out0, off, of64, z);
-      } else {
-        const cd x = load_c(a.aux, off, false);
-        if (a.epi == EPI_L4_R1) {  // y = Q, x = P
-          cd X, Y;
-          lawson_r1(x, y, a.nl, X, Y);
-          store_c(a.out0, off, of64, X);
-          store_c(a.out1, off, of64, Y);
-        } else {  // EPI_L4_R2: y = H Y, x = H X
-          const cd z = lawson_r2(x, y, a.nl);
+    for (int b = 0; b < PB; ++b) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = pt * PT + wp * (PT / 2) + b * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (m >= a.n) continue;
+        const int64_t off = base + a.R_out * (int64_t)m;
+        if (a.epi == EPI_NONE) {
+          if (of64)
+            reinterpret_cast<double2*>(a.out0)[off] =
+                double2{static_cast<double>(accr[b][r]), static_cast<double>(acci[b][r])};
+          else
+            reinterpret_cast<float2*>(a.out0)[off] = float2{accr[b][r], acci[b][r]};
+          continue;
+        }
+        const cd y = {static_cast<double>(accr[b][r]), static_cast<double>(acci[b][r])};
+        if (a.epi == EPI_FLOW) {
+          const cd z = half_flow(y, a.nl, flag);
           if (!finite2(z)) flag |= FLAG_NONFINITE;
           store_c(a.out0, off, of64, z);
+        } else {
+          const cd x = load_c(a.aux, off, false);
+          if (a.epi == EPI_L4_R1) {  // y = Q, x = P
+            cd X, Y;
+            lawson_r1(x, y, a.nl, X, Y);
+            store_c(a.out0, off, of64, X);
+            store_c(a.out1, off, of64, Y);
+          } else {  // EPI_L4_R2: y = H Y, x = H X
+            const cd z = lawson_r2(x, y, a.nl);
+            if (!finite2(z)) flag |= FLAG_NONFINITE;
+            store_c(a.out0, off, of64, z);
+          }
         }
       }
     }
@@ -334,42 +356,52 @@ __global__ __launch_bounds__(256, 2) void k_pass_split(PassSplit a) {
   if (flag) atomicOr(a.flag, flag);
 }
 
-template <bool CONTIG, int PRO>
+template <int PT, int KS, bool CONTIG, int PRO>
 void launch_pro(const PassSplit& a, dim3 grid, hipStream_t s) {
   if (a.in_f64)
-    hipLaunchKernelGGL((k_pass_split<CONTIG, PRO, true>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_pass_split<PT, KS, CONTIG, PRO, true>), grid, dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((k_pass_split<CONTIG, PRO, false>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_pass_split<PT, KS, CONTIG, PRO, false>), grid, dim3(256), 0, s, a);
 }
 
-template <bool CONTIG>
+template <int PT, int KS, bool CONTIG>
 void launch_contig(const PassSplit& a, dim3 grid, hipStream_t s) {
   if (a.pro == PRO_FLOW)
-    launch_pro<CONTIG, PRO_FLOW>(a, grid, s);
+    launch_pro<PT, KS, CONTIG, PRO_FLOW>(a, grid, s);
   else if (a.pro == PRO_G)
-    launch_pro<CONTIG, PRO_G>(a, grid, s);
+    launch_pro<PT, KS, CONTIG, PRO_G>(a, grid, s);
   else
-    launch_pro<CONTIG, PRO_NONE>(a, grid, s);
+    launch_pro<PT, KS, CONTIG, PRO_NONE>(a, grid, s);
+}
+
+template <int PT, int KS>
+void launch_tile(const PassSplit& a, dim3 grid, hipStream_t s) {
+  if (a.R == 1)
+    launch_contig<PT, KS, true>(a, grid, s);
+  else
+    launch_contig<PT, KS, false>(a, grid, s);
 }
 
 }  // namespace
 
 hipError_t launch_pass_split(const PassSplit& a, hipStream_t s) {
+  if (a.tile < 0 || a.tile >= SPLIT_NTILES) return hipErrorInvalidValue;
+  const int PT = SPLIT_TILES[a.tile].PT, KS = SPLIT_TILES[a.tile].KS;
   if (a.Pp % PT != 0 || a.Kp % KS != 0 || a.Kp < a.n || a.Pp < a.n || a.F <= 0)
     return hipErrorInvalidValue;
   if (!a.in0 || !a.out0 || !a.op || !a.flag) return hipErrorInvalidValue;
   if ((a.epi == EPI_L4_R1 || a.epi == EPI_L4_R2) && !a.aux) return hipErrorInvalidValue;
   if (a.epi == EPI_L4_R1 && !a.out1) return hipErrorInvalidValue;
+  if (a.R_out < 1 || (a.pro != PRO_NONE && a.pro != PRO_FLOW && a.pro != PRO_G))
+    return hipErrorInvalidValue;
   const int64_t nF = (a.F + FT - 1) / FT;
   const int64_t G = nF * (a.Pp / PT);
   if (G > 0x7fffffffLL) return hipErrorInvalidValue;
-  if (a.R_out < 1 || (a.pro != PRO_NONE && a.pro != PRO_FLOW && a.pro != PRO_G))
-    return hipErrorInvalidValue;
   const dim3 grid(static_cast<unsigned>(G));
-  if (a.R == 1)
-    launch_contig<true>(a, grid, s);
+  if (a.tile == 0)
+    launch_tile<64, 32>(a, grid, s);
   else
-    launch_contig<false>(a, grid, s);
+    launch_tile<128, 16>(a, grid, s);
   return hipGetLastError();
 }
 

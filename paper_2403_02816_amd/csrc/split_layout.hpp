@@ -18,12 +18,18 @@
 
 namespace cgl {
 
-constexpr int SPK_P = 64;  // complex output rows per p-tile
-constexpr int SPK_K = 32;  // complex contraction indices per stage
-constexpr int SPK_Q = 6;   // planes per stage block
+constexpr int SPK_Q = 6;  // planes per stage block
 
-// Builds the planes of M (3 bf16 terms of Re and Im of every entry); Pp, Kp
-// receive the padded row / contraction counts.
-void build_split_operator(const CMat& M, std::vector<uint16_t>& out, int& Pp, int& Kp);
+// Tile shapes of the split kernel: (rows per workgroup, stage depth).
+struct SplitTile {
+  int PT, KS;
+};
+constexpr SplitTile SPLIT_TILES[2] = {{64, 32}, {128, 16}};
+constexpr int SPLIT_NTILES = 2;
+
+// Builds the planes of M (3 bf16 terms of Re and Im of every entry) for tile
+// shape (PT, KS); Pp, Kp receive the padded row / contraction counts.
+void build_split_operator(const CMat& M, int PT, int KS, std::vector<uint16_t>& out, int& Pp,
+                          int& Kp);
 
 }  // namespace cgl

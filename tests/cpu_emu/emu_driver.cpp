@@ -206,6 +206,11 @@ int main(int argc, char** argv) {
     steppers({12, 10, 14}, CGL_SPLIT_BF16, 0, cq, -15, 15, CGL_NEUMANN);
     steppers({12, 10, 14}, CGL_SPLIT_BF16, CGL_FLAG_FP64_MASTER, cq, -15, 15, CGL_NEUMANN);
     steppers({37}, CGL_SPLIT_BF16, CGL_FLAG_FP64_MASTER, cub, -10, 10, CGL_DIRICHLET);
+  } else if (argc > 1 && std::string(argv[1]) == "split") {
+    kernel_parity({20, 9, 7}, CGL_SPLIT_BF16, 3);
+    kernel_parity({32, 64, 3}, CGL_SPLIT_BF16, 6);
+    steppers({32, 64}, CGL_SPLIT_BF16, 0, cub, -10, 10, CGL_DIRICHLET);
+    steppers({7, 6, 5}, CGL_SPLIT_BF16, CGL_FLAG_FP64_MASTER, cq, -15, 15, CGL_NEUMANN);
   } else {
     // quick: every kernel variant (mu = 1 contiguous, mu > 1 strided, ragged
     // tiles, both precisions) and every stepper path, on small grids

@@ -130,3 +130,26 @@ def test_split_graph_replay_equals_eager_bitwise():
     torch.cuda.synchronize()
     assert torch.equal(a, b)
     plan.destroy()
+
+
+@pytest.mark.parametrize("tile", ["0", "1"])
+def test_split_every_tile_shape(tile, monkeypatch):
+    """Both compiled tile shapes (64 rows x 32-deep stages, 128 rows x 16-deep
+    stages), forced instead of autotuned: kernel parity on a ragged shape and
+    the one-step gate on full tiles."""
+    monkeypatch.setenv("CGL_SPLIT_TILE", tile)
+    torch = require_gpu()
+    p, Es, Hs = _random_plan((130, 70, 9), 500)
+    U = _c64(ci.random_complex((130, 70, 9), 19))
+    x = p.to_device(U, dtype=torch.complex64)
+    out = torch.empty_like(x)
+    for mu in range(3):
+        p.mode_product(mu, 1, x, out)
+        torch.cuda.synchronize()
+        assert rel_l2(p.to_host(out), tensor.mode_product(U, Hs[mu], mu)) < 1e-6
+    p.tucker(0, x, out)
+    torch.cuda.synchronize()
+    assert rel_l2(p.to_host(out), tensor.tucker(U, Es)) < 1e-6
+    p.destroy()
+    for method in ("strang", "lawson4"):
+        assert _one_step_gate(ci.scaled(ci.C2, (64, 32, 48)), method) < 1e-6
