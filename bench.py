@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c1", choices=["c1", "c2_strang", "c2_lawson4"])
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2_strang", "c2_lawson4", "c3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
@@ -133,6 +133,128 @@ def cpu_baseline(p, method, nsteps):
                       f"(numpy FP64, literal scheme), after 1 warm-up step; {dt:.2f} s"}
 
 
+def bench_batched(args):
+    """512 independent 2-D cubic instances (n1, n2 in {64,...,192}), Lawson4,
+    tau = 1e-2, split form, one persistent launch per mu-mode pass."""
+    import torch
+    import cgl_inputs as ci
+    from oracle import metrics
+    from paper_2403_02816_amd import cgl
+    probs = ci.batched_sweep()
+    K, W = args.steps, args.warmup
+    t_setup = time.perf_counter()
+    bp = cgl.BatchedPlan([p.n for p in probs], [p.coeffs for p in probs], ci.C3_TAU,
+                         precision="split")
+    bp.set_fd_operators_batched(probs)
+    t_setup = time.perf_counter() - t_setup
+    u0 = [ci.initial_state(p) for p in probs]
+    u = bp.to_device_batched(u0)
+    if W > 0:
+        assert bp.run("lawson4", u, W, W) == 0
+    assert bp.run("lawson4", u, K, K) == 0  # captures the timed chunk's graph
+    u.copy_(bp.to_device_batched(u0))
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    assert bp.run("lawson4", u, K, K) == 0
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    Ntot = sum(p.N for p in probs)
+    launches = 4 * 2
+    launch_ms = ms / (K * launches)
+    mfma = sum(6.0 * 8.0 * p.N * (p.n[0] + p.n[1]) for p in probs) * 4 / launches
+    achieved = mfma / (launch_ms * 1e-3) / 1e12
+    # one-step gate on a sample of instances, oracle on their exponentials
+    from oracle import steppers
+    sample = list(range(0, len(probs), 64))
+    ug = bp.to_device_batched([ci.initial_state(p).astype(np.complex64) for p in probs])
+    bp.step_lawson4(ug, 1)
+    torch.cuda.synchronize()
+    outs = bp.to_host_batched(ug)
+    gate = 0.0
+    for j in sample:
+        p = probs[j]
+        H = [bp.get_instance_operator(j, mu, 1) for mu in range(2)]
+        E = [h @ h for h in H]
+        nl = steppers.CGLNonlinearity(p.coeffs.as_tuple())
+        ref = steppers.lawson4_step(ci.initial_state(p).astype(np.complex64).astype(np.complex128),
+                                    E, H, p.tau, nl)
+        gate = max(gate, metrics.rel_l2(outs[j], ref))
+    split_state = u.clone()
+    bp.destroy()
+    fp64 = None
+    traj = None
+    if not args.no_fp64:
+        b64 = cgl.BatchedPlan([p.n for p in probs], [p.coeffs for p in probs], ci.C3_TAU,
+                              precision="fp64")
+        b64.set_fd_operators_batched(probs)
+        v = b64.to_device_batched(u0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b64.step_lawson4(v, K)
+        torch.cuda.synchronize()
+        s64 = time.perf_counter() - t0
+        fp64 = {"value": Ntot * K / s64, "ms_per_step": 1e3 * s64 / K,
+                "note": "FP64 form, one launch per instance and pass (eager)"}
+        a = bp_split = split_state.to(torch.complex128)
+        traj = max(float(torch.linalg.vector_norm(a[o:o + p.N] - v[o:o + p.N]).item()
+                         / torch.linalg.vector_norm(v[o:o + p.N]).item())
+                   for p, o in zip(probs, b64.offsets))
+        b64.destroy()
+    cpu = None
+    if not args.no_cpu_baseline:
+        sub = probs[:8]
+        cpu = cpu_baseline_batched(sub, 2)
+    rec = {
+        "metric": "grid-point-steps/s at rel-L2 <=1e-6 vs FP64 oracle; MFMA util % of peak",
+        "value": Ntot * K / (ms * 1e-3), "unit": "grid-point-steps/s", "n_gpus": 1,
+        "steps": K, "warmup": W, "ms_per_step": ms / K, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3->f32 (split), state c64",
+        "data": "synthetic",
+        "config": {"workload": f"batched sweep: {len(probs)} 2-D cubic CGL instances, n1,n2 in "
+                               f"{list(ci.C3_SIZES)}, Lawson4, tau={ci.C3_TAU}, split form, "
+                               f"{Ntot} grid points", "instances": len(probs),
+                   "grid_points": Ntot, "method": "lawson4", "parallelism": "single-gpu"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": MI355X_PEAK_BF16_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / MI355X_PEAK_BF16_TFLOPS,
+                     "traffic": None, "kernel": "k_pass_split_batched (persistent)",
+                     "launch_ms": launch_ms},
+        "accuracy": {"one_step_rel_l2_vs_fp64_oracle_max_sampled": gate, "gate": 1e-6,
+                     "sampled_instances": len(sample),
+                     "trajectory_rel_l2_vs_fp64_form_max": traj, "trajectory_steps": K},
+        "fp64_form": fp64, "cpu_baseline": cpu, "setup_s": t_setup,
+    }
+    print(json.dumps(rec))
+
+
+def cpu_baseline_batched(problems, nsteps):
+    import cgl_inputs as ci
+    from oracle import steppers
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    steps = []
+    for p in problems:
+        E = steppers.operators_for(p, p.tau)
+        H = steppers.operators_for(p, 0.5 * p.tau)
+        nl = steppers.CGLNonlinearity(p.coeffs.as_tuple())
+        steps.append((steppers.make_step("lawson4", E, H, p.tau, nl), ci.initial_state(p)))
+    t0 = time.perf_counter()
+    pts = 0
+    for step, u in steps:
+        for _ in range(nsteps):
+            u = step(u)
+        pts += u.size * nsteps
+    dt = time.perf_counter() - t0
+    return {"value": pts / dt, "unit": "grid-point-steps/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{nsteps} Lawson4 steps of each of the first {len(problems)} instances "
+                      f"(numpy FP64, literal scheme); {dt:.2f} s"}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -142,6 +264,8 @@ def main():
     import torch
     import cgl_inputs as ci
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "c3":
+        return bench_batched(args)
     p, method = workload(args.workload)
     u0 = ci.initial_state(p)
     K, W = args.steps, args.warmup

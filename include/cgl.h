@@ -167,6 +167,34 @@ const char* cgl_strerror(int status);
 /* Number of bf16 terms used per operator entry by a CGL_SPLIT_BF16 plan. */
 int cgl_split_terms(cgl_plan_t p, int* op_terms, int* state_terms);
 
+/* Give every operator at once: A[mu] for mu < d (plain plan) or A[j*d + mu]
+ * (batched plan), each host complex128 column-major.  The exponentials
+ * H = exp(tau A / 2) (Pade-13 with scaling and squaring) and E = H H are
+ * computed in parallel host threads.  Errors as cgl_set_operators. */
+int cgl_set_operators_all(cgl_plan_t p, const double* const* A);
+
+/* ---- batched plans: many independent instances stepped together ----
+ * Instance j (0 <= j < batch) has its own grid n[j*d .. j*d+d-1] and
+ * coefficients c[j] (the shared step tau and precision).  Every state tensor
+ * of the plan concatenates the instances: instance j occupies the complex
+ * elements [off_j, off_j + prod_mu n[j*d+mu]) (cgl_instance_offset), each
+ * column-major as in a plain plan.  cgl_step_strang, cgl_step_lawson4,
+ * cgl_run, cgl_tucker, cgl_status and cgl_destroy accept batched plans; in the
+ * split form each mu-mode pass of all instances is ONE persistent launch over
+ * a device table of (instance, row tile, fibre tile) work items, with the tile
+ * shape chosen by timing at the first step.  The FP64 form launches one pass
+ * per instance.  cgl_mode_product, cgl_set_operators, cgl_set_exponentials and
+ * cgl_get_operator reject batched plans (CGL_EINVAL). */
+int cgl_plan_batched(cgl_plan_t* out, int batch, int d, const int64_t* n /*[batch*d]*/,
+                     const cgl_coeffs* c /*[batch]*/, double tau, int precision, unsigned flags,
+                     void* hip_stream);
+int cgl_batch_size(cgl_plan_t p, int* batch); /* 0 for a plain plan */
+int cgl_instance_offset(cgl_plan_t p, int j, int64_t* off);
+/* operator A_mu of instance j (host complex128 column-major, copied) */
+int cgl_set_instance_operators(cgl_plan_t p, int j, int mu, const double* A);
+/* FP64 exponential (which = CGL_E / CGL_H) of direction mu of instance j */
+int cgl_get_instance_operator(cgl_plan_t p, int j, int mu, int which, double* out_host);
+
 #ifdef __cplusplus
 }
 #endif

@@ -48,6 +48,13 @@ SIGNATURES = {
     "cgl_destroy": (None, [_P]),
     "cgl_strerror": (C.c_char_p, [_I]),
     "cgl_split_terms": (_I, [_P, C.POINTER(_I), C.POINTER(_I)]),
+    "cgl_set_operators_all": (_I, [_P, C.POINTER(_DP)]),
+    "cgl_plan_batched": (_I, [C.POINTER(_P), _I, _I, C.POINTER(_I64), C.POINTER(Coeffs), _D, _I,
+                              C.c_uint, _P]),
+    "cgl_batch_size": (_I, [_P, C.POINTER(_I)]),
+    "cgl_instance_offset": (_I, [_P, _I, C.POINTER(_I64)]),
+    "cgl_set_instance_operators": (_I, [_P, _I, _I, _DP]),
+    "cgl_get_instance_operator": (_I, [_P, _I, _I, _I, _DP]),
 }
 
 _lib = None

@@ -108,8 +108,13 @@ class Plan:
         check(L.lib().cgl_set_exponentials(self._h, mu, _dptr(E), _dptr(H)), "cgl_set_exponentials")
 
     def set_fd_operators(self, a: float, b: float, bc: int, coeffs) -> None:
-        for mu, nm in enumerate(self.n):
-            self.set_operators(mu, fd_operator(nm, a, b, bc, coeffs, self.d))
+        self.set_operators_all([fd_operator(nm, a, b, bc, coeffs, self.d) for nm in self.n])
+
+    def set_operators_all(self, As) -> None:
+        """cgl_set_operators_all: every operator at once (parallel exponentials)."""
+        mats = [np.asfortranarray(A, dtype=np.complex128) for A in As]
+        arr = (C.POINTER(C.c_double) * len(mats))(*[_dptr(m) for m in mats])
+        check(L.lib().cgl_set_operators_all(self._h, arr), "cgl_set_operators_all")
 
     def get_operator(self, mu: int, which: int) -> np.ndarray:
         nm = self.n[mu]
@@ -162,3 +167,69 @@ class Plan:
             self.destroy()
         except Exception:
             pass
+
+
+class BatchedPlan(Plan):
+    """cgl_plan_batched: independent instances with their own grids and
+    coefficients, stepped together.  State tensors are 1-D complex torch
+    tensors holding every instance's column-stacked grid function at the
+    offsets ``self.offsets``."""
+
+    def __init__(self, grids, coeffs, tau: float, precision: str = "split",
+                 master: bool = False, rk4_flow: bool = False, stream: Optional[int] = None):
+        grids = [tuple(int(v) for v in g) for g in grids]
+        self.grids = grids
+        self.batch = len(grids)
+        d = len(grids[0])
+        assert all(len(g) == d for g in grids)
+        self.n = grids[0]
+        self.d = d
+        self.tau = float(tau)
+        self.precision = precision
+        self.master = bool(master)
+        flags = (L.FLAG_FP64_MASTER if master else 0) | (L.FLAG_RK4_FLOW if rk4_flow else 0)
+        if stream is None:
+            stream = current_stream_handle()
+        self._stream = stream
+        flat = [v for g in grids for v in g]
+        arr = (C.c_int64 * len(flat))(*flat)
+        carr = (L.Coeffs * self.batch)(*[_coeffs(c) for c in coeffs])
+        h = C.c_void_p()
+        check(L.lib().cgl_plan_batched(C.byref(h), self.batch, d, arr, carr, self.tau,
+                                       PRECISIONS[precision], flags, C.c_void_p(stream)),
+              "cgl_plan_batched")
+        self._h = h
+        self.offsets = []
+        for j in range(self.batch):
+            off = C.c_int64()
+            check(L.lib().cgl_instance_offset(self._h, j, C.byref(off)))
+            self.offsets.append(off.value)
+        self.N = int(sum(int(np.prod(g)) for g in grids))
+
+    def set_fd_operators_batched(self, problems) -> None:
+        """FD operators of every instance (problems[j] with n, a, b, bc, coeffs)."""
+        mats = []
+        for p in problems:
+            for nm in p.n:
+                mats.append(fd_operator(nm, p.a, p.b, p.bc, p.coeffs, len(p.n)))
+        self.set_operators_all(mats)
+
+    def get_instance_operator(self, j: int, mu: int, which: int) -> np.ndarray:
+        nm = self.grids[j][mu]
+        out = np.zeros((nm, nm), dtype=np.complex128, order="F")
+        check(L.lib().cgl_get_instance_operator(self._h, j, mu, which, _dptr(out)))
+        return out
+
+    def to_device_batched(self, states, dtype=None):
+        torch = _torch()
+        flat = np.concatenate([np.asarray(u).reshape(-1, order="F") for u in states])
+        return torch.from_numpy(flat.astype(np.complex128)).to(device="cuda",
+                                                                 dtype=dtype or self.state_dtype)
+
+    def to_host_batched(self, t):
+        v = t.detach().to("cpu").numpy().astype(np.complex128)
+        out = []
+        for j, g in enumerate(self.grids):
+            Nj = int(np.prod(g))
+            out.append(v[self.offsets[j]:self.offsets[j] + Nj].reshape(g, order="F"))
+        return out

@@ -10,6 +10,8 @@
 #include <map>
 #include <string>
 #include <new>
+#include <thread>
+#include <atomic>
 #include <tuple>
 #include <vector>
 
@@ -63,11 +65,29 @@ struct cgl_plan_s {
   unsigned* hflag = nullptr;  // pinned
   std::map<GraphKey, hipGraphExec_t> graphs;
   NlParams nl{};
+  // batched plans (batch > 0): independent instances, instance j has grid
+  // bn[j*d .. j*d+d-1], coefficients bnl[j], and lives at complex offset boff[j]
+  int batch = 0;
+  std::vector<int64_t> bn, boff;
+  std::vector<NlParams> bnl;
+  std::vector<CMat> bE, bH;         // [batch*d] FP64 exponentials
+  std::vector<DeviceOp> bdE, bdH;   // [batch*d]
+  std::vector<char> bhave;          // [batch*d]
+  BatchInstance* dinst[3] = {nullptr, nullptr, nullptr};
+  BatchTile* dtiles[3][SPLIT_NTILES] = {};
+  int ntiles[3][SPLIT_NTILES] = {};
+  bool tables = false;
+  int nwg = 0;  // persistent grid size
 };
 
 namespace {
 
 bool ready(const cgl_plan_s* p) {
+  if (p->batch > 0) {
+    for (char h : p->bhave)
+      if (!h) return false;
+    return true;
+  }
   for (int mu = 0; mu < p->d; ++mu)
     if (!p->have_ops[mu]) return false;
   return true;
@@ -140,8 +160,13 @@ int upload_op(cgl_plan_s* p, const CMat& M, DeviceOp& dst) {
 
 // rotated: the input's contraction axis is its fastest one and the output is
 // written with that axis moved to the slowest position (split form only).
+int pass_batched(cgl_plan_s* p, int mu, int which, const void* in0, const void* aux, void* out0,
+                 void* out1, int pro, int epi, bool in_f64, bool out_f64, hipStream_t s);
+
 int pass(cgl_plan_s* p, int mu, int which, const void* in0, const void* aux, void* out0,
          void* out1, int pro, int epi, bool in_f64, bool out_f64, bool rotated, hipStream_t s) {
+  if (p->batch > 0)
+    return pass_batched(p, mu, which, in0, aux, out0, out1, pro, epi, in_f64, out_f64, s);
   const DeviceOp& op = (which == CGL_E) ? p->dE[mu] : p->dH[mu];
   int64_t R = 1;
   for (int nu = 0; nu < mu; ++nu) R *= p->n[nu];
@@ -191,6 +216,113 @@ int pass(cgl_plan_s* p, int mu, int which, const void* in0, const void* aux, voi
   return e == hipSuccess ? CGL_OK : CGL_EDEVICE;
 }
 
+// One pass over every instance of a batched plan.  Split form: one persistent
+// launch over the tile table of direction mu (rotated layout).  FP64 form: one
+// in-place launch per instance.
+int pass_batched(cgl_plan_s* p, int mu, int which, const void* in0, const void* aux, void* out0,
+                 void* out1, int pro, int epi, bool in_f64, bool out_f64, hipStream_t s) {
+  const int d = p->d;
+  if (p->precision == CGL_SPLIT_BF16) {
+    if (!p->tables) return CGL_ENOTREADY;
+    const int t = p->tile[mu] >= 0 ? p->tile[mu] : 0;
+    PassBatch b{};
+    b.in0 = in0;
+    b.aux = aux;
+    b.out0 = out0;
+    b.out1 = out1;
+    b.inst = p->dinst[mu];
+    b.tiles = p->dtiles[mu][t];
+    b.ntiles = p->ntiles[mu][t];
+    b.which = which == CGL_E ? 0 : 1;
+    b.pro = pro;
+    b.epi = epi;
+    b.in_f64 = in_f64 ? 1 : 0;
+    b.out_f64 = out_f64 ? 1 : 0;
+    b.tile = t;
+    b.flag = p->dflag;
+    return launch_pass_split_batched(b, p->nwg, s) == hipSuccess ? CGL_OK : CGL_EDEVICE;
+  }
+  for (int j = 0; j < p->batch; ++j) {
+    const int64_t* nj = &p->bn[static_cast<size_t>(j) * d];
+    int64_t Nj = 1, R = 1;
+    for (int nu = 0; nu < d; ++nu) Nj *= nj[nu];
+    for (int nu = 0; nu < mu; ++nu) R *= nj[nu];
+    const DeviceOp& op = (which == CGL_E) ? p->bdE[static_cast<size_t>(j) * d + mu]
+                                          : p->bdH[static_cast<size_t>(j) * d + mu];
+    const size_t o = static_cast<size_t>(p->boff[j]) * 2;
+    PassF64 a{};
+    a.in0 = static_cast<const double*>(in0) + o;
+    a.aux = aux ? static_cast<const double*>(aux) + o : nullptr;
+    a.out0 = static_cast<double*>(out0) + o;
+    a.out1 = out1 ? static_cast<double*>(out1) + o : nullptr;
+    a.op = static_cast<const double*>(op.ptr[0]);
+    a.R = R;
+    a.F = Nj / nj[mu];
+    a.n = static_cast<int>(nj[mu]);
+    a.Pp = op.Pp[0];
+    a.Kp = op.Kp[0];
+    a.pro = pro;
+    a.epi = epi;
+    a.nl = p->bnl[j];
+    a.flag = p->dflag;
+    if (launch_pass_f64(a, s) != hipSuccess) return CGL_EDEVICE;
+  }
+  return CGL_OK;
+}
+
+// Device instance tables and tile lists of a split batched plan (built once
+// all operators are set).  Tiles are ordered by decreasing contraction length
+// so that the persistent grid's round-robin deal balances the work.
+int build_tables(cgl_plan_s* p) {
+  if (p->tables || p->batch == 0 || p->precision != CGL_SPLIT_BF16) return CGL_OK;
+  const int d = p->d;
+  for (int mu = 0; mu < d; ++mu) {
+    std::vector<BatchInstance> inst(p->batch);
+    for (int j = 0; j < p->batch; ++j) {
+      const size_t k = static_cast<size_t>(j) * d + mu;
+      int64_t Nj = 1;
+      for (int nu = 0; nu < d; ++nu) Nj *= p->bn[static_cast<size_t>(j) * d + nu];
+      BatchInstance& b = inst[j];
+      b.off = p->boff[j];
+      b.n = static_cast<int>(p->bn[k]);
+      b.F = static_cast<int>(Nj / p->bn[k]);
+      for (int t = 0; t < SPLIT_NTILES; ++t) {
+        b.Pp[t] = p->bdE[k].Pp[t];
+        b.Kp[t] = p->bdE[k].Kp[t];
+        b.opE[t] = static_cast<const uint16_t*>(p->bdE[k].ptr[t]);
+        b.opH[t] = static_cast<const uint16_t*>(p->bdH[k].ptr[t]);
+      }
+      b.nl = p->bnl[j];
+    }
+    int st = upload_bytes(p, inst.data(), inst.size() * sizeof(BatchInstance),
+                          reinterpret_cast<void**>(&p->dinst[mu]));
+    if (st != CGL_OK) return st;
+    for (int t = 0; t < SPLIT_NTILES; ++t) {
+      std::vector<std::pair<int, BatchTile>> order;
+      for (int j = 0; j < p->batch; ++j) {
+        const int nP = inst[j].Pp[t] / SPLIT_TILES[t].PT;
+        const int nF = (inst[j].F + SP_FT - 1) / SP_FT;
+        for (int pt = 0; pt < nP; ++pt)
+          for (int ft = 0; ft < nF; ++ft) order.push_back({inst[j].Kp[t], BatchTile{j, pt, ft}});
+      }
+      std::stable_sort(order.begin(), order.end(),
+                       [](const auto& x, const auto& y) { return x.first > y.first; });
+      std::vector<BatchTile> tl;
+      for (auto& o : order) tl.push_back(o.second);
+      p->ntiles[mu][t] = static_cast<int>(tl.size());
+      st = upload_bytes(p, tl.data(), tl.size() * sizeof(BatchTile),
+                        reinterpret_cast<void**>(&p->dtiles[mu][t]));
+      if (st != CGL_OK) return st;
+    }
+  }
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  p->nwg = 2 * cus;  // two 256-thread workgroups per CU fit the LDS of either tile shape
+  p->tables = true;
+  return CGL_OK;
+}
+
 // d passes of one exponential action.  Intermediate results alternate between
 // the ping-pong buffers stage[0] / stage[1]; the last pass applies the
 // epilogue and writes out0 (and out1).  A pass never reads and writes the same
@@ -228,6 +360,8 @@ int action(cgl_plan_s* p, int which, const void* in0, const void* aux, void* out
 // any graph capture; a no-op for FP64 plans and directions already tuned.
 int ensure_tuned(cgl_plan_s* p) {
   if (p->precision != CGL_SPLIT_BF16) return CGL_OK;
+  const int bt = build_tables(p);
+  if (bt != CGL_OK) return bt;
   // CGL_SPLIT_TILE=<index> fixes the tile shape (tests of every shape, tuning studies)
   const char* forced = std::getenv("CGL_SPLIT_TILE");
   for (int mu = 0; mu < p->d; ++mu) {
@@ -238,9 +372,16 @@ int ensure_tuned(cgl_plan_s* p) {
       p->tile[mu] = t;
       continue;
     }
-    const int64_t n = p->n[mu];
-    const std::string key = device_tag() + ":split:n" + std::to_string(n) + ":F" +
-                            std::to_string(p->N / n);
+    std::string key;
+    if (p->batch > 0) {
+      uint64_t h = 1469598103934665603ull;  // FNV-1a over the instance sizes
+      for (int64_t v : p->bn) h = (h ^ static_cast<uint64_t>(v)) * 1099511628211ull;
+      key = device_tag() + ":splitbatch:b" + std::to_string(p->batch) + ":mu" +
+            std::to_string(mu) + ":h" + std::to_string(h);
+    } else {
+      const int64_t n = p->n[mu];
+      key = device_tag() + ":split:n" + std::to_string(n) + ":F" + std::to_string(p->N / n);
+    }
     const int saved = p->tile[mu];
     auto launch = [&](int t) -> hipError_t {
       p->tile[mu] = t;
@@ -317,11 +458,15 @@ int cgl_expm(int64_t n, const double* A, double t, double* out) {
   return CGL_OK;
 }
 
-int cgl_plan(cgl_plan_t* out, int d, const int64_t* n, const cgl_coeffs* c, double tau,
-             int precision, unsigned flags, void* hip_stream) {
-  if (!out) return CGL_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// Validates the common arguments and allocates a plan whose state tensors
+// have N complex points (stage buffers, flags, streams, events).
+int create_plan(cgl_plan_t* out, int d, const int64_t* n, int64_t N, const cgl_coeffs* c,
+                double tau, int precision, unsigned flags, void* hip_stream) {
   *out = nullptr;
-  if (!n || !c || d < 1 || d > 3) return CGL_EINVAL;
   if (!(tau > 0.0) || !std::isfinite(tau)) return CGL_EINVAL;
   if (!(c->a1 > 0.0)) return CGL_EINVAL;
   if (precision != CGL_FP64 && precision != CGL_SPLIT_BF16) return CGL_EINVAL;
@@ -330,16 +475,11 @@ int cgl_plan(cgl_plan_t* out, int d, const int64_t* n, const cgl_coeffs* c, doub
   const double cv[7] = {c->a1, c->b1, c->a2, c->a3, c->b3, c->a4, c->b4};
   for (double v : cv)
     if (!std::isfinite(v)) return CGL_EINVAL;
-  int64_t N = 1;
-  for (int mu = 0; mu < d; ++mu) {
-    if (n[mu] < 3 || n[mu] > 4096) return CGL_EINVAL;
-    N *= n[mu];
-  }
-  if (N > (int64_t(1) << 31)) return CGL_EINVAL;
+  if (N < 3 || N > (int64_t(1) << 31)) return CGL_EINVAL;
   cgl_plan_s* p = new (std::nothrow) cgl_plan_s();
   if (!p) return CGL_ENOMEM;
   p->d = d;
-  for (int mu = 0; mu < d; ++mu) p->n[mu] = n[mu];
+  for (int mu = 0; mu < d; ++mu) p->n[mu] = n ? n[mu] : 1;
   p->N = N;
   p->c = *c;
   p->tau = tau;
@@ -379,8 +519,197 @@ int cgl_plan(cgl_plan_t* out, int d, const int64_t* n, const cgl_coeffs* c, doub
   return CGL_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int cgl_plan(cgl_plan_t* out, int d, const int64_t* n, const cgl_coeffs* c, double tau,
+             int precision, unsigned flags, void* hip_stream) {
+  if (!out) return CGL_EINVAL;
+  *out = nullptr;
+  if (!n || !c || d < 1 || d > 3) return CGL_EINVAL;
+  int64_t N = 1;
+  for (int mu = 0; mu < d; ++mu) {
+    if (n[mu] < 3 || n[mu] > 4096) return CGL_EINVAL;
+    N *= n[mu];
+  }
+  return create_plan(out, d, n, N, c, tau, precision, flags, hip_stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// H = exp(tau A / 2) by Pade-13 with scaling and squaring, and E = H H (the
+// final squaring of the same method), for a list of operators, in parallel
+// host threads.  Returns false if any exponential fails.
+bool exponentials(const std::vector<CMat>& A, double tau, std::vector<CMat>& E,
+                  std::vector<CMat>& H) {
+  E.assign(A.size(), CMat());
+  H.assign(A.size(), CMat());
+  std::atomic<size_t> next{0};
+  std::atomic<bool> ok{true};
+  auto work = [&]() {
+    for (size_t i = next++; i < A.size(); i = next++) {
+      if (!expm_pade13(A[i], 0.5 * tau, H[i])) {
+        ok = false;
+        continue;
+      }
+      cmat_mul(H[i], H[i], E[i]);
+    }
+  };
+  const unsigned hw = std::max(1u, std::min<unsigned>(std::thread::hardware_concurrency(), 32u));
+  const unsigned nt = static_cast<unsigned>(std::min<size_t>(hw, A.size()));
+  std::vector<std::thread> th;
+  for (unsigned t = 1; t < nt; ++t) th.emplace_back(work);
+  work();
+  for (auto& t : th) t.join();
+  return ok;
+}
+
+bool finite_mat(const double* A, int64_t n) {
+  for (int64_t k = 0; k < 2 * n * n; ++k)
+    if (!std::isfinite(A[k])) return false;
+  return true;
+}
+
+int set_instance(cgl_plan_s* p, size_t k, const CMat& E, const CMat& H) {
+  p->bE[k] = E;
+  p->bH[k] = H;
+  int st = upload_op(p, E, p->bdE[k]);
+  if (st == CGL_OK) st = upload_op(p, H, p->bdH[k]);
+  p->bhave[k] = (st == CGL_OK);
+  return st;
+}
+
+void invalidate(cgl_plan_s* p) {
+  for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+  p->graphs.clear();
+  for (int mu = 0; mu < 3; ++mu) {
+    if (p->dinst[mu]) (void)hipFree(p->dinst[mu]);
+    p->dinst[mu] = nullptr;
+    for (int t = 0; t < SPLIT_NTILES; ++t) {
+      if (p->dtiles[mu][t]) (void)hipFree(p->dtiles[mu][t]);
+      p->dtiles[mu][t] = nullptr;
+    }
+  }
+  p->tables = false;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cgl_plan_batched(cgl_plan_t* out, int batch, int d, const int64_t* n, const cgl_coeffs* c,
+                     double tau, int precision, unsigned flags, void* hip_stream) {
+  if (!out) return CGL_EINVAL;
+  *out = nullptr;
+  if (batch < 1 || !n || !c || d < 1 || d > 3) return CGL_EINVAL;
+  std::vector<int64_t> boff(batch);
+  int64_t N = 0;
+  for (int j = 0; j < batch; ++j) {
+    int64_t Nj = 1;
+    for (int mu = 0; mu < d; ++mu) {
+      const int64_t v = n[static_cast<size_t>(j) * d + mu];
+      if (v < 3 || v > 4096) return CGL_EINVAL;
+      Nj *= v;
+    }
+    if (!(c[j].a1 > 0.0)) return CGL_EINVAL;
+    for (double v : {c[j].a1, c[j].b1, c[j].a2, c[j].a3, c[j].b3, c[j].a4, c[j].b4})
+      if (!std::isfinite(v)) return CGL_EINVAL;
+    boff[j] = N;
+    N += Nj;
+  }
+  cgl_plan_t p = nullptr;
+  int st = create_plan(&p, d, nullptr, N, &c[0], tau, precision, flags, hip_stream);
+  if (st != CGL_OK) return st;
+  p->batch = batch;
+  p->bn.assign(n, n + static_cast<size_t>(batch) * d);
+  p->boff = boff;
+  p->bnl.resize(batch);
+  for (int j = 0; j < batch; ++j) {
+    NlParams q = p->nl;
+    q.a3 = c[j].a3;
+    q.b3 = c[j].b3;
+    q.a4 = c[j].a4;
+    q.b4 = c[j].b4;
+    q.exact = (c[j].a4 == 0.0 && c[j].b4 == 0.0 && !(flags & CGL_FLAG_RK4_FLOW)) ? 1 : 0;
+    p->bnl[j] = q;
+  }
+  const size_t K = static_cast<size_t>(batch) * d;
+  p->bE.resize(K);
+  p->bH.resize(K);
+  p->bdE.resize(K);
+  p->bdH.resize(K);
+  p->bhave.assign(K, 0);
+  *out = p;
+  return CGL_OK;
+}
+
+int cgl_batch_size(cgl_plan_t p, int* batch) {
+  if (!p || !batch) return CGL_EINVAL;
+  *batch = p->batch;
+  return CGL_OK;
+}
+
+int cgl_instance_offset(cgl_plan_t p, int j, int64_t* off) {
+  if (!p || !off || j < 0 || j >= std::max(1, p->batch)) return CGL_EINVAL;
+  *off = p->batch > 0 ? p->boff[j] : 0;
+  return CGL_OK;
+}
+
+int cgl_set_instance_operators(cgl_plan_t p, int j, int mu, const double* A) {
+  if (!p || !A || p->batch == 0 || j < 0 || j >= p->batch || mu < 0 || mu >= p->d)
+    return CGL_EINVAL;
+  const size_t k = static_cast<size_t>(j) * p->d + mu;
+  const int64_t n = p->bn[k];
+  if (!finite_mat(A, n)) return CGL_EINVAL;
+  std::vector<CMat> Av{CMat::from_interleaved(n, A)}, E, H;
+  if (!exponentials(Av, p->tau, E, H)) return CGL_EINVAL;
+  invalidate(p);
+  return set_instance(p, k, E[0], H[0]);
+}
+
+int cgl_set_operators_all(cgl_plan_t p, const double* const* A) {
+  if (!p || !A) return CGL_EINVAL;
+  const size_t K = p->batch > 0 ? static_cast<size_t>(p->batch) * p->d : static_cast<size_t>(p->d);
+  std::vector<CMat> Av(K);
+  for (size_t k = 0; k < K; ++k) {
+    const int64_t n = p->batch > 0 ? p->bn[k] : p->n[k];
+    if (!A[k] || !finite_mat(A[k], n)) return CGL_EINVAL;
+    Av[k] = CMat::from_interleaved(n, A[k]);
+  }
+  std::vector<CMat> E, H;
+  if (!exponentials(Av, p->tau, E, H)) return CGL_EINVAL;
+  invalidate(p);
+  for (size_t k = 0; k < K; ++k) {
+    int st;
+    if (p->batch > 0) {
+      st = set_instance(p, k, E[k], H[k]);
+    } else {
+      p->E[k] = E[k];
+      p->H[k] = H[k];
+      st = upload_op(p, p->E[k], p->dE[k]);
+      if (st == CGL_OK) st = upload_op(p, p->H[k], p->dH[k]);
+      p->have_ops[k] = (st == CGL_OK);
+    }
+    if (st != CGL_OK) return st;
+  }
+  return CGL_OK;
+}
+
+int cgl_get_instance_operator(cgl_plan_t p, int j, int mu, int which, double* out_host) {
+  if (!p || !out_host || p->batch == 0 || j < 0 || j >= p->batch || mu < 0 || mu >= p->d ||
+      (which != CGL_E && which != CGL_H))
+    return CGL_EINVAL;
+  const size_t k = static_cast<size_t>(j) * p->d + mu;
+  if (!p->bhave[k]) return CGL_ENOTREADY;
+  (which == CGL_E ? p->bE[k] : p->bH[k]).to_interleaved(out_host);
+  return CGL_OK;
+}
+
 int cgl_set_exponentials(cgl_plan_t p, int mu, const double* E, const double* H) {
-  if (!p || !E || !H || mu < 0 || mu >= p->d) return CGL_EINVAL;
+  if (!p || !E || !H || mu < 0 || mu >= p->d || p->batch > 0) return CGL_EINVAL;
   const int64_t n = p->n[mu];
   for (int64_t k = 0; k < 2 * n * n; ++k)
     if (!std::isfinite(E[k]) || !std::isfinite(H[k])) return CGL_EINVAL;
@@ -396,21 +725,20 @@ int cgl_set_exponentials(cgl_plan_t p, int mu, const double* E, const double* H)
 }
 
 int cgl_set_operators(cgl_plan_t p, int mu, const double* A) {
-  if (!p || !A || mu < 0 || mu >= p->d) return CGL_EINVAL;
+  if (!p || !A || mu < 0 || mu >= p->d || p->batch > 0) return CGL_EINVAL;
   const int64_t n = p->n[mu];
-  for (int64_t k = 0; k < 2 * n * n; ++k)
-    if (!std::isfinite(A[k])) return CGL_EINVAL;
-  const CMat M = CMat::from_interleaved(n, A);
-  CMat E, H;
-  if (!expm_pade13(M, p->tau, E) || !expm_pade13(M, 0.5 * p->tau, H)) return CGL_EINVAL;
+  if (!finite_mat(A, n)) return CGL_EINVAL;
+  std::vector<CMat> Av{CMat::from_interleaved(n, A)}, E, H;
+  if (!exponentials(Av, p->tau, E, H)) return CGL_EINVAL;
   std::vector<double> e(2 * n * n), h(2 * n * n);
-  E.to_interleaved(e.data());
-  H.to_interleaved(h.data());
+  E[0].to_interleaved(e.data());
+  H[0].to_interleaved(h.data());
   return cgl_set_exponentials(p, mu, e.data(), h.data());
 }
 
 int cgl_get_operator(cgl_plan_t p, int mu, int which, double* out_host) {
-  if (!p || !out_host || mu < 0 || mu >= p->d || (which != CGL_E && which != CGL_H))
+  if (!p || !out_host || mu < 0 || mu >= p->d || (which != CGL_E && which != CGL_H) ||
+      p->batch > 0)
     return CGL_EINVAL;
   if (!p->have_ops[mu]) return CGL_ENOTREADY;
   (which == CGL_E ? p->E[mu] : p->H[mu]).to_interleaved(out_host);
@@ -425,7 +753,8 @@ int cgl_split_terms(cgl_plan_t p, int* op_terms, int* state_terms) {
 }
 
 int cgl_mode_product(cgl_plan_t p, int mu, int which, const void* in_dev, void* out_dev) {
-  if (!p || !in_dev || !out_dev || mu < 0 || mu >= p->d || in_dev == out_dev) return CGL_EINVAL;
+  if (!p || !in_dev || !out_dev || mu < 0 || mu >= p->d || in_dev == out_dev || p->batch > 0)
+    return CGL_EINVAL;
   if (which != CGL_E && which != CGL_H) return CGL_EINVAL;
   if (!ready(p)) return CGL_ENOTREADY;
   const int st = ensure_tuned(p);
@@ -544,10 +873,14 @@ void cgl_destroy(cgl_plan_t p) {
   if (p->gstream) (void)hipStreamSynchronize(p->gstream);
   (void)hipDeviceSynchronize();
   for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+  p->graphs.clear();
   for (int mu = 0; mu < 3; ++mu) {
     free_op(p->dE[mu]);
     free_op(p->dH[mu]);
   }
+  invalidate(p);
+  for (auto& o : p->bdE) free_op(o);
+  for (auto& o : p->bdH) free_op(o);
   for (void* s : p->stage)
     if (s) (void)hipFree(s);
   if (p->dflag) (void)hipFree(p->dflag);

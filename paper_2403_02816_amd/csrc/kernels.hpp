@@ -98,8 +98,45 @@ struct PassSplit {
 };
 
 constexpr int SP_FT = 64;    // fibres per workgroup (rows/stage sizes: split_layout.hpp)
+constexpr int SPLIT_MAX_TILES = 2;
 constexpr int SP_TERMS = 3;  // bf16 terms per operand
 
 hipError_t launch_pass_split(const PassSplit& a, hipStream_t s);
+
+// ---- batched split-precision passes (many independent instances)
+struct BatchInstance {
+  int64_t off;  // complex offset of the instance in every batched tensor
+  int n;        // contraction length of this pass
+  int F;        // fibres of this pass
+  int Pp[SPLIT_MAX_TILES];
+  int Kp[SPLIT_MAX_TILES];
+  const uint16_t* opE[SPLIT_MAX_TILES];  // bf16 planes of exp(tau A) per tile shape
+  const uint16_t* opH[SPLIT_MAX_TILES];  // and of exp(tau A / 2)
+  NlParams nl;
+};
+
+struct BatchTile {
+  int inst, pt, ft;
+};
+
+struct PassBatch {
+  const void* in0;
+  const void* aux;
+  void* out0;
+  void* out1;
+  const BatchInstance* inst;  // device table for this pass direction
+  const BatchTile* tiles;     // device list, largest instances first
+  int ntiles;
+  int which;  // 0: E, 1: H
+  int pro;
+  int epi;
+  int in_f64;
+  int out_f64;
+  int tile;  // tile shape (index into SPLIT_TILES)
+  unsigned* flag;
+};
+
+// launches a persistent grid of at most nwg workgroups over b.tiles
+hipError_t launch_pass_split_batched(const PassBatch& b, int nwg, hipStream_t s);
 
 }  // namespace cgl

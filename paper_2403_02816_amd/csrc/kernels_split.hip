@@ -127,28 +127,33 @@ __device__ __forceinline__ void store_terms(unsigned short* dst, const unsigned*
   }
 }
 
+template <int PT, int KS>
+struct Lds {
+  static constexpr int PITCH = KS + 8;  // LDS row pitch in bf16
+  unsigned short A[6][PT][PITCH];
+  unsigned short B[6][FT][PITCH];
+};
+
+// One workgroup tile: output rows [pt*PT, pt*PT + PT) x fibres [f0, f0 + 64)
+// of the pass described by a.  Every thread of the workgroup calls it.
 template <int PT, int KS, bool CONTIG, int PRO, bool IN64>
-__global__ __launch_bounds__(256, 2) void k_pass_split(PassSplit a) {
+__device__ __forceinline__ void split_tile(const PassSplit& a, int pt, int64_t f0,
+                                           Lds<PT, KS>& lds) {
   constexpr int FI = Stage<KS, CONTIG>::FI;
   constexpr int KJ = Stage<KS, CONTIG>::KJ;
   constexpr int PB = PT / 64;          // 32-row blocks per wave
-  constexpr int PITCH = KS + 8;        // LDS row pitch in bf16
   constexpr int CPS = PT * KS / 8;     // 16-byte chunks per plane per stage
   constexpr int OPCH = 6 * CPS / 256;  // operator chunks per thread per stage
   static_assert(OPCH * 256 == 6 * CPS, "operator stage must split evenly");
-  __shared__ __attribute__((aligned(16))) unsigned short sA[6][PT][PITCH];
-  __shared__ __attribute__((aligned(16))) unsigned short sB[6][FT][PITCH];
+  auto& sA = lds.A;
+  auto& sB = lds.B;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wp = wave & 1;
   const int wf = wave >> 1;
-  const int nP = a.Pp / PT;
   const int nKS = a.Kp / KS;
-  const unsigned w = xcd_remap(blockIdx.x, gridDim.x);
-  const int pt = static_cast<int>(w % nP);
-  const int64_t f0 = static_cast<int64_t>(w / nP) * FT;
   const u32x4* opblk =
       reinterpret_cast<const u32x4*>(a.op + static_cast<size_t>(pt) * nKS * (6 * PT * KS));
   const bool of64 = a.out_f64 != 0;
@@ -356,6 +361,48 @@ __global__ __launch_bounds__(256, 2) void k_pass_split(PassSplit a) {
   if (flag) atomicOr(a.flag, flag);
 }
 
+template <int PT, int KS, bool CONTIG, int PRO, bool IN64>
+__global__ __launch_bounds__(256, 2) void k_pass_split(PassSplit a) {
+  __shared__ __attribute__((aligned(16))) Lds<PT, KS> lds;
+  const int nP = a.Pp / PT;
+  const unsigned w = xcd_remap(blockIdx.x, gridDim.x);
+  split_tile<PT, KS, CONTIG, PRO, IN64>(a, static_cast<int>(w % nP),
+                                       static_cast<int64_t>(w / nP) * FT, lds);
+}
+
+// Batched form: a persistent grid walks a table of (instance, p-tile, fibre
+// tile) entries; each instance has its own grid size, coefficients and
+// operator planes, and lives at its own offset in every batched tensor.
+template <int PT, int KS, int PRO, bool IN64>
+__global__ __launch_bounds__(256, 2) void k_pass_split_batched(PassBatch b) {
+  __shared__ __attribute__((aligned(16))) Lds<PT, KS> lds;
+  for (int t = blockIdx.x; t < b.ntiles; t += gridDim.x) {
+    const BatchTile tl = b.tiles[t];
+    const BatchInstance& in = b.inst[tl.inst];
+    PassSplit a{};
+    const size_t esz_in = IN64 ? 16 : 8, esz_out = b.out_f64 ? 16 : 8;
+    a.in0 = static_cast<const char*>(b.in0) + in.off * esz_in;
+    a.aux = b.aux ? static_cast<const char*>(b.aux) + in.off * 8 : nullptr;
+    a.out0 = static_cast<char*>(b.out0) + in.off * esz_out;
+    a.out1 = b.out1 ? static_cast<char*>(b.out1) + in.off * esz_out : nullptr;
+    a.op = b.which == 0 ? in.opE[b.tile] : in.opH[b.tile];
+    a.R = 1;
+    a.R_out = in.F;
+    a.F = in.F;
+    a.n = in.n;
+    a.Pp = in.Pp[b.tile];
+    a.Kp = in.Kp[b.tile];
+    a.pro = PRO;
+    a.epi = b.epi;
+    a.in_f64 = IN64 ? 1 : 0;
+    a.out_f64 = b.out_f64;
+    a.tile = b.tile;
+    a.nl = in.nl;
+    a.flag = b.flag;
+    split_tile<PT, KS, true, PRO, IN64>(a, tl.pt, static_cast<int64_t>(tl.ft) * FT, lds);
+  }
+}
+
 template <int PT, int KS, bool CONTIG, int PRO>
 void launch_pro(const PassSplit& a, dim3 grid, hipStream_t s) {
   if (a.in_f64)
@@ -383,6 +430,40 @@ void launch_tile(const PassSplit& a, dim3 grid, hipStream_t s) {
 }
 
 }  // namespace
+
+template <int PT, int KS>
+void launch_batched_tile(const PassBatch& b, dim3 grid, hipStream_t s) {
+  if (b.pro == PRO_G) {
+    if (b.in_f64)
+      hipLaunchKernelGGL((k_pass_split_batched<PT, KS, PRO_G, true>), grid, dim3(256), 0, s, b);
+    else
+      hipLaunchKernelGGL((k_pass_split_batched<PT, KS, PRO_G, false>), grid, dim3(256), 0, s, b);
+  } else if (b.pro == PRO_FLOW) {
+    if (b.in_f64)
+      hipLaunchKernelGGL((k_pass_split_batched<PT, KS, PRO_FLOW, true>), grid, dim3(256), 0, s, b);
+    else
+      hipLaunchKernelGGL((k_pass_split_batched<PT, KS, PRO_FLOW, false>), grid, dim3(256), 0, s, b);
+  } else {
+    if (b.in_f64)
+      hipLaunchKernelGGL((k_pass_split_batched<PT, KS, PRO_NONE, true>), grid, dim3(256), 0, s, b);
+    else
+      hipLaunchKernelGGL((k_pass_split_batched<PT, KS, PRO_NONE, false>), grid, dim3(256), 0, s, b);
+  }
+}
+
+hipError_t launch_pass_split_batched(const PassBatch& b, int nwg, hipStream_t s) {
+  if (b.tile < 0 || b.tile >= SPLIT_NTILES || b.ntiles <= 0 || nwg <= 0) return hipErrorInvalidValue;
+  if (!b.in0 || !b.out0 || !b.inst || !b.tiles || !b.flag) return hipErrorInvalidValue;
+  if ((b.epi == EPI_L4_R1 || b.epi == EPI_L4_R2) && !b.aux) return hipErrorInvalidValue;
+  if (b.epi == EPI_L4_R1 && !b.out1) return hipErrorInvalidValue;
+  if (b.pro != PRO_NONE && b.pro != PRO_FLOW && b.pro != PRO_G) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>(nwg < b.ntiles ? nwg : b.ntiles));
+  if (b.tile == 0)
+    launch_batched_tile<64, 32>(b, grid, s);
+  else
+    launch_batched_tile<128, 16>(b, grid, s);
+  return hipGetLastError();
+}
 
 hipError_t launch_pass_split(const PassSplit& a, hipStream_t s) {
   if (a.tile < 0 || a.tile >= SPLIT_NTILES) return hipErrorInvalidValue;

@@ -34,7 +34,7 @@ def oracle_run(p: ci.Problem, u0: np.ndarray, method: str, m: int, E, H, rk4_flo
     library applies e^{tau K} as e^{tau K/2} e^{tau K/2}; the oracle is given
     E = H H so both use the same data."""
     nl = steppers.CGLNonlinearity(p.coeffs.as_tuple(), force_rk4=rk4_flow)
-    if method == "lawson4":
+    if method == "lawson4" or E is None:
         E = [h @ h for h in H]
     u, bad = steppers.run(u0, steppers.make_step(method, E, H, p.tau, nl), m)
     return u

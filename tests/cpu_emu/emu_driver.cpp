@@ -176,6 +176,74 @@ static void run_steps(std::vector<int64_t> n, int precision, unsigned flags, cgl
   cgl_destroy(p);
 }
 
+// Batched plan vs one plain plan per instance with the same exponentials:
+// the same kernels run on the same data, so the states must agree bitwise.
+static void batched_vs_single(int precision) {
+  const std::vector<std::vector<int64_t>> grids = {{32, 48}, {20, 33}, {64, 32}, {9, 7}};
+  const int B = static_cast<int>(grids.size()), d = 2;
+  std::vector<int64_t> flat;
+  std::vector<cgl_coeffs> cs;
+  for (int j = 0; j < B; ++j) {
+    flat.insert(flat.end(), grids[j].begin(), grids[j].end());
+    cs.push_back(cgl_coeffs{1.0 + 0.2 * j, -0.5 + 0.3 * j, 0.1 * j, -1.0 - 0.1 * j, 0.5 + 0.2 * j, 0, 0});
+  }
+  cgl_plan_t bp = nullptr;
+  expect(cgl_plan_batched(&bp, B, d, flat.data(), cs.data(), 0.01, precision, 0, nullptr) == CGL_OK,
+         "plan_batched");
+  std::vector<std::vector<cd>> As;
+  std::vector<const double*> ptrs;
+  for (int j = 0; j < B; ++j)
+    for (int mu = 0; mu < d; ++mu) {
+      As.emplace_back(grids[j][mu] * grids[j][mu]);
+      expect(cgl_fd_operator(grids[j][mu], -10, 10, CGL_DIRICHLET, &cs[j], d,
+                             reinterpret_cast<double*>(As.back().data())) == CGL_OK, "fd");
+    }
+  for (auto& A : As) ptrs.push_back(reinterpret_cast<const double*>(A.data()));
+  expect(cgl_set_operators_all(bp, ptrs.data()) == CGL_OK, "set_operators_all");
+  int64_t N = 0;
+  std::vector<int64_t> offs(B);
+  for (int j = 0; j < B; ++j) {
+    expect(cgl_instance_offset(bp, j, &offs[j]) == CGL_OK, "offset");
+    N += grids[j][0] * grids[j][1];
+  }
+  auto U = rnd(N, 21, 0.4);
+  std::vector<cd> u64 = U;
+  std::vector<std::complex<float>> u32 = cast<float>(U);
+  const bool c128 = precision == CGL_FP64;
+  void* u = c128 ? static_cast<void*>(u64.data()) : static_cast<void*>(u32.data());
+  expect(cgl_step_lawson4(bp, u, 2) == CGL_OK, "batched lawson4");
+  expect(cgl_run(bp, CGL_STRANG, u, 2, 1) == CGL_OK, "batched run strang");
+  expect(cgl_status(bp) == CGL_OK, "batched status");
+  int mism = 0;
+  for (int j = 0; j < B; ++j) {
+    cgl_plan_t sp = nullptr;
+    expect(cgl_plan(&sp, d, grids[j].data(), &cs[j], 0.01, precision, 0, nullptr) == CGL_OK, "plan");
+    for (int mu = 0; mu < d; ++mu) {
+      std::vector<cd> E(grids[j][mu] * grids[j][mu]), H(E.size());
+      expect(cgl_get_instance_operator(bp, j, mu, CGL_E, reinterpret_cast<double*>(E.data())) ==
+                 CGL_OK, "get E");
+      expect(cgl_get_instance_operator(bp, j, mu, CGL_H, reinterpret_cast<double*>(H.data())) ==
+                 CGL_OK, "get H");
+      expect(cgl_set_exponentials(sp, mu, reinterpret_cast<double*>(E.data()),
+                                  reinterpret_cast<double*>(H.data())) == CGL_OK, "set exps");
+    }
+    const int64_t Nj = grids[j][0] * grids[j][1];
+    std::vector<cd> v64(U.begin() + offs[j], U.begin() + offs[j] + Nj);
+    std::vector<std::complex<float>> v32 = cast<float>(v64);
+    void* v = c128 ? static_cast<void*>(v64.data()) : static_cast<void*>(v32.data());
+    expect(cgl_step_lawson4(sp, v, 2) == CGL_OK, "single lawson4");
+    expect(cgl_run(sp, CGL_STRANG, v, 2, 1) == CGL_OK, "single run strang");
+    for (int64_t i = 0; i < Nj; ++i) {
+      const bool same = c128 ? (v64[i] == u64[offs[j] + i]) : (v32[i] == u32[offs[j] + i]);
+      if (!same) ++mism;
+    }
+    cgl_destroy(sp);
+  }
+  std::printf("  batched vs single prec=%d mismatches=%d\n", precision, mism);
+  expect(mism == 0, "batched == single");
+  cgl_destroy(bp);
+}
+
 int main(int argc, char** argv) {
   if (argc > 1 && std::string(argv[1]) == "gpu-sequence") {
     // the GPU FP64 test file's order: mode products, Tuckers, C0 Strang, C0 Lawson4
@@ -207,6 +275,7 @@ int main(int argc, char** argv) {
     steppers({12, 10, 14}, CGL_SPLIT_BF16, CGL_FLAG_FP64_MASTER, cq, -15, 15, CGL_NEUMANN);
     steppers({37}, CGL_SPLIT_BF16, CGL_FLAG_FP64_MASTER, cub, -10, 10, CGL_DIRICHLET);
   } else if (argc > 1 && std::string(argv[1]) == "split") {
+    batched_vs_single(CGL_SPLIT_BF16);
     kernel_parity({20, 9, 7}, CGL_SPLIT_BF16, 3);
     kernel_parity({32, 64, 3}, CGL_SPLIT_BF16, 6);
     steppers({32, 64}, CGL_SPLIT_BF16, 0, cub, -10, 10, CGL_DIRICHLET);
@@ -227,6 +296,8 @@ int main(int argc, char** argv) {
     steppers({64, 32}, CGL_SPLIT_BF16, CGL_FLAG_FP64_MASTER, cub, -10, 10, CGL_DIRICHLET);
     steppers({7, 6, 5}, CGL_SPLIT_BF16, CGL_FLAG_FP64_MASTER, cq, -15, 15, CGL_NEUMANN);
     steppers({9}, CGL_SPLIT_BF16, CGL_FLAG_FP64_MASTER, cub, -10, 10, CGL_DIRICHLET);
+    batched_vs_single(CGL_FP64);
+    batched_vs_single(CGL_SPLIT_BF16);
   }
   std::printf("%s (%d failures)\n", failures ? "FAILED" : "PASSED", failures);
   return failures ? 1 : 0;

@@ -244,6 +244,9 @@ inline hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
 inline hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) { *ms = 1.0f; return hipSuccess; }
 struct hipDeviceProp_t { char gcnArchName[256]; };
 inline hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }
+enum { hipDeviceAttributeMultiprocessorCount = 1 };
+// a small emulated device: few workgroups, so persistent grids loop over tiles
+inline hipError_t hipDeviceGetAttribute(int* v, int, int) { *v = 2; return hipSuccess; }
 inline hipError_t hipGetDeviceProperties(hipDeviceProp_t* p, int) {
   std::strcpy(p->gcnArchName, "emu");
   return hipSuccess;
