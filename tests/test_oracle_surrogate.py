@@ -1,0 +1,67 @@
+"""Pins of the FP64 surrogate oracle: the 3x3 convolution against an
+independent library correlation, gradients against central finite
+differences, the SiLU derivative, Adam's first step, and the parameter count."""
+import numpy as np
+import scipy.signal
+
+from oracle import surrogate as S
+
+
+def test_param_count_of_the_48_channel_6_layer_net():
+    assert S.param_count(48, 4) == 87074
+
+
+def test_conv3x3_equals_scipy_correlate2d_with_zero_padding():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((2, 3, 6, 5))
+    W = rng.standard_normal((4, 3, 3, 3))
+    b = rng.standard_normal(4)
+    out = S.conv3x3(x, W, b)
+    for s in range(2):
+        for o in range(4):
+            ref = b[o] + sum(scipy.signal.correlate2d(x[s, c], W[o, c], mode="same", boundary="fill")
+                             for c in range(3))
+            assert np.abs(out[s, o] - ref).max() < 1e-12
+
+
+def test_silu_derivative():
+    a = np.linspace(-6, 6, 101)
+    h = 1e-6
+    fd = (S.silu(a + h) - S.silu(a - h)) / (2 * h)
+    assert np.abs(S.silu_grad(a) - fd).max() < 1e-8
+
+
+def test_backward_matches_central_finite_differences():
+    C, blocks = 3, 2
+    rng = np.random.default_rng(1)
+    params = S.init_params(2, C, blocks) + 0.05 * rng.standard_normal(S.param_count(C, blocks))
+    x = rng.standard_normal((2, 7, 5, 6))
+    target = rng.standard_normal((2, 2, 5, 6))
+    y, cache = S.forward(params, x, C, blocks)
+    g = S.backward(params, cache, y, target, C, blocks)
+    h = 1e-6
+    fd = np.zeros_like(params)
+    for i in range(params.size):
+        e = np.zeros_like(params)
+        e[i] = h
+        fd[i] = (S.loss(S.forward(params + e, x, C, blocks)[0], target)
+                 - S.loss(S.forward(params - e, x, C, blocks)[0], target)) / (2 * h)
+    assert np.abs(g - fd).max() < 1e-7 * max(1.0, np.abs(fd).max())
+
+
+def test_adam_first_step_is_lr_times_sign():
+    p = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 1e-3])
+    q, m, v = S.adam_step(p, g, np.zeros(3), np.zeros(3), 1, 0.01)
+    assert np.allclose(q, p - 0.01 * g / (np.abs(g) + 1e-8))
+
+
+def test_identity_net_returns_its_input_state():
+    """With zero output weights and biases the network is the identity on u."""
+    C, blocks = 4, 1
+    params = S.init_params(3, C, blocks)
+    layers = S.unpack(params, C, blocks)
+    layers[-1] = (np.zeros_like(layers[-1][0]), np.zeros(2))
+    x = np.random.default_rng(4).standard_normal((1, 7, 4, 5))
+    y, _ = S.forward(S.pack(layers), x, C, blocks)
+    assert np.array_equal(y, x[:, 0:2])
