@@ -195,6 +195,87 @@ int cgl_set_instance_operators(cgl_plan_t p, int j, int mu, const double* A);
 /* FP64 exponential (which = CGL_E / CGL_H) of direction mu of instance j */
 int cgl_get_instance_operator(cgl_plan_t p, int j, int mu, int which, double* out_host);
 
+/* ---- learned surrogate of the stepper (no counterpart in the paper) ----
+ * A residual convolutional network on a 2-D grid n1 x n2 that maps a state
+ * u(t) to an estimate of u(t + M tau) in one jump:
+ *   x   = [Re u, Im u, c_1 .. c_5]  (7 planes; c = the five coefficients
+ *         (a1, b1, a2, a3, b3) of eq. cqCGL standardised by the caller)
+ *   h0  = silu(conv_in x)                      7 -> 48 channels
+ *   h_k = h_{k-1} + silu(conv_k h_{k-1})        48 -> 48, k = 1..4
+ *   y   = (Re u, Im u) + conv_out h_4           48 -> 2
+ * with 3x3 kernels, zero padding, silu(a) = a / (1 + e^{-a}).  Parameters are
+ * FP32 on the device, packed as W_in, b_in, W_1, b_1, ..., W_out, b_out with
+ * W[co][ci][ky][kx] (ky along index 2, kx along index 1); the convolutions
+ * run on bf16 MFMA with the weights and activations rounded to bf16 and FP32
+ * accumulation.  Training minimises a loss (cgl_sur_set_loss) with Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8).
+ * States are complex64 device arrays, index 1 fastest; sample s of a batch
+ * lives at complex offset s * n1 * n2.  Work is enqueued on the stream given
+ * to cgl_sur_create; entry points returning host data synchronise it. */
+typedef struct cgl_sur_s* cgl_sur_t;
+
+/* Number of FP32 parameters (87 074). */
+int cgl_sur_param_count(int64_t* count);
+
+/* Network for grids n1 x n2 (n1 a multiple of 64, 64 <= n1 <= 4096,
+ * 1 <= n2 <= 4096) and batches of at most max_batch samples; allocates the
+ * activations of a training batch (about 2.6 KB per point and sample).
+ * CGL_EINVAL for bad sizes, CGL_ENOMEM when allocation fails. */
+int cgl_sur_create(cgl_sur_t* out, int64_t n1, int64_t n2, int max_batch, void* hip_stream);
+
+/* Copy count FP32 parameters from the host (synchronous) and reset the Adam
+ * moments and step count.  CGL_EINVAL if any parameter is not finite. */
+int cgl_sur_set_params(cgl_sur_t s, const float* params_host);
+/* Training loss: CGL_SUR_LOSS_MSE (the default) is the mean over samples,
+ * planes and points of (y - target)^2; CGL_SUR_LOSS_REL is the mean over
+ * samples of sum (y - target)^2 / sum target^2, the square of the relative
+ * L2 error that the gated run checks (a sample with a zero target counts 0). */
+enum { CGL_SUR_LOSS_MSE = 0, CGL_SUR_LOSS_REL = 1 };
+int cgl_sur_set_loss(cgl_sur_t s, int kind);
+
+/* Copy the current parameters to the host (synchronous). */
+int cgl_sur_get_params(cgl_sur_t s, float* params_host);
+
+/* out = network(u) for batch samples (1 <= batch <= max_batch); cstd_dev is a
+ * device float array [batch][5].  out may equal u.  CGL_ENOTREADY before
+ * cgl_sur_set_params. */
+int cgl_sur_forward(cgl_sur_t s, int batch, const void* u_dev, const float* cstd_dev,
+                    void* out_dev);
+
+/* Training batch: sample s is input src[i_s] with coefficients cstd[i_s]
+ * (device [*][5]) and target src[i_s + target_offset], where i_s = idx[s]
+ * (device int32 array) or s when idx_dev is NULL.  cgl_sur_grad writes the
+ * loss gradient to grad_host[count] and the loss to *loss_host (if not NULL)
+ * without changing the parameters (synchronous).  cgl_sur_train_step takes
+ * one Adam step with learning rate lr (asynchronous); the mean loss of the
+ * steps since the last call is returned by cgl_sur_take_loss (synchronous). */
+int cgl_sur_grad(cgl_sur_t s, int batch, const void* src_dev, const float* cstd_dev,
+                 const int32_t* idx_dev, int64_t target_offset, float* grad_host,
+                 double* loss_host);
+int cgl_sur_train_step(cgl_sur_t s, int batch, const void* src_dev, const float* cstd_dev,
+                       const int32_t* idx_dev, int64_t target_offset, float lr);
+int cgl_sur_take_loss(cgl_sur_t s, double* mean_loss);
+
+/* Synchronise and free the network.  NULL is accepted. */
+void cgl_sur_destroy(cgl_sur_t s);
+
+/* Gated run of njumps jumps of steps_per_jump Lawson4 steps each on the
+ * complex64 state u_dev of plan p (a 2-D CGL_SPLIT_BF16 plan without
+ * CGL_FLAG_FP64_MASTER on the network's grid), with standardised
+ * coefficients cstd[5].  Jumps j = check_every, 2 check_every, ... and the
+ * last one are checked: the plain stepper advances the state the jump
+ * started from by steps_per_jump steps; if the relative L2 distance of the
+ * jump's result from it is <= tol, the jumps since the previous check are
+ * accepted and the run continues from the plain result; otherwise they are
+ * rejected, the state is rolled back to the last verified state and the
+ * span is redone with the plain stepper, so the result then equals the
+ * plain stepper's.  stats (if not NULL) receives [accepted jumps, rejected
+ * jumps, checks, plain steps taken].  Runs on the plan's stream and
+ * synchronises at every check. */
+int cgl_run_surrogate(cgl_plan_t p, cgl_sur_t s, void* u_dev, const double* cstd,
+                      int64_t njumps, int64_t steps_per_jump, int64_t check_every, double tol,
+                      int64_t* stats);
+
 #ifdef __cplusplus
 }
 #endif

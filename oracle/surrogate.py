@@ -10,8 +10,9 @@ Network (C = 48 channels, 3x3 kernels, zero padding, pixel p = i1 + n1 i2):
     h_k = h_{k-1} + silu(conv_k(h_{k-1})),  k = 1..4               (C -> C)
     d   = conv_out(h_4)                                           (C -> 2)
     y   = (Re u, Im u) + d
-silu(a) = a sigmoid(a).  Loss: mean over samples, channels and pixels of
-(y - target)^2.  Parameters are packed in the order W_in, b_in, W_1, b_1,
+silu(a) = a sigmoid(a).  Loss "mse": mean over samples, channels and pixels
+of (y - target)^2; loss "rel": mean over samples of the squared relative L2
+error sum (y - target)^2 / sum target^2 (sums over channels and pixels).  Parameters are packed in the order W_in, b_in, W_1, b_1,
 ..., W_4, b_4, W_out, b_out with W[co, ci, ky, kx] (ky along i2, kx along i1).
 """
 from __future__ import annotations
@@ -123,16 +124,28 @@ def forward(params: np.ndarray, x: np.ndarray, C: int = 48, blocks: int = 4):
     return y, cache
 
 
-def loss(y: np.ndarray, target: np.ndarray) -> float:
-    return float(np.mean((y - target) ** 2))
+def loss(y: np.ndarray, target: np.ndarray, kind: str = "mse") -> float:
+    if kind == "mse":
+        return float(np.mean((y - target) ** 2))
+    num = np.sum((y - target) ** 2, axis=(1, 2, 3))
+    den = np.sum(target ** 2, axis=(1, 2, 3))
+    return float(np.mean(num / den))
+
+
+def loss_grad(y: np.ndarray, target: np.ndarray, kind: str = "mse") -> np.ndarray:
+    """d loss / d y."""
+    if kind == "mse":
+        return 2.0 * (y - target) / y.size
+    den = np.sum(target ** 2, axis=(1, 2, 3))
+    return 2.0 * (y - target) / (y.shape[0] * den[:, None, None, None])
 
 
 def backward(params: np.ndarray, cache, y: np.ndarray, target: np.ndarray, C: int = 48,
-             blocks: int = 4) -> np.ndarray:
-    """Gradient of loss(y, target) with respect to the packed parameters."""
+             blocks: int = 4, kind: str = "mse") -> np.ndarray:
+    """Gradient of loss(y, target, kind) with respect to the packed parameters."""
     layers = unpack(params, C, blocks)
     grads = [None] * len(layers)
-    dy = 2.0 * (y - target) / y.size
+    dy = loss_grad(y, target, kind)
     hs, As = cache["h"], cache["a"]
     # output conv: d = conv_out(h_last)
     dh, dW, db = conv3x3_grads(hs[-1], layers[-1][0], dy)

@@ -19,6 +19,7 @@ DIRICHLET, NEUMANN = 0, 1
 E, H = 0, 1
 FLAG_FP64_MASTER = 1
 FLAG_RK4_FLOW = 2
+SUR_LOSS_MSE, SUR_LOSS_REL = 0, 1
 
 
 class Coeffs(C.Structure):
@@ -55,6 +56,17 @@ SIGNATURES = {
     "cgl_instance_offset": (_I, [_P, _I, C.POINTER(_I64)]),
     "cgl_set_instance_operators": (_I, [_P, _I, _I, _DP]),
     "cgl_get_instance_operator": (_I, [_P, _I, _I, _I, _DP]),
+    "cgl_sur_param_count": (_I, [C.POINTER(_I64)]),
+    "cgl_sur_create": (_I, [C.POINTER(_P), _I64, _I64, _I, _P]),
+    "cgl_sur_set_params": (_I, [_P, C.POINTER(C.c_float)]),
+    "cgl_sur_get_params": (_I, [_P, C.POINTER(C.c_float)]),
+    "cgl_sur_set_loss": (_I, [_P, _I]),
+    "cgl_sur_forward": (_I, [_P, _I, _P, _P, _P]),
+    "cgl_sur_grad": (_I, [_P, _I, _P, _P, _P, _I64, C.POINTER(C.c_float), _DP]),
+    "cgl_sur_train_step": (_I, [_P, _I, _P, _P, _P, _I64, C.c_float]),
+    "cgl_sur_take_loss": (_I, [_P, _DP]),
+    "cgl_sur_destroy": (None, [_P]),
+    "cgl_run_surrogate": (_I, [_P, _P, _P, _DP, _I64, _I64, _I64, _D, C.POINTER(_I64)]),
 }
 
 _lib = None

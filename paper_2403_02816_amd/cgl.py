@@ -233,3 +233,94 @@ class BatchedPlan(Plan):
             Nj = int(np.prod(g))
             out.append(v[self.offsets[j]:self.offsets[j] + Nj].reshape(g, order="F"))
         return out
+
+
+def _fptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def sur_param_count() -> int:
+    n = C.c_int64()
+    check(L.lib().cgl_sur_param_count(C.byref(n)))
+    return n.value
+
+
+class Surrogate:
+    """cgl_sur_*: the residual conv net on an n1 x n2 grid.  States are 1-D
+    complex64 torch tensors of batch * n1 * n2 elements (sample-major, each
+    sample column-stacked); coefficient tensors are float32 (batch, 5) on the
+    device; index tensors int32."""
+
+    def __init__(self, n1: int, n2: int, max_batch: int, stream: Optional[int] = None):
+        self.n1, self.n2, self.max_batch = int(n1), int(n2), int(max_batch)
+        self.P = self.n1 * self.n2
+        if stream is None:
+            stream = current_stream_handle()
+        h = C.c_void_p()
+        check(L.lib().cgl_sur_create(C.byref(h), self.n1, self.n2, self.max_batch,
+                                     C.c_void_p(stream)), "cgl_sur_create")
+        self._h = h
+        self.count = sur_param_count()
+
+    def set_params(self, params: np.ndarray) -> None:
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        assert a.size == self.count
+        check(L.lib().cgl_sur_set_params(self._h, _fptr(a)), "cgl_sur_set_params")
+
+    def set_loss(self, kind: str) -> None:
+        """"mse" or "rel" (mean squared relative L2 error per sample)."""
+        check(L.lib().cgl_sur_set_loss(self._h, {"mse": L.SUR_LOSS_MSE, "rel": L.SUR_LOSS_REL}[kind]),
+              "cgl_sur_set_loss")
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.count, dtype=np.float32)
+        check(L.lib().cgl_sur_get_params(self._h, _fptr(out)), "cgl_sur_get_params")
+        return out
+
+    def forward(self, batch: int, u, cstd, out) -> None:
+        check(L.lib().cgl_sur_forward(self._h, int(batch), _ptr(u), _ptr(cstd), _ptr(out)),
+              "cgl_sur_forward")
+
+    def grad(self, batch: int, src, cstd, idx, target_offset: int):
+        g = np.zeros(self.count, dtype=np.float32)
+        loss = C.c_double()
+        check(L.lib().cgl_sur_grad(self._h, int(batch), _ptr(src), _ptr(cstd), _ptr(idx),
+                                   int(target_offset), _fptr(g), C.byref(loss)), "cgl_sur_grad")
+        return g, loss.value
+
+    def train_step(self, batch: int, src, cstd, idx, target_offset: int, lr: float) -> None:
+        check(L.lib().cgl_sur_train_step(self._h, int(batch), _ptr(src), _ptr(cstd), _ptr(idx),
+                                         int(target_offset), float(lr)), "cgl_sur_train_step")
+
+    def take_loss(self) -> float:
+        v = C.c_double()
+        check(L.lib().cgl_sur_take_loss(self._h, C.byref(v)), "cgl_sur_take_loss")
+        return v.value
+
+    def destroy(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.lib().cgl_sur_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def run_surrogate(plan: Plan, sur: Surrogate, u, cstd, njumps: int, steps_per_jump: int,
+                  check_every: int, tol: float):
+    """cgl_run_surrogate; returns (status, dict of counters)."""
+    c = np.ascontiguousarray(cstd, dtype=np.float64)
+    stats = (C.c_int64 * 4)()
+    st = L.lib().cgl_run_surrogate(plan._h, sur._h, _ptr(u), _dptr(c), int(njumps),
+                                   int(steps_per_jump), int(check_every), float(tol), stats)
+    if st not in (L.OK, L.ENONFINITE, L.EBLOWUP):
+        raise CGLError(st, "cgl_run_surrogate")
+    return st, {"accepted": stats[0], "rejected": stats[1], "checks": stats[2],
+                "plain_steps": stats[3]}

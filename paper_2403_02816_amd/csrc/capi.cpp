@@ -19,6 +19,7 @@
 #include "autotune.hpp"
 #include "host_numerics.hpp"
 #include "kernels.hpp"
+#include "plan_internal.hpp"
 #include "split_layout.hpp"
 
 using namespace cgl;
@@ -892,3 +893,14 @@ void cgl_destroy(cgl_plan_t p) {
 }
 
 }  // extern "C"
+
+int cgl::plan_info(cgl_plan_t p, PlanInfo* out) {
+  if (!p || !out) return CGL_EINVAL;
+  out->d = p->d;
+  for (int mu = 0; mu < 3; ++mu) out->n[mu] = p->n[mu];
+  out->precision = p->precision;
+  out->flags = p->flags;
+  out->batch = p->batch;
+  out->stream = p->ustream;
+  return CGL_OK;
+}

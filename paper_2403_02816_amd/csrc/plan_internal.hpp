@@ -1,0 +1,23 @@
+// Read access to a plan's shape and stream for other parts of the library
+// (the surrogate driver); not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "../../include/cgl.h"
+
+namespace cgl {
+
+struct PlanInfo {
+  int d = 0;
+  int64_t n[3] = {1, 1, 1};
+  int precision = 0;
+  unsigned flags = 0;
+  int batch = 0;
+  hipStream_t stream = nullptr;  // the caller's stream given to cgl_plan
+};
+
+int plan_info(cgl_plan_t p, PlanInfo* out);
+
+}  // namespace cgl

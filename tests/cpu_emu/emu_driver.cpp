@@ -5,6 +5,8 @@
 #include <complex>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
+#include <cmath>
 #include <random>
 #include <string>
 #include <vector>
@@ -244,6 +246,107 @@ static void batched_vs_single(int precision) {
   cgl_destroy(bp);
 }
 
+template <class T>
+static std::vector<T> read_file(const std::string& path, size_t n) {
+  std::vector<T> v(n);
+  FILE* f = std::fopen(path.c_str(), "rb");
+  if (!f || std::fread(v.data(), sizeof(T), n, f) != n) {
+    std::printf("FAIL: cannot read %s\n", path.c_str());
+    std::exit(2);
+  }
+  std::fclose(f);
+  return v;
+}
+
+template <class T>
+static void write_file(const std::string& path, const std::vector<T>& v) {
+  FILE* f = std::fopen(path.c_str(), "wb");
+  if (!f || std::fwrite(v.data(), sizeof(T), v.size(), f) != v.size()) {
+    std::printf("FAIL: cannot write %s\n", path.c_str());
+    std::exit(2);
+  }
+  std::fclose(f);
+}
+
+// Surrogate entry points on inputs written by the test (dir/params.f32,
+// dir/src.c64 with 2S samples: inputs then targets, dir/cstd.f32 [2S][5]);
+// writes the forward result, the gradient, the loss and the parameters
+// after one Adam step, for comparison with the oracle.  Then checks that a
+// gated run whose checks fail reproduces the plain stepper exactly.
+static void surrogate(const std::string& dir, int64_t n1, int64_t n2, int S, float lr) {
+  const int64_t P = n1 * n2;
+  int64_t count = 0;
+  expect(cgl_sur_param_count(&count) == CGL_OK && count == 87074, "param count");
+  auto params = read_file<float>(dir + "/params.f32", count);
+  auto src = read_file<std::complex<float>>(dir + "/src.c64", 2 * S * P);
+  auto cstd = read_file<float>(dir + "/cstd.f32", 2 * S * 5);
+  cgl_sur_t s = nullptr;
+  expect(cgl_sur_create(&s, n1, n2, S, nullptr) == CGL_OK, "sur create");
+  std::vector<std::complex<float>> out(S * P);
+  expect(cgl_sur_forward(s, S, src.data(), cstd.data(), out.data()) == CGL_ENOTREADY, "not ready");
+  expect(cgl_sur_set_params(s, params.data()) == CGL_OK, "set params");
+  expect(cgl_sur_forward(s, S, src.data(), cstd.data(), out.data()) == CGL_OK, "forward");
+  write_file(dir + "/fwd.c64", out);
+  std::vector<float> grad(count);
+  double loss = 0.0;
+  expect(cgl_sur_grad(s, S, src.data(), cstd.data(), nullptr, S, grad.data(), &loss) == CGL_OK,
+         "grad");
+  write_file(dir + "/grad.f32", grad);
+  write_file(dir + "/loss.f64", std::vector<double>{loss});
+  expect(cgl_sur_train_step(s, S, src.data(), cstd.data(), nullptr, S, lr) == CGL_OK, "train");
+  double mean = 0.0;
+  expect(cgl_sur_take_loss(s, &mean) == CGL_OK && std::fabs(mean - loss) <= 1e-6 * loss,
+         "take loss");
+  std::vector<float> after(count);
+  expect(cgl_sur_get_params(s, after.data()) == CGL_OK, "get params");
+  write_file(dir + "/params_after.f32", after);
+  // an index array: sample 1 then 0
+  std::vector<int32_t> idx = {1, 0};
+  if (S >= 2) {
+    std::vector<float> g2(count);
+    double l2 = 0.0;
+    expect(cgl_sur_set_params(s, params.data()) == CGL_OK, "reset params");
+    expect(cgl_sur_grad(s, 2, src.data(), cstd.data(), idx.data(), S, g2.data(), &l2) == CGL_OK,
+           "grad idx");
+    double num = 0, den = 0;
+    for (int64_t i = 0; i < count; ++i) {
+      num += (g2[i] - grad[i]) * (g2[i] - grad[i]);
+      den += grad[i] * grad[i];
+    }
+    // the same two pairs in the other order: equal up to summation order
+    expect(std::sqrt(num / den) < 1e-5 && std::fabs(l2 - loss) < 1e-9 * loss, "idx permutation");
+  }
+
+  // gated run with checks that fail: equals the plain stepper bit for bit
+  cgl_coeffs c{1.0, 0.5, 0.2, -1.0, 1.0, 0.0, 0.0};
+  const int64_t n[2] = {n1, n2};
+  cgl_plan_t p = nullptr;
+  expect(cgl_plan(&p, 2, n, &c, 0.01, CGL_SPLIT_BF16, 0, nullptr) == CGL_OK, "plan");
+  for (int mu = 0; mu < 2; ++mu) {
+    std::vector<double> A(2 * n[mu] * n[mu]);
+    expect(cgl_fd_operator(n[mu], -10, 10, CGL_DIRICHLET, &c, 2, A.data()) == CGL_OK, "fd");
+    expect(cgl_set_operators(p, mu, A.data()) == CGL_OK, "ops");
+  }
+  std::vector<std::complex<float>> ua(src.begin(), src.begin() + P), ub = ua;
+  const double cs[5] = {0.1, -0.2, 0.3, 0.0, 0.5};
+  int64_t stats[4] = {};
+  std::vector<float> bad(count, 0.0f);
+  bad[count - 2] = 50.0f;  // output bias: a jump far from the stepper
+  bad[count - 1] = 50.0f;
+  expect(cgl_sur_set_params(s, bad.data()) == CGL_OK, "bad params");
+  const int gst = cgl_run_surrogate(p, s, ua.data(), cs, 3, 2, 2, 1e-3, stats);
+  if (gst != CGL_OK) std::printf("gated run status %d\n", gst);
+  expect(gst == CGL_OK, "gated run");
+  expect(stats[0] == 0 && stats[1] == 3 && stats[2] == 2 && stats[3] == 2 + 2 * 2 + 2 + 2,
+         "gated stats");
+  expect(cgl_run(p, CGL_LAWSON4, ub.data(), 6, 0) == CGL_OK, "plain run");
+  expect(std::memcmp(ua.data(), ub.data(), ua.size() * sizeof(ua[0])) == 0, "rollback exact");
+  double rs[5] = {0, 0, 0, 0, 0};
+  expect(cgl_run_surrogate(p, s, ua.data(), rs, 1, 0, 1, 1e-3, stats) == CGL_EINVAL, "bad M");
+  cgl_destroy(p);
+  cgl_sur_destroy(s);
+}
+
 int main(int argc, char** argv) {
   if (argc > 1 && std::string(argv[1]) == "gpu-sequence") {
     // the GPU FP64 test file's order: mode products, Tuckers, C0 Strang, C0 Lawson4
@@ -254,6 +357,13 @@ int main(int argc, char** argv) {
     cgl_coeffs c0{1.0, 1.5, 0.5, -1.0, 1.0, 0.0, 0.0};
     run_steps({64, 64}, CGL_FP64, 0, c0, -10, 10, CGL_DIRICHLET, 0.01, CGL_STRANG, 100);
     run_steps({64, 64}, CGL_FP64, 0, c0, -10, 10, CGL_DIRICHLET, 0.01, CGL_LAWSON4, 50);
+    std::printf("%s (%d failures)\n", failures ? "FAILED" : "PASSED", failures);
+    return failures ? 1 : 0;
+  }
+  if (argc > 1 && std::string(argv[1]) == "sur") {
+    if (argc < 7) return 2;
+    surrogate(argv[2], std::atoll(argv[3]), std::atoll(argv[4]), std::atoi(argv[5]),
+              static_cast<float>(std::atof(argv[6])));
     std::printf("%s (%d failures)\n", failures ? "FAILED" : "PASSED", failures);
     return failures ? 1 : 0;
   }

@@ -134,8 +134,39 @@ inline emu_f32x16 emu_mfma_bf16_32(emu_bf16x8 a, emu_bf16x8 b, emu_f32x16 c) {
   return d;
 }
 
+// D(16x16) += A(16x32) B(32x16) in bf16 with FP32 accumulation; lane l:
+// A[l%16][8(l/16)+e], B[8(l/16)+e][l%16], accumulator register r: row
+// 4(l/16) + r, column l%16.
+typedef float emu_f32x4 __attribute__((ext_vector_type(4)));
+inline emu_f32x4 emu_mfma_bf16_16(emu_bf16x8 a, emu_bf16x8 b, emu_f32x4 c) {
+  emu::exchange(a, b);
+  const int l = emu::lane();
+  emu_f32x4 d = c;
+  for (int r = 0; r < 4; ++r) {
+    const int row = 4 * (l / 16) + r, col = l % 16;
+    double s = 0.0;
+    for (int k = 0; k < 32; ++k) {
+      const emu_bf16x8 av = emu::get<emu_bf16x8>(emu::xa[emu::wave()], row + 16 * (k / 8));
+      const emu_bf16x8 bv = emu::get<emu_bf16x8>(emu::xb[emu::wave()], col + 16 * (k / 8));
+      s += static_cast<double>(static_cast<float>(av[k % 8])) *
+           static_cast<double>(static_cast<float>(bv[k % 8]));
+    }
+    d[r] = static_cast<float>(static_cast<double>(d[r]) + s);
+  }
+  emu::wave_barriers[emu::wave()]->arrive_and_wait();
+  return d;
+}
+
+inline double atomicAdd(double* p, double v) {
+  std::lock_guard<std::mutex> g(emu::atomic_mu);
+  const double o = *p;
+  *p = o + v;
+  return o;
+}
+
 #define __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, x, y, z) emu_mfma_f64((a), (b), (c))
 #define __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, x, y, z) emu_mfma_bf16_32((a), (b), (c))
+#define __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, x, y, z) emu_mfma_bf16_16((a), (b), (c))
 
 namespace emu {
 // A persistent pool of host threads plays the workgroup's lanes: for every

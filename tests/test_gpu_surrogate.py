@@ -1,0 +1,214 @@
+"""Surrogate kernels on the GPU against the oracle network: forward pass,
+loss, gradient and Adam step (tight against the oracle evaluated with the
+kernels' bf16 roundings, loose against plain FP64), index gathering, the
+gated run's rollback and acceptance, and a short training run."""
+import numpy as np
+import pytest
+
+import cgl_inputs as ci
+from oracle import surrogate as osur
+from tests import _sur_ref as ref
+from tests._util import log, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def _params(seed):
+    rng = np.random.default_rng(seed)
+    layers = osur.unpack(osur.init_params(seed))
+    layers = [(W * (1.0 if k == 0 else 5.0), rng.uniform(-0.3, 0.3, size=b.shape))
+              for k, (W, b) in enumerate(layers)]
+    return osur.pack(layers).astype(np.float32).astype(np.float64)
+
+
+def _case(n1, n2, S, seed):
+    rng = np.random.default_rng(seed)
+    P = n1 * n2
+    src = (rng.normal(size=(2 * S, P)) + 1j * rng.normal(size=(2 * S, P))).astype(np.complex64)
+    cstd = rng.uniform(-1, 1, size=(2 * S, 5)).astype(np.float32)
+    return _params(seed), src, cstd
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+@pytest.mark.parametrize("n1,n2,S", [(128, 37, 3), (64, 64, 1), (192, 9, 2)])
+def test_forward_and_gradient_parity(n1, n2, S):
+    torch = require_gpu()
+    from paper_2403_02816_amd import cgl
+    log(f"surrogate parity n1={n1} n2={n2} S={S}")
+    params, src, cstd = _case(n1, n2, S, seed=n1 + n2 + S)
+    P = n1 * n2
+    sur = cgl.Surrogate(n1, n2, S)
+    sur.set_params(params.astype(np.float32))
+    u = _dev(torch, src.reshape(-1))
+    cs = _dev(torch, cstd)
+    out = torch.empty((S * P,), dtype=torch.complex64, device="cuda")
+    sur.forward(S, u, cs, out)
+    g, loss = sur.grad(S, u, cs, None, S)
+    fwd = out.cpu().numpy().reshape(S, P)
+
+    s128 = src.astype(np.complex128)
+    c64 = cstd.astype(np.float64)
+    x = ref.inputs_from_states(s128[:S], c64[:S], n1, n2)
+    t = ref.inputs_from_states(s128[S:], c64[S:], n1, n2)[:, 0:2]
+    y_ref, g_ref, loss_ref = ref.grad(params, x, t)
+    y64, cache = osur.forward(params, x)
+    g64 = osur.backward(params, cache, y64, t)
+    e = {"fwd": rel(fwd, ref.planes_to_states(y_ref)),
+         "delta": rel(fwd - s128[:S], ref.planes_to_states(y_ref) - s128[:S]),
+         "grad": rel(g, g_ref), "fwd64": rel(fwd, ref.planes_to_states(y64)),
+         "grad64": rel(g, g64), "loss": abs(loss - loss_ref) / loss_ref}
+    log("  " + " ".join(f"{k} {v:.2e}" for k, v in e.items()))
+    # FP32 accumulation moves activations by ~1e-6 relative; the few that sit
+    # next to a bf16 rounding boundary then round the other way (a 2^-8
+    # change): ~1e-4 in the output.  An indexing error would be O(1).
+    assert e["fwd"] < 5e-4 and e["delta"] < 1e-3
+    assert e["grad"] < 5e-4 and e["loss"] < 1e-5
+    # bf16 weights and activations against the unrounded FP64 network
+    assert e["fwd64"] < 1e-2 and e["grad64"] < 2e-2
+    o = 0
+    for co, cin in osur.layer_shapes():
+        nW = co * cin * 9
+        assert rel(g[o:o + nW], g_ref[o:o + nW]) < 1e-3
+        assert rel(g[o + nW:o + nW + co], g_ref[o + nW:o + nW + co]) < 1e-3
+        o += nW + co
+    # the relative loss (per-sample weights); targets of unequal scale
+    if S > 1:
+        scale = np.geomspace(1e-2, 1.0, S).astype(np.float32)
+        src2 = src.copy()
+        src2[S:] *= scale[:, None]
+        u2 = _dev(torch, src2.reshape(-1))
+        sur.set_loss("rel")
+        g2, loss2 = sur.grad(S, u2, cs, None, S)
+        t2 = ref.inputs_from_states(src2[S:].astype(np.complex128), c64[S:], n1, n2)[:, 0:2]
+        _, g2_ref, loss2_ref = ref.grad(params, x, t2, kind="rel")
+        log(f"  rel loss: grad {rel(g2, g2_ref):.2e} loss {abs(loss2 - loss2_ref) / loss2_ref:.2e}")
+        assert rel(g2, g2_ref) < 5e-4 and abs(loss2 - loss2_ref) < 1e-5 * loss2_ref
+    sur.destroy()
+
+
+def test_adam_step_and_index_gather():
+    torch = require_gpu()
+    from paper_2403_02816_amd import cgl
+    n1, n2, S = 64, 20, 4
+    params, src, cstd = _case(n1, n2, S, seed=11)
+    sur = cgl.Surrogate(n1, n2, S)
+    sur.set_params(params.astype(np.float32))
+    u = _dev(torch, src.reshape(-1))
+    cs = _dev(torch, cstd)
+    g, loss = sur.grad(S, u, cs, None, S)
+    # the same pairs through an index array, in another order
+    idx = _dev(torch, np.array([2, 0, 3, 1], dtype=np.int32))
+    g2, loss2 = sur.grad(S, u, cs, idx, S)
+    assert rel(g2, g) < 1e-5 and abs(loss2 - loss) < 1e-6 * loss
+    # a subset: pairs 1 and 3 alone
+    idx13 = _dev(torch, np.array([3, 1], dtype=np.int32))
+    g13, _ = sur.grad(2, u, cs, idx13, S)
+    x = ref.inputs_from_states(src[[3, 1]].astype(np.complex128), cstd[[3, 1]].astype(np.float64), n1, n2)
+    t = ref.inputs_from_states(src[[S + 3, S + 1]].astype(np.complex128),
+                               cstd[[S + 3, S + 1]].astype(np.float64), n1, n2)[:, 0:2]
+    _, g_ref, _ = ref.grad(params, x, t)
+    assert rel(g13, g_ref) < 5e-4
+    # two Adam steps against the oracle's update on the kernels' gradients
+    lr = 2e-3
+    sur.train_step(S, u, cs, None, S, lr)
+    p1 = sur.get_params().astype(np.float64)
+    m = np.zeros_like(params)
+    v = np.zeros_like(params)
+    exp1, m, v = osur.adam_step(params, g.astype(np.float64), m, v, 1, lr)
+    assert np.max(np.abs(p1 - exp1)) < 1e-6
+    g1, _ = sur.grad(S, u, cs, None, S)  # at the updated parameters
+    sur.train_step(S, u, cs, None, S, lr)
+    p2 = sur.get_params().astype(np.float64)
+    exp2, _, _ = osur.adam_step(p1, g1.astype(np.float64), m, v, 2, lr)
+    assert np.max(np.abs(p2 - exp2)) < 1e-6
+    sur.destroy()
+
+
+def test_errors():
+    require_gpu()
+    from paper_2403_02816_amd import cgl, _lib as L
+    import ctypes as C
+    with pytest.raises(cgl.CGLError):
+        cgl.Surrogate(100, 10, 1)  # n1 not a multiple of 64
+    sur = cgl.Surrogate(64, 8, 2)
+    bad = np.zeros(sur.count, dtype=np.float32)
+    bad[5] = np.nan
+    with pytest.raises(cgl.CGLError):
+        sur.set_params(bad)
+    with pytest.raises(cgl.CGLError):  # no parameters yet
+        sur.get_params()
+    sur.set_params(np.zeros(sur.count, dtype=np.float32))
+    import torch
+    u = torch.zeros(64 * 8 * 3, dtype=torch.complex64, device="cuda")
+    cs = torch.zeros((3, 5), dtype=torch.float32, device="cuda")
+    with pytest.raises(cgl.CGLError):  # batch above max_batch
+        sur.forward(3, u, cs, u)
+    sur.destroy()
+
+
+def _plan_128(p: ci.Problem):
+    from paper_2403_02816_amd import cgl
+    plan = cgl.Plan(p.n, p.coeffs, p.tau, precision="split")
+    plan.set_fd_operators(p.a, p.b, p.bc, p.coeffs)
+    return plan
+
+
+def test_gated_run_rollback_and_accept():
+    torch = require_gpu()
+    from paper_2403_02816_amd import cgl
+    from paper_2403_02816_amd import surrogate as S
+    p = ci.batched_sweep(2, ci.C4_EVAL_SEED, fixed_n=128)[1]
+    plan = _plan_128(p)
+    cs = S.standardise(p.coeffs)
+    sur = cgl.Surrogate(128, 128, 1)
+    bad = np.zeros(sur.count, dtype=np.float32)
+    bad[-2:] = 5.0  # constant offset: every check fails
+    sur.set_params(bad)
+    u0 = plan.to_device(ci.initial_state(p))
+    ua, ub = u0.clone(), u0.clone()
+    st, stats = cgl.run_surrogate(plan, sur, ua, cs, 7, 10, 3, 1e-3)
+    assert st == 0
+    assert stats == {"accepted": 0, "rejected": 7, "checks": 3, "plain_steps": 30 + 70}
+    assert plan.run("lawson4", ub, 70) == 0
+    torch.cuda.synchronize()
+    # rolled back and redone by the plain stepper: identical bits
+    assert torch.equal(ua, ub)
+    # an identity network accepted at a loose tolerance: every accepted check
+    # continues from the plain result of its span, so the state advances by
+    # the 3 checked spans only
+    sur.set_params(np.zeros(sur.count, dtype=np.float32))
+    uc = u0.clone()
+    st, stats = cgl.run_surrogate(plan, sur, uc, cs, 7, 10, 3, 10.0)
+    assert st == 0 and stats == {"accepted": 7, "rejected": 0, "checks": 3, "plain_steps": 30}
+    ud = u0.clone()
+    assert plan.run("lawson4", ud, 30) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(uc, ud)
+    sur.destroy()
+    plan.destroy()
+
+
+def test_training_reduces_loss():
+    require_gpu()
+    from paper_2403_02816_amd import cgl
+    from paper_2403_02816_amd import surrogate as S
+    data = S.generate_pairs(16, ci.C4_TRAIN_SEED, burn_in=100, pairs=6)
+    log(f"  16 trajectories x 6 pairs in {data.seconds:.2f} s")
+    sur = cgl.Surrogate(128, 128, 16)
+    sur.set_params(S.init_params(0))
+    ids = data.pair_ids(range(16))
+    e0 = S.validation_error(sur, data, ids)
+    losses = S.train(sur, data, ids, epochs=40, batch=16, lr_max=1e-3, lr_min=1e-4, log=None)
+    e1 = S.validation_error(sur, data, ids)
+    log(f"  loss {losses[0]:.3e} -> {losses[-1]:.3e}; jump error {e0[0]:.3e} -> {e1[0]:.3e}")
+    assert all(np.isfinite(losses))
+    assert losses[-1] < 0.3 * losses[0]
+    assert e1[0] < 0.6 * e0[0]
+    sur.destroy()

@@ -2,6 +2,7 @@
 independent library correlation, gradients against central finite
 differences, the SiLU derivative, Adam's first step, and the parameter count."""
 import numpy as np
+import pytest
 import scipy.signal
 
 from oracle import surrogate as S
@@ -31,21 +32,22 @@ def test_silu_derivative():
     assert np.abs(S.silu_grad(a) - fd).max() < 1e-8
 
 
-def test_backward_matches_central_finite_differences():
+@pytest.mark.parametrize("kind", ["mse", "rel"])
+def test_backward_matches_central_finite_differences(kind):
     C, blocks = 3, 2
     rng = np.random.default_rng(1)
     params = S.init_params(2, C, blocks) + 0.05 * rng.standard_normal(S.param_count(C, blocks))
     x = rng.standard_normal((2, 7, 5, 6))
-    target = rng.standard_normal((2, 2, 5, 6))
+    target = rng.standard_normal((2, 2, 5, 6)) * np.array([1.0, 0.01])[:, None, None, None]
     y, cache = S.forward(params, x, C, blocks)
-    g = S.backward(params, cache, y, target, C, blocks)
+    g = S.backward(params, cache, y, target, C, blocks, kind=kind)
     h = 1e-6
     fd = np.zeros_like(params)
     for i in range(params.size):
         e = np.zeros_like(params)
         e[i] = h
-        fd[i] = (S.loss(S.forward(params + e, x, C, blocks)[0], target)
-                 - S.loss(S.forward(params - e, x, C, blocks)[0], target)) / (2 * h)
+        fd[i] = (S.loss(S.forward(params + e, x, C, blocks)[0], target, kind)
+                 - S.loss(S.forward(params - e, x, C, blocks)[0], target, kind)) / (2 * h)
     assert np.abs(g - fd).max() < 1e-7 * max(1.0, np.abs(fd).max())
 
 
@@ -65,3 +67,18 @@ def test_identity_net_returns_its_input_state():
     x = np.random.default_rng(4).standard_normal((1, 7, 4, 5))
     y, _ = S.forward(S.pack(layers), x, C, blocks)
     assert np.array_equal(y, x[:, 0:2])
+
+
+def test_relative_loss_closed_forms():
+    """y = (1 + e_s) t per sample gives the mean of e_s^2, whatever the scale
+    of t; with equal target norms it is the mean square divided by the mean
+    square of the target."""
+    rng = np.random.default_rng(5)
+    t = rng.standard_normal((3, 2, 4, 6)) * np.array([1e-3, 1.0, 50.0])[:, None, None, None]
+    e = np.array([0.1, -0.02, 0.3])
+    y = t * (1.0 + e)[:, None, None, None]
+    assert abs(S.loss(y, t, "rel") - np.mean(e ** 2)) < 1e-14
+    t2 = rng.standard_normal((2, 2, 4, 6))
+    t2[1] *= np.sqrt(np.sum(t2[0] ** 2) / np.sum(t2[1] ** 2))
+    y2 = t2 + 0.1 * rng.standard_normal(t2.shape)
+    assert abs(S.loss(y2, t2, "rel") - S.loss(y2, t2) / np.mean(t2 ** 2)) < 1e-12

@@ -1,0 +1,83 @@
+"""The surrogate's HIP kernels and C ABI run on the CPU (emulated HIP runtime
+under AddressSanitizer / UndefinedBehaviorSanitizer), compared with the
+oracle network evaluated with the kernels' bf16 roundings: forward pass,
+loss, gradient, one Adam step, index gathering, and the gated run's
+rollback to the plain stepper."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import surrogate as osur
+from tests import _sur_ref as ref
+
+N1, N2, S, LR = 64, 5, 2, 1e-3
+
+
+def _inputs(tmp, seed=7):
+    rng = np.random.default_rng(seed)
+    params = osur.init_params(seed)
+    # non-zero biases and stronger residual weights exercise every term
+    layers = osur.unpack(params.copy())
+    layers = [(W * (1.0 if k == 0 else 5.0), rng.uniform(-0.3, 0.3, size=b.shape))
+              for k, (W, b) in enumerate(layers)]
+    params = osur.pack(layers).astype(np.float32)
+    P = N1 * N2
+    src = (rng.normal(size=(2 * S, P)) + 1j * rng.normal(size=(2 * S, P))).astype(np.complex64)
+    cstd = rng.uniform(-1, 1, size=(2 * S, 5)).astype(np.float32)
+    params.tofile(os.path.join(tmp, "params.f32"))
+    src.tofile(os.path.join(tmp, "src.c64"))
+    cstd.tofile(os.path.join(tmp, "cstd.f32"))
+    return params.astype(np.float64), src.astype(np.complex128), cstd.astype(np.float64)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+@pytest.mark.skipif(not os.path.exists("/opt/rocm/llvm/bin/clang++"), reason="needs ROCm clang++")
+def test_surrogate_kernels_under_cpu_emulation(tmp_path):
+    from tests.cpu_emu import build as emu_build
+    exe = emu_build.build()
+    tmp = str(tmp_path)
+    params, src, cstd = _inputs(tmp)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    r = subprocess.run([exe, "sur", tmp, str(N1), str(N2), str(S), str(LR)], capture_output=True,
+                       text=True, timeout=900, env=env)
+    print(r.stdout[-3000:], r.stderr[-3000:])
+    assert r.returncode == 0 and "PASSED (0 failures)" in r.stdout
+
+    P = N1 * N2
+    x = ref.inputs_from_states(src[:S], cstd[:S], N1, N2)
+    t = ref.inputs_from_states(src[S:], cstd[S:], N1, N2)[:, 0:2]
+    y_ref, g_ref, loss_ref = ref.grad(params, x, t)
+
+    fwd = np.fromfile(os.path.join(tmp, "fwd.c64"), dtype=np.complex64).reshape(S, P)
+    e_fwd = rel(fwd, ref.planes_to_states(y_ref))
+    # the network's change of the state, the part the kernels compute
+    e_delta = rel(fwd - src[:S], ref.planes_to_states(y_ref) - src[:S])
+    grad = np.fromfile(os.path.join(tmp, "grad.f32"), dtype=np.float32).astype(np.float64)
+    e_grad = rel(grad, g_ref)
+    loss = float(np.fromfile(os.path.join(tmp, "loss.f64"), dtype=np.float64)[0])
+    print(f"forward {e_fwd:.2e} delta {e_delta:.2e} grad {e_grad:.2e} loss {loss} vs {loss_ref}")
+    # bf16 rounding of an activation that the FP32 and FP64 paths place on
+    # either side of a rounding boundary moves it by 2^-8: a few such flips
+    assert e_delta < 1e-4
+    assert e_fwd < 5e-5
+    assert abs(loss - loss_ref) < 1e-5 * loss_ref
+    # per-layer gradients (each slice of the packed vector)
+    o = 0
+    for co, ci in osur.layer_shapes():
+        nW = co * ci * 9
+        assert rel(grad[o:o + nW], g_ref[o:o + nW]) < 1e-3, ("W", co, ci)
+        assert rel(grad[o + nW:o + nW + co], g_ref[o + nW:o + nW + co]) < 1e-3, ("b", co, ci)
+        o += nW + co
+    assert e_grad < 5e-4
+
+    # one Adam step from zero moments on the kernels' own gradient
+    after = np.fromfile(os.path.join(tmp, "params_after.f32"), dtype=np.float32)
+    p32 = params.astype(np.float32).astype(np.float64)
+    exp, _, _ = osur.adam_step(p32, grad, np.zeros_like(grad), np.zeros_like(grad), 1, LR)
+    assert np.max(np.abs(after - exp)) < 1e-6
