@@ -29,13 +29,31 @@ MI355X_PEAK_BF16_TFLOPS = 2500.0  # dense MFMA
 MI355X_PEAK_FP64_TFLOPS = 78.6
 MI355X_PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per split-pass launch of the 128^3 Lawson4 workload from two
+# rocprofv3 counter runs (FETCH_SIZE x 2 + WRITE_SIZE, scale factors measured
+# on a 256 MiB device copy; profiles/split_pass_c1_128_lawson4.md), valid for
+# the kernel sources whose digest is recorded with them.
+SPLIT_TRAFFIC_C1 = {"bytes_per_launch": 38762365.0, "sources_sha256_16": "02a0e4b5d3744fb5"}
+SPLIT_SOURCES = ("kernels_split.hip", "kernels.hpp", "pointwise.hpp", "split_layout.cpp",
+                 "split_layout.hpp")
+
+
+def split_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for name in SPLIT_SOURCES:
+        with open(os.path.join(ROOT, "paper_2403_02816_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c1", choices=["c1", "c2_strang", "c2_lawson4", "c3"])
+    ap.add_argument("--workload", default="c1",
+                    choices=["c1", "c2_strang", "c2_lawson4", "c3", "c4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
@@ -105,6 +123,15 @@ def one_step_gate(p, method, plan):
     nl = steppers.CGLNonlinearity(p.coeffs.as_tuple())
     ref = steppers.make_step(method, E, H, p.tau, nl)(u0)
     return metrics.rel_l2(plan.to_host(u), ref)
+
+
+def _cores():
+    """Threads the host math libraries use."""
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()]))
+    except Exception:
+        return int(os.cpu_count())
 
 
 def cpu_baseline(p, method, nsteps):
@@ -205,7 +232,7 @@ def bench_batched(args):
         b64.destroy()
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline_batched(probs[::8], 4, budget_s=12.0)
+        cpu = cpu_baseline_batched(probs[::8], 150, budget_s=12.0)
     rec = {
         "metric": "grid-point-steps/s at rel-L2 <=1e-6 vs FP64 oracle; MFMA util % of peak",
         "value": Ntot * K / (ms * 1e-3), "unit": "grid-point-steps/s", "n_gpus": 1,
@@ -261,6 +288,137 @@ def cpu_baseline_batched(problems, nsteps, budget_s):
                       f"{dt:.2f} s"}
 
 
+def bench_surrogate(args):
+    """The learned surrogate on 128^2 2-D cubic instances: K timed training
+    steps (batch 64, Adam), the batched forward pass, and gated runs of 20
+    jumps of 50 Lawson4 steps (checked every 10th jump at rel-L2 1e-3) against
+    the plain stepper to the same time on held-out instances."""
+    import torch
+    import cgl_inputs as ci
+    from paper_2403_02816_amd import cgl
+    from paper_2403_02816_amd import surrogate as S
+    K, W = args.steps, args.warmup
+    M, JUMPS, CHECK, TOL, B = ci.C4_JUMP, 20, 10, 1e-3, 64
+    n = ci.C4_N
+    P = n * n
+    data = S.generate_pairs(512, ci.C4_TRAIN_SEED)
+    tr, _ = S.split_trajectories(data.B)
+    sur = cgl.Surrogate(n, n, B)
+    sur.set_params(S.init_params(0))
+    order = np.random.default_rng(0).permutation(
+        np.resize(data.pair_ids(tr), (W + K) * B)).astype(np.int32)
+    idx = torch.from_numpy(order).to("cuda")
+    for b in range(W):
+        sur.train_step(B, data.snaps, data.cstd, idx[b * B:(b + 1) * B], data.B, 1e-3)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for b in range(W, W + K):
+        sur.train_step(B, data.snaps, data.cstd, idx[b * B:(b + 1) * B], data.B, 1e-3)
+    ev1.record()
+    torch.cuda.synchronize()
+    train_ms = ev0.elapsed_time(ev1) / K
+    loss = sur.take_loss()
+    # batched forward pass (inference: 6 conv launches + packing)
+    out = torch.empty((B * P,), dtype=torch.complex64, device="cuda")
+    src = data.snaps[:B * P]
+    cs = data.cstd[:B].contiguous()
+    for _ in range(3):
+        sur.forward(B, src, cs, out)
+    reps = 20
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(reps):
+        sur.forward(B, src, cs, out)
+    ev1.record()
+    torch.cuda.synchronize()
+    fwd_ms = ev0.elapsed_time(ev1) / reps
+    layers = [(48, 7)] + [(48, 48)] * 4 + [(2, 48)]
+    flops_px = sum(2.0 * 9 * co * cin for co, cin in layers)
+    # per point and sample, each stage reads its input and writes its output
+    # once in FP32 (pack 8 + 28, conv_in 28 + 192, residual convs 192 + 192,
+    # conv_out 192 + 8 + 8, unpack 8 + 8)
+    bytes_px = 36 + 220 + 4 * 384 + 208 + 16
+    fwd_gbs = bytes_px * B * P / (fwd_ms * 1e-3) / 1e9
+    fwd_tf = flops_px * B * P / (fwd_ms * 1e-3) / 1e12
+    net = cgl.Surrogate(n, n, 1)
+    net.set_params(sur.get_params())
+    sur.destroy()
+    rows = []
+    for p in ci.batched_sweep(4, ci.C4_EVAL_SEED, fixed_n=n):
+        plan = cgl.Plan(p.n, p.coeffs, p.tau, precision="split")
+        plan.set_fd_operators(p.a, p.b, p.bc, p.coeffs)
+        c5 = S.standardise(p.coeffs)
+        u = plan.to_device(ci.initial_state(p))
+        assert plan.run("lawson4", u, 100) == 0
+        ua, ub = u.clone(), u.clone()
+        cgl.run_surrogate(plan, net, ua, c5, JUMPS, M, CHECK, TOL)
+        plan.run("lawson4", ub, JUMPS * M)
+        ua.copy_(u)
+        ub.copy_(u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, stats = cgl.run_surrogate(plan, net, ua, c5, JUMPS, M, CHECK, TOL)
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        plan.run("lawson4", ub, JUMPS * M)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        err = float(torch.linalg.vector_norm(ua - ub).item() / torch.linalg.vector_norm(ub).item())
+        rows.append((stats, tg, tp, err))
+        plan.destroy()
+    net.destroy()
+    tg = sum(r[1] for r in rows)
+    tp = sum(r[2] for r in rows)
+    acc = sum(r[0]["accepted"] for r in rows) / (JUMPS * len(rows))
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_surrogate(data, S)
+    rec = {
+        "metric": "grid-point-steps/s to T, surrogate jumps gated at rel-L2 <=1e-3 vs plain "
+                  "Lawson4 (fallback: the plain stepper)",
+        "value": len(rows) * P * JUMPS * M / tg, "unit": "grid-point-steps/s", "n_gpus": 1,
+        "steps": K, "warmup": W, "ms_per_step": train_ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16->f32 (conv MFMA), state c64",
+        "data": "synthetic",
+        "config": {"workload": f"surrogate: 6-layer residual CNN (48 ch, 3x3), 128^2 2-D cubic "
+                               f"CGL, jump = {M} Lawson4 steps; trained on 512 x 40 pairs of the "
+                               f"sweep; {len(rows)} held-out instances x {JUMPS} jumps, check "
+                               f"every {CHECK}th", "batch": B, "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": fwd_gbs, "peak": MI355X_PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": fwd_gbs / MI355X_PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "k_conv (forward pass of 64 samples: 6 conv launches + packing)",
+                     "forward_ms": fwd_ms, "mfma_tflops": fwd_tf},
+        "surrogate": {"train_ms_per_step": train_ms, "train_samples_per_s": B / (train_ms * 1e-3),
+                      "train_loss_mean": loss, "forward_ms_batch64": fwd_ms,
+                      "gated_ms": 1e3 * tg / len(rows), "plain_ms": 1e3 * tp / len(rows),
+                      "gain_vs_plain": tp / tg, "accepted_fraction": acc,
+                      "final_rel_l2_vs_plain_max": max(r[3] for r in rows),
+                      "stats": [r[0] for r in rows]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec))
+
+
+def cpu_baseline_surrogate(data, S):
+    """The oracle network forward pass (numpy FP64) on single 128^2 samples."""
+    from oracle import surrogate as osur
+    params = osur.init_params(0)
+    P = data.n * data.n
+    u = data.snaps[:P].cpu().numpy().astype(np.complex128).reshape(data.n, data.n, order="F")
+    x = osur.make_input(u, data.cstd[0].cpu().numpy().astype(np.float64))[None]
+    done, t0 = 0, time.perf_counter()
+    while done < 1 or (time.perf_counter() - t0 < 10.0 and done < 8):
+        osur.forward(params, x)
+        done += 1
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "jumps/s (forward passes of one 128^2 sample)",
+            "cores": _cores(), "kind": "oracle",
+            "sample": f"{done} forward passes of the FP64 numpy network; {dt:.2f} s"}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -272,6 +430,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "c3":
         return bench_batched(args)
+    if args.workload == "c4":
+        return bench_surrogate(args)
     p, method = workload(args.workload)
     u0 = ci.initial_state(p)
     K, W = args.steps, args.warmup
@@ -315,6 +475,9 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(p, method, args.cpu_sample_steps)
 
+    traffic = None
+    if args.workload == "c1" and split_sources_digest() == SPLIT_TRAFFIC_C1["sources_sha256_16"]:
+        traffic = SPLIT_TRAFFIC_C1["bytes_per_launch"]
     rec = {
         "metric": "grid-point-steps/s at rel-L2 <=1e-6 vs FP64 oracle; MFMA util % of peak",
         "value": value,
@@ -334,7 +497,7 @@ def main():
                    "grid": list(p.n), "method": method, "tau": p.tau, "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": achieved_tf, "peak": MI355X_PEAK_BF16_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tf / MI355X_PEAK_BF16_TFLOPS,
-                     "traffic": None,
+                     "traffic": traffic,
                      "kernel": "k_pass_split (all mu-mode passes of a step)",
                      "launch_ms": launch_ms,
                      "hbm_gbs": alg_bytes / (launch_ms * 1e-3) / 1e9},

@@ -296,12 +296,24 @@ __global__ __launch_bounds__(NT) void k_wgrad(WgradArgs a, float* part, int ntil
       }
 }
 
+// grad[j] = sum over the G partial rows of part[b][j]: a workgroup takes 32
+// consecutive j, its 8 thread rows take every 8th partial row, and the 8
+// FP64 sums are combined in LDS
+constexpr int RJ = 32, RB = NT / RJ;
 __global__ void k_reduce_parts(const float* part, int G, int L, float* grad) {
-  const int j = blockIdx.x * NT + threadIdx.x;
-  if (j >= L) return;
+  __shared__ double red[RB][RJ];
+  const int jj = threadIdx.x % RJ, bg = threadIdx.x / RJ;
+  const int j = blockIdx.x * RJ + jj;
   double s = 0.0;
-  for (int b = 0; b < G; ++b) s += part[static_cast<int64_t>(b) * L + j];
-  grad[j] = static_cast<float>(s);
+  if (j < L)
+    for (int b = bg; b < G; b += RB) s += part[static_cast<int64_t>(b) * L + j];
+  red[bg][jj] = s;
+  __syncthreads();
+  if (bg == 0 && j < L) {
+    double t = 0.0;
+    for (int k = 0; k < RB; ++k) t += red[k][jj];
+    grad[j] = static_cast<float>(t);
+  }
 }
 
 __global__ void k_pack_input(const float2* u, const int* idx, const float* cstd, float* x, int S,
@@ -517,7 +529,7 @@ hipError_t launch_wgrad(const WgradArgs& a, float* part, float* grad, hipStream_
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int L = a.cout * a.cin * 9 + a.cout;
-  hipLaunchKernelGGL(k_reduce_parts, dim3((L + NT - 1) / NT), dim3(NT), 0, s, part, G, L, grad);
+  hipLaunchKernelGGL(k_reduce_parts, dim3((L + RJ - 1) / RJ), dim3(NT), 0, s, part, G, L, grad);
   return hipGetLastError();
 }
 

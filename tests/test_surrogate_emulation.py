@@ -12,7 +12,7 @@ import pytest
 from oracle import surrogate as osur
 from tests import _sur_ref as ref
 
-N1, N2, S, LR = 64, 5, 2, 1e-3
+N1, N2, S, LR = 64, 3, 2, 1e-3
 
 
 def _inputs(tmp, seed=7):
