@@ -11,7 +11,9 @@
 // lane l holds rows l/16 + 4r (r < 4) of a 16-row block; the host orders the
 // embedding's rows so that these are two whole complex numbers.
 // Workgroups are remapped so that the P-tiles sharing one input tile run on
-// the same XCD (its L2 keeps the input tile for all of them).
+// the same XCD (its L2 keeps the input tile for all of them).  The next
+// stage's operator and input values are loaded into registers before the
+// current stage's MFMAs; three workgroups fit on a CU (168 VGPRs, 20 KB LDS).
 #include "kernels.hpp"
 #include "pointwise.hpp"
 
@@ -36,7 +38,7 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned h, unsigned G) {
 }
 
 template <bool CONTIG>
-__global__ __launch_bounds__(256) void k_pass_f64(PassF64 a) {
+__global__ __launch_bounds__(256, 3) void k_pass_f64(PassF64 a) {
   __shared__ double sOp[KC][LDP];
   __shared__ double sIn[KC][LDF];
 
@@ -51,18 +53,22 @@ __global__ __launch_bounds__(256) void k_pass_f64(PassF64 a) {
   const int64_t f0 = static_cast<int64_t>(w / nP) * FT;
   const int p0 = pt * PT;
 
-  // staging assignment: two complex elements per stage
-  int fl[2], kl[2];
-  int64_t gbase[2];
+  // staging assignment: NJ complex input elements and NJ operator pairs per
+  // thread and stage (KC/2 complex contraction indices x 64 fibres)
+  constexpr int KCC = KC / 2;
+  constexpr int NJ = KCC * FT / 256;
+  static_assert(NJ * 256 == KCC * FT && NJ * 256 == KC * PT / 2, "stage must split evenly");
+  int fl[NJ], kl[NJ];
+  int64_t gbase[NJ];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int j = 0; j < NJ; ++j) {
     const int e = tid + 256 * j;
     if (CONTIG) {
-      fl[j] = e >> 3;
-      kl[j] = e & 7;
+      fl[j] = e / KCC;
+      kl[j] = e % KCC;
     } else {
-      fl[j] = e & 63;
-      kl[j] = e >> 6;
+      fl[j] = e % FT;
+      kl[j] = e / FT;
     }
     const int64_t f = f0 + fl[j];
     gbase[j] = (f < a.F) ? fibre_base(f, a.R, a.n) : -1;
@@ -75,26 +81,39 @@ __global__ __launch_bounds__(256) void k_pass_f64(PassF64 a) {
     for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
   unsigned flag = 0;
 
+  // the next stage's operator and input values, loaded into registers before
+  // the current stage's MFMAs so that their latency overlaps the math
+  double2 opv[NJ];
+  cd xin[NJ];
+  bool xok[NJ];
+  auto load_stage = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int e = tid + 256 * j;
+      opv[j] = *reinterpret_cast<const double2*>(a.op + (int64_t)(k0 + e / (PT / 2)) * a.Pp + p0 +
+                                                 2 * (e % (PT / 2)));
+      const int k = (k0 >> 1) + kl[j];
+      xok[j] = gbase[j] >= 0 && k < a.n;
+      xin[j] = {0.0, 0.0};
+      if (xok[j]) {
+        const double2 v =
+            *reinterpret_cast<const double2*>(a.in0 + 2 * (gbase[j] + a.R * (int64_t)k));
+        xin[j] = {v.x, v.y};
+      }
+    }
+  };
+
+  load_stage(0);
   for (int k0 = 0; k0 < a.Kp; k0 += KC) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < NJ; ++j) {
       const int e = tid + 256 * j;
-      const int kr = e >> 5;
-      const int c2 = e & 31;
-      const double2 v =
-          *reinterpret_cast<const double2*>(a.op + (int64_t)(k0 + kr) * a.Pp + p0 + 2 * c2);
-      sOp[kr][2 * c2] = v.x;
-      sOp[kr][2 * c2 + 1] = v.y;
-    }
-    const int kc0 = k0 >> 1;
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int k = kc0 + kl[j];
-      cd x = {0.0, 0.0};
-      if (gbase[j] >= 0 && k < a.n) {
-        const int64_t off = gbase[j] + a.R * (int64_t)k;
-        const double2 v = *reinterpret_cast<const double2*>(a.in0 + 2 * off);
-        x = {v.x, v.y};
+      const int kr = e / (PT / 2);
+      const int c2 = e % (PT / 2);
+      sOp[kr][2 * c2] = opv[j].x;
+      sOp[kr][2 * c2 + 1] = opv[j].y;
+      cd x = xin[j];
+      if (xok[j]) {
         if (a.pro == PRO_FLOW) {
           x = half_flow(x, a.nl, flag);
         } else if (a.pro == PRO_G) {
@@ -105,6 +124,7 @@ __global__ __launch_bounds__(256) void k_pass_f64(PassF64 a) {
       sIn[2 * kl[j] + 1][fl[j]] = x.im;
     }
     __syncthreads();
+    if (k0 + KC < a.Kp) load_stage(k0 + KC);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       const int kr = kk + (lane >> 4);

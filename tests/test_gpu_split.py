@@ -110,6 +110,12 @@ def test_split_one_step_gate_c1_full_size():
     assert _one_step_gate(ci.C1, "lawson4") < 1e-6
 
 
+@pytest.mark.parametrize("method", ["strang", "lawson4"])
+def test_split_one_step_gate_c2_full_size(method):
+    """256^3 Dirichlet cubic-quintic, the full grid (the oracle takes ~10 s)."""
+    assert _one_step_gate(ci.C2, method) < 1e-6
+
+
 def test_split_trajectory_error_is_reported():
     p = ci.scaled(ci.C1, (32, 32, 32))
     err = _one_step_gate(p, "lawson4", steps=40)
