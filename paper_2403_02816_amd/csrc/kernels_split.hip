@@ -107,8 +107,9 @@ __device__ __forceinline__ bf16x8 neg8(bf16x8 v) {
 
 // Staging geometry of one thread: FI fibres x KJ consecutive contraction
 // indices.  Contiguous contraction axis: 1 fibre x KS/4 indices (4 threads
-// cover the KS indices of a fibre); strided: 2 adjacent fibres x KS/8 indices
-// (32 threads cover 64 adjacent fibres of one index with 16-byte loads).
+// cover the KS indices of a fibre, 8 consecutive lanes 8 fibres); strided: 2
+// adjacent fibres x KS/8 indices (32 threads cover 64 adjacent fibres of one
+// index with 16-byte loads).
 template <int KS, bool CONTIG>
 struct Stage {
   static constexpr int FI = CONTIG ? 1 : 2;
@@ -164,8 +165,9 @@ __device__ __forceinline__ void split_tile(const PassSplit& a, int pt, int64_t f
   int fl[FI];
   int k0t;
   if (CONTIG) {
-    fl[0] = tid >> 2;
-    k0t = KJ * (tid & 3);
+    // 8 consecutive lanes take 8 fibres (LDS rows) at one index chunk
+    fl[0] = (tid & 7) + 8 * (tid >> 5);
+    k0t = KJ * ((tid >> 3) & 3);
   } else {
     fl[0] = 2 * (tid & 31);
     fl[FI - 1] = fl[0] + 1;
@@ -252,7 +254,7 @@ __device__ __forceinline__ void split_tile(const PassSplit& a, int pt, int64_t f
 #pragma unroll
     for (int j = 0; j < OPCH; ++j) {
       const int c = tid + 256 * j;
-      *reinterpret_cast<u32x4*>(&sA[c / CPS][(c / (KS / 8)) % PT][8 * (c % (KS / 8))]) = opr[j];
+      *reinterpret_cast<u32x4*>(&sA[c / CPS][c % PT][8 * ((c / PT) % (KS / 8))]) = opr[j];
     }
 #pragma unroll
     for (int i = 0; i < FI; ++i) {

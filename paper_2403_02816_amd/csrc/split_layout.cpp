@@ -18,9 +18,11 @@ void build_split_operator(const CMat& M, int PT, int KS, std::vector<uint16_t>& 
       const int pt = static_cast<int>(m / PT), row = static_cast<int>(m % PT);
       const int ks = static_cast<int>(k / KS), kk = static_cast<int>(k % KS);
       uint16_t* b = out.data() + (static_cast<size_t>(pt) * nKS + ks) * block;
+      // within a plane: 16-byte chunk (kk / 8, row) at chunk index (kk / 8) * PT + row
+      const size_t c = static_cast<size_t>(kk / 8) * PT + row;
       for (int t = 0; t < 3; ++t) {
-        b[(static_cast<size_t>(t) * PT + row) * KS + kk] = tr[t];
-        b[(static_cast<size_t>(3 + t) * PT + row) * KS + kk] = ti[t];
+        b[(static_cast<size_t>(t) * PT * KS) + c * 8 + kk % 8] = tr[t];
+        b[(static_cast<size_t>(3 + t) * PT * KS) + c * 8 + kk % 8] = ti[t];
       }
     }
   }

@@ -4,11 +4,13 @@
 // The complex product y = M x is evaluated as four real products
 //   Re y = Re M Re x - Im M Im x,   Im y = Im M Re x + Re M Im x,
 // each operand given as a sum of three bf16 terms.  Layout, in bf16 units:
-//   [p-tile pt < Pp/SPK_P][k-stage ks < Kp/SPK_K][plane q < 6][row < SPK_P][k < SPK_K]
+//   [p-tile pt < Pp/PT][k-stage ks < Kp/KS][plane q < 6][k/8 < KS/8][row < PT][k%8 < 8]
 // with planes q = 0,1,2: terms of Re M; q = 3,4,5: terms of Im M, row = output
 // index m (within the p-tile), k = contraction index j (within the stage);
 // entries beyond n are zero.  One (pt, ks) block is contiguous, so a
-// workgroup copies one stage of its p-tile with plain 16-byte loads.
+// workgroup copies one stage of its p-tile with plain 16-byte loads, and
+// consecutive 16-byte chunks belong to consecutive rows (consecutive lanes
+// write distinct LDS banks).
 #pragma once
 
 #include <cstdint>
