@@ -20,7 +20,7 @@ ARCH = os.environ.get("CGL_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
+          "-ffp-contract=on", "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
 
 def _hipcc() -> str:
