@@ -56,12 +56,15 @@ struct cgl_plan_s {
   unsigned flags = 0;
   hipStream_t ustream = nullptr;  // caller's stream
   hipStream_t gstream = nullptr;  // plan-owned stream used for graph capture/replay
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipStream_t bstream = nullptr;  // plan-owned stream of the second Lawson4 branch
+  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr, ev_join = nullptr;
   bool have_ops[3] = {false, false, false};
   CMat E[3], H[3];
   DeviceOp dE[3], dH[3];
   int tile[3] = {-1, -1, -1};  // split tile shape per direction (autotuned)
-  void* stage[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  // [0], [1]: ping-pong intermediates; [2..4]: Lawson4 stage tensors; [5], [6]:
+  // ping-pong intermediates of the second branch
+  void* stage[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   unsigned* dflag = nullptr;
   unsigned* hflag = nullptr;  // pinned
   std::map<GraphKey, hipGraphExec_t> graphs;
@@ -324,25 +327,34 @@ int build_tables(cgl_plan_s* p) {
   return CGL_OK;
 }
 
-// d passes of one exponential action.  Intermediate results alternate between
-// the ping-pong buffers stage[0] / stage[1]; the last pass applies the
-// epilogue and writes out0 (and out1).  A pass never reads and writes the same
-// buffer: with d = 1 and out0 == in0 the result goes through stage[0].
-int action(cgl_plan_s* p, int which, const void* in0, const void* aux, void* out0, void* out1,
-           int pro, int epi, bool in_f64, bool out_f64, hipStream_t s) {
+// Where an exponential action stands between passes: the tensor the next
+// pass reads and whether it is complex128.
+struct ActionCursor {
+  const void* cur;
+  bool f64;
+};
+
+// Passes [mu0, mu1) of one exponential action.  Intermediate results
+// alternate between the ping-pong buffers of branch br (stage[0] / stage[1],
+// or stage[5] / stage[6]); the first pass applies the prologue, the last pass
+// (mu = d - 1) the epilogue and writes out0 (and out1).  A pass never reads
+// and writes the same buffer: with d = 1 and out0 == in0 the result goes
+// through a ping-pong buffer.
+int action_range(cgl_plan_s* p, int which, ActionCursor& c, const void* aux, void* out0,
+                 void* out1, int pro, int epi, bool out_f64, hipStream_t s, int br, int mu0,
+                 int mu1) {
   // the split form rotates the axis order by one per pass (back to the
   // original after d passes); the FP64 form contracts in place
   const bool rotated = p->precision == CGL_SPLIT_BF16;
-  const void* cur = in0;
-  bool cf64 = in_f64;
-  for (int mu = 0; mu < p->d; ++mu) {
+  void* const* tmp = br == 0 ? &p->stage[0] : &p->stage[5];
+  for (int mu = mu0; mu < mu1; ++mu) {
     const bool last = (mu == p->d - 1);
-    void* dst = last ? out0 : p->stage[mu & 1];
-    const bool via_tmp = last && dst == cur;
-    if (via_tmp) dst = p->stage[0];
+    void* dst = last ? out0 : tmp[mu & 1];
+    const bool via_tmp = last && dst == c.cur;
+    if (via_tmp) dst = tmp[0];
     const bool of64 = last ? out_f64 : false;
-    int st = pass(p, mu, which, cur, aux, dst, out1, mu == 0 ? pro : PRO_NONE,
-                  last ? epi : EPI_NONE, cf64, of64, rotated, s);
+    int st = pass(p, mu, which, c.cur, aux, dst, out1, mu == 0 ? pro : PRO_NONE,
+                  last ? epi : EPI_NONE, c.f64, of64, rotated, s);
     if (st != CGL_OK) return st;
     if (via_tmp) {
       // stage buffers are sized for the caller's element type (see cgl_plan)
@@ -350,10 +362,17 @@ int action(cgl_plan_s* p, int which, const void* in0, const void* aux, void* out
       if (hipMemcpyAsync(out0, dst, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return CGL_EDEVICE;
     }
-    cur = dst;
-    cf64 = of64;
+    c.cur = dst;
+    c.f64 = of64;
   }
   return CGL_OK;
+}
+
+// All d passes of one exponential action on stream s (branch 0 buffers).
+int action(cgl_plan_s* p, int which, const void* in0, const void* aux, void* out0, void* out1,
+           int pro, int epi, bool in_f64, bool out_f64, hipStream_t s) {
+  ActionCursor c{in0, in_f64};
+  return action_range(p, which, c, aux, out0, out1, pro, epi, out_f64, s, 0, 0, p->d);
 }
 
 // Picks the split tile shape of every direction by timing one pass of each
@@ -401,19 +420,47 @@ int enqueue_strang(cgl_plan_s* p, void* u, hipStream_t s) {
   return action(p, CGL_E, u, nullptr, u, nullptr, PRO_FLOW, EPI_FLOW, m, m, s);
 }
 
+// One round of two exponential actions of e^{tau K/2}: a = H in_a -> out_a,
+// and b = H pro(in_b), whose epilogue reads out_a.  The first d - 1 passes of
+// b do not depend on a: they run on the plan's second stream (own ping-pong
+// buffers) while a runs on s; the last pass of b follows both on s.
+int lawson_round(cgl_plan_s* p, const void* in_a, void* out_a, bool a_in64, const void* in_b,
+                 bool b_in64, int pro_b, int epi_b, void* out_b0, void* out_b1, bool b_out64,
+                 hipStream_t s) {
+  if (p->d == 1) {
+    int st = action(p, CGL_H, in_a, nullptr, out_a, nullptr, PRO_NONE, EPI_NONE, a_in64, false, s);
+    if (st == CGL_OK)
+      st = action(p, CGL_H, in_b, out_a, out_b0, out_b1, pro_b, epi_b, b_in64, b_out64, s);
+    return st;
+  }
+  if (hipEventRecord(p->ev_fork, s) != hipSuccess ||
+      hipStreamWaitEvent(p->bstream, p->ev_fork, 0) != hipSuccess)
+    return CGL_EDEVICE;
+  ActionCursor cb{in_b, b_in64};
+  int st = action_range(p, CGL_H, cb, nullptr, nullptr, nullptr, pro_b, EPI_NONE, false,
+                        p->bstream, 1, 0, p->d - 1);
+  const bool recorded = hipEventRecord(p->ev_join, p->bstream) == hipSuccess;
+  if (st == CGL_OK)
+    st = action(p, CGL_H, in_a, nullptr, out_a, nullptr, PRO_NONE, EPI_NONE, a_in64, false, s);
+  // rejoin s even when an enqueue failed, so that a capture can end
+  if (!recorded || hipStreamWaitEvent(s, p->ev_join, 0) != hipSuccess) return CGL_EDEVICE;
+  if (st == CGL_OK)
+    st = action_range(p, CGL_H, cb, out_a, out_b0, out_b1, PRO_NONE, epi_b, b_out64, s, 1,
+                      p->d - 1, p->d);
+  return st;
+}
+
 // Lawson4 (eq. lawson4) with e^{tau K} = e^{tau K/2} e^{tau K/2}: four
-// actions of e^{tau K/2},
-//   P = H u,  Q = H g(u) -> (X, Y) in the epilogue,  H X,  H Y -> u_{n+1},
+// actions of e^{tau K/2} in two rounds,
+//   P = H u,  Q = H g(u) -> (X, Y) in the epilogue;  H X,  H Y -> u_{n+1},
 // where the stage combinations run in the last-pass epilogues.
 int enqueue_lawson4(cgl_plan_s* p, void* u, hipStream_t s) {
   const bool m = master(p);
   void* B0 = p->stage[2];
   void* B1 = p->stage[3];
   void* B2 = p->stage[4];
-  int st = action(p, CGL_H, u, nullptr, B0, nullptr, PRO_NONE, EPI_NONE, m, false, s);
-  if (st == CGL_OK) st = action(p, CGL_H, u, B0, B1, B2, PRO_G, EPI_L4_R1, m, false, s);
-  if (st == CGL_OK) st = action(p, CGL_H, B1, nullptr, B0, nullptr, PRO_NONE, EPI_NONE, false, false, s);
-  if (st == CGL_OK) st = action(p, CGL_H, B2, B0, u, nullptr, PRO_NONE, EPI_L4_R2, false, m, s);
+  int st = lawson_round(p, u, B0, m, u, m, PRO_G, EPI_L4_R1, B1, B2, false, s);
+  if (st == CGL_OK) st = lawson_round(p, B1, B0, false, B2, false, PRO_NONE, EPI_L4_R2, u, nullptr, m, s);
   return st;
 }
 
@@ -495,10 +542,13 @@ int create_plan(cgl_plan_t* out, int d, const int64_t* n, int64_t N, const cgl_c
   p->nl.exact = (c->a4 == 0.0 && c->b4 == 0.0 && !(flags & CGL_FLAG_RK4_FLOW)) ? 1 : 0;
   int st = CGL_OK;
   if (hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&p->bstream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&p->ev_out, hipEventDisableTiming) != hipSuccess)
+      hipEventCreateWithFlags(&p->ev_out, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess)
     st = CGL_EDEVICE;
-  for (int i = 0; i < 5 && st == CGL_OK; ++i)
+  for (int i = 0; i < 7 && st == CGL_OK; ++i)
     if (hipMalloc(&p->stage[i], std::max(stage_bytes(p), user_bytes(p))) != hipSuccess)
       st = CGL_ENOMEM;
   if (st == CGL_OK && hipMalloc(reinterpret_cast<void**>(&p->dflag), 256) != hipSuccess)
@@ -507,7 +557,7 @@ int create_plan(cgl_plan_t* out, int d, const int64_t* n, int64_t N, const cgl_c
     st = CGL_ENOMEM;
   if (st == CGL_OK && hipMemsetAsync(p->dflag, 0, 256, p->ustream) != hipSuccess)
     st = CGL_EDEVICE;
-  for (int i = 0; i < 5 && st == CGL_OK; ++i)
+  for (int i = 0; i < 7 && st == CGL_OK; ++i)
     if (hipMemsetAsync(p->stage[i], 0, std::max(stage_bytes(p), user_bytes(p)), p->ustream) !=
         hipSuccess)
       st = CGL_EDEVICE;
@@ -872,6 +922,7 @@ void cgl_destroy(cgl_plan_t p) {
   if (!p) return;
   if (p->ustream) (void)hipStreamSynchronize(p->ustream);
   if (p->gstream) (void)hipStreamSynchronize(p->gstream);
+  if (p->bstream) (void)hipStreamSynchronize(p->bstream);
   (void)hipDeviceSynchronize();
   for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
   p->graphs.clear();
@@ -888,7 +939,10 @@ void cgl_destroy(cgl_plan_t p) {
   if (p->hflag) (void)hipHostFree(p->hflag);
   if (p->ev_in) (void)hipEventDestroy(p->ev_in);
   if (p->ev_out) (void)hipEventDestroy(p->ev_out);
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
   if (p->gstream) (void)hipStreamDestroy(p->gstream);
+  if (p->bstream) (void)hipStreamDestroy(p->bstream);
   delete p;
 }
 
