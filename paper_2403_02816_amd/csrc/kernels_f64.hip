@@ -144,7 +144,24 @@ __global__ __launch_bounds__(256, 3) void k_pass_f64(PassF64 a) {
 
   // epilogue: the accumulator of lane l holds rows g + 4r (g = l/16, r < 4)
   // of a 16-row block b; the host's row permutation makes registers (0, 1)
-  // the (re, im) of output m = 8b + g and registers (2, 3) those of m + 4
+  // the (re, im) of output m = 8b + g and registers (2, 3) those of m + 4.
+  // For the Lawson4 combinations the 8 auxiliary values of the lane are
+  // loaded before the first store (stores could alias them).
+  const bool lawson = a.epi == EPI_L4_R1 || a.epi == EPI_L4_R2;
+  double2 xa[2][2][2];
+#pragma unroll
+  for (int pb = 0; pb < 2; ++pb)
+#pragma unroll
+    for (int fb = 0; fb < 2; ++fb)
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        const int m = 8 * ((p0 + wp * 32 + pb * 16) >> 4) + (lane >> 4) + 4 * hh;
+        const int64_t f = f0 + wf * 32 + fb * 16 + (lane & 15);
+        xa[pb][fb][hh] = double2{0.0, 0.0};
+        if (lawson && f < a.F && m < a.n)
+          xa[pb][fb][hh] = *reinterpret_cast<const double2*>(
+              a.aux + 2 * (fibre_base(f, a.R, a.n) + a.R * (int64_t)m));
+      }
 #pragma unroll
   for (int pb = 0; pb < 2; ++pb) {
 #pragma unroll
@@ -166,8 +183,7 @@ __global__ __launch_bounds__(256, 3) void k_pass_f64(PassF64 a) {
           if (!finite2(z)) flag |= FLAG_NONFINITE;
           *reinterpret_cast<double2*>(a.out0 + off) = double2{z.re, z.im};
         } else {
-          const double2 q = *reinterpret_cast<const double2*>(a.aux + off);
-          const cd x = {q.x, q.y};
+          const cd x = {xa[pb][fb][hh].x, xa[pb][fb][hh].y};
           if (a.epi == EPI_L4_R1) {  // y = Q, x = P
             cd X, Y;
             lawson_r1(x, y, a.nl, X, Y);

@@ -321,25 +321,50 @@ __device__ __forceinline__ void split_tile(const PassSplit& a, int pt, int64_t f
 
   // ---- epilogue: in each block, lane holds rows 8q + 4(lane/32) + s (q, s < 4)
   // of fibre column lane%32; the output (and aux) use the output stride
-  const int64_t f = f0 + wf * 32 + (lane & 31);
-  if (f < a.F) {
-    const int64_t base = fibre_base(f, a.R_out, a.n);
+  if (a.epi == EPI_NONE) {
+    const int64_t f = f0 + wf * 32 + (lane & 31);
+    if (f < a.F) {
+      const int64_t base = fibre_base(f, a.R_out, a.n);
 #pragma unroll
-    for (int b = 0; b < PB; ++b) {
+      for (int b = 0; b < PB; ++b)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int m = pt * PT + wp * (PT / 2) + b * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        if (m >= a.n) continue;
-        const int64_t off = base + a.R_out * (int64_t)m;
-        if (a.epi == EPI_NONE) {
+        for (int r = 0; r < 16; ++r) {
+          const int m = pt * PT + wp * (PT / 2) + b * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          if (m >= a.n) continue;
+          const int64_t off = base + a.R_out * (int64_t)m;
           if (of64)
             reinterpret_cast<double2*>(a.out0)[off] =
                 double2{static_cast<double>(accr[b][r]), static_cast<double>(acci[b][r])};
           else
             reinterpret_cast<float2*>(a.out0)[off] = float2{accr[b][r], acci[b][r]};
-          continue;
         }
-        const cd y = {static_cast<double>(accr[b][r]), static_cast<double>(acci[b][r])};
+    }
+  } else {
+    // pointwise epilogues (flow, Lawson4 combinations) are long FP64 code:
+    // the accumulators go through LDS, 64 rows at a time, and one copy of
+    // the code runs in a loop over the elements (consecutive threads take
+    // consecutive fibres of one row)
+    constexpr int EP = FT + 1;  // row pitch in float2
+    static_assert(64 * EP * 8 <= static_cast<int>(sizeof(Lds<PT, KS>)), "epilogue staging fits");
+    float2* sE = reinterpret_cast<float2*>(&lds);
+#pragma unroll
+    for (int b = 0; b < PB; ++b) {
+      // rows wp * (PT / 2) + b * 32 + [0, 32) of the tile -> LDS rows wp * 32 + [0, 32)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int lr = wp * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        sE[lr * EP + wf * 32 + (lane & 31)] = float2{accr[b][r], acci[b][r]};
+      }
+      __syncthreads();
+#pragma unroll 1
+      for (int e = tid; e < 64 * FT; e += 256) {
+        const int lr = e / FT, fc = e % FT;
+        const int m = pt * PT + (lr / 32) * (PT / 2) + b * 32 + (lr % 32);
+        const int64_t f = f0 + fc;
+        if (m >= a.n || f >= a.F) continue;
+        const int64_t off = fibre_base(f, a.R_out, a.n) + a.R_out * (int64_t)m;
+        const float2 v = sE[lr * EP + fc];
+        const cd y = {static_cast<double>(v.x), static_cast<double>(v.y)};
         if (a.epi == EPI_FLOW) {
           const cd z = half_flow(y, a.nl, flag);
           if (!finite2(z)) flag |= FLAG_NONFINITE;
@@ -358,6 +383,9 @@ __device__ __forceinline__ void split_tile(const PassSplit& a, int pt, int64_t f
           }
         }
       }
+      // LDS is read here until every thread is done: the next block, or the
+      // next work item of a persistent grid, stages into it afterwards
+      __syncthreads();
     }
   }
   if (flag) atomicOr(a.flag, flag);

@@ -1,0 +1,86 @@
+"""Edge cases on the GPU: the largest direction a plan accepts (n = 4096)
+beside the smallest (n = 3), zero-step calls, and the linear equation
+(g = 0), where every step of either method is exactly the exponential
+action e^{tau K} (eq. Strang and eq. lawson4 with g = 0)."""
+import numpy as np
+import pytest
+
+import cgl_inputs as ci
+from oracle import tensor
+from tests._util import log, rel_l2, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+def test_largest_and_smallest_direction(precision):
+    torch = require_gpu()
+    from paper_2403_02816_amd import cgl
+    shape = (4096, 3)
+    p = cgl.Plan(shape, ci.C0.coeffs, 0.01, precision=precision)
+    M = []
+    for mu, n in enumerate(shape):
+        E = ci.random_complex((n, n), 70 + mu) / np.sqrt(n)
+        H = ci.random_complex((n, n), 80 + mu) / np.sqrt(n)
+        p.set_exponentials(mu, E, H)
+        M.append(H)
+    U = ci.random_complex(shape, 90)
+    if precision == "split":
+        U = U.astype(np.complex64).astype(np.complex128)
+    x = p.to_device(U, dtype=p.stage_dtype)
+    out = torch.empty_like(x)
+    # split form: the 1e-6 bound holds for contraction lengths up to 256; an
+    # FP32 accumulator that takes ~3n/4 additions (the six term products of
+    # the four real products per 16-deep MFMA) drifts like u sqrt(3n/4),
+    # u = 6e-8, so for n = 4096 the bound scales by sqrt(4096 / 256) = 4
+    for mu in range(2):
+        tol = 1e-13 if precision == "fp64" else 1e-6 * max(1.0, np.sqrt(shape[mu] / 256))
+        p.mode_product(mu, 1, x, out)
+        torch.cuda.synchronize()
+        err = rel_l2(p.to_host(out), tensor.mode_product(U, M[mu], mu))
+        log(f"{precision} (4096, 3) mode {mu}: {err:.2e} (bound {tol:.0e})")
+        assert err < tol
+    p.tucker(1, x, out)
+    torch.cuda.synchronize()
+    tol = 1e-13 if precision == "fp64" else 4e-6
+    assert rel_l2(p.to_host(out), tensor.tucker(U, M)) < tol
+    p.destroy()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+def test_zero_steps_leave_the_state_unchanged(precision):
+    torch = require_gpu()
+    from tests._util import make_plan
+    p = ci.scaled(ci.C0, (20, 24))
+    plan = make_plan(p, precision)
+    u = plan.to_device(ci.initial_state(p))
+    v = u.clone()
+    plan.step_strang(u, 0)
+    plan.step_lawson4(u, 0)
+    assert plan.run("lawson4", u, 0) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(u, v)
+    plan.destroy()
+
+
+@pytest.mark.parametrize("method", ["strang", "lawson4"])
+def test_linear_equation_steps_are_the_exponential_action(method):
+    torch = require_gpu()
+    from paper_2403_02816_amd import cgl
+    c = ci.Coeffs(1.0, 0.7, 0.3, 0.0, 0.0)  # g = 0
+    n = (30, 26, 22)
+    plan = cgl.Plan(n, c, 0.01, precision="fp64")
+    plan.set_fd_operators(-10.0, 10.0, ci.DIRICHLET, c)
+    u0 = ci.random_complex(n, 5)
+    u = plan.to_device(u0)
+    getattr(plan, f"step_{method}")(u, 3)
+    torch.cuda.synchronize()
+    H = [plan.get_operator(mu, 1) for mu in range(3)]
+    E = [h @ h for h in H] if method == "lawson4" else [plan.get_operator(mu, 0) for mu in range(3)]
+    ref = u0
+    for _ in range(3):
+        ref = tensor.tucker(ref, E)
+    err = rel_l2(plan.to_host(u), ref)
+    log(f"linear {method}: {err:.2e}")
+    assert err < 1e-13
+    plan.destroy()
