@@ -33,7 +33,7 @@ MI355X_PEAK_HBM_GBS = 8000.0
 # rocprofv3 counter runs (FETCH_SIZE x 2 + WRITE_SIZE, scale factors measured
 # on a 256 MiB device copy; profiles/split_pass_c1_128_lawson4.md), valid for
 # the kernel sources whose digest is recorded with them.
-SPLIT_TRAFFIC_C1 = {"bytes_per_launch": 38767749.0, "sources_sha256_16": "be8332ecc740c6d5"}
+SPLIT_TRAFFIC_C1 = {"bytes_per_launch": 38381829.0, "sources_sha256_16": "91f89ff56fc49337"}
 SPLIT_SOURCES = ("kernels_split.hip", "kernels.hpp", "pointwise.hpp", "split_layout.cpp",
                  "split_layout.hpp")
 
@@ -56,7 +56,9 @@ def parse():
                     choices=["c1", "c2_strang", "c2_lawson4", "c3", "c4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    ap.add_argument("--cpu-budget-s", type=float, default=12.0,
+                    help="host time spent on the oracle baseline (whole steps)")
+    ap.add_argument("--cpu-max-steps", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (a kernel of known "
                          "traffic for scaling HBM counters)")
@@ -134,27 +136,25 @@ def _cores():
         return int(os.cpu_count())
 
 
-def cpu_baseline(p, method, nsteps):
+def cpu_baseline(p, method, budget_s, max_steps):
     """The FP64 oracle (as written: six exponential actions per Lawson4 step)
-    timed on the host cores on a bounded sample of steps."""
+    timed on the host cores on a bounded sample of full-grid steps: steps
+    until the time budget is spent (at least one, at most max_steps)."""
     import cgl_inputs as ci
     from oracle import steppers
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
-    except Exception:
-        cores = os.cpu_count()
     E = steppers.operators_for(p, p.tau)
     H = steppers.operators_for(p, 0.5 * p.tau)
     nl = steppers.CGLNonlinearity(p.coeffs.as_tuple())
     step = steppers.make_step(method, E, H, p.tau, nl)
     u = ci.initial_state(p)
     u = step(u)  # warm-up step
+    nsteps = 0
     t0 = time.perf_counter()
-    for _ in range(nsteps):
+    while nsteps < max_steps and (nsteps == 0 or time.perf_counter() - t0 < budget_s):
         u = step(u)
+        nsteps += 1
     dt = time.perf_counter() - t0
-    return {"value": p.N * nsteps / dt, "unit": "grid-point-steps/s", "cores": int(cores),
+    return {"value": p.N * nsteps / dt, "unit": "grid-point-steps/s", "cores": _cores(),
             "kind": "oracle",
             "sample": f"{nsteps} {method} steps of the full {'x'.join(map(str, p.n))} grid "
                       f"(numpy FP64, literal scheme), after 1 warm-up step; {dt:.2f} s"}
@@ -473,7 +473,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(p, method, args.cpu_sample_steps)
+        cpu = cpu_baseline(p, method, args.cpu_budget_s, args.cpu_max_steps)
 
     traffic = None
     if args.workload == "c1" and split_sources_digest() == SPLIT_TRAFFIC_C1["sources_sha256_16"]:
