@@ -78,21 +78,44 @@ __global__ __launch_bounds__(NT) void k_conv(ConvArgs a, int ntiles) {
     const int cb = t % ncb, rb = (t / ncb) % nrb, s = t / (ncb * nrb);
     const int c0 = cb * TW, r0 = rb * TR;
     __syncthreads();  // weights staged / previous tile's halo no longer read
-    for (int i = tid; i < XPOS * XROWS * NG; i += NT) {
-      const int pos = i % XPOS, rr = (i / XPOS) % XROWS, grp = i / (XPOS * XROWS);
-      const int gi1 = c0 + pos - 1, gi2 = r0 + rr - 1;
-      const bool in = gi1 >= 0 && gi1 < n1 && gi2 >= 0 && gi2 < n2;
-      float v[8];
+    // the halo in items of two adjacent image columns (starting at an even
+    // column: one 8-byte load per channel, the pair entirely inside or
+    // outside the image) x 8 channels; all loads of a thread are issued
+    // before its LDS stores
+    {
+      constexpr int NPAIR = TW / 2 + 2;  // columns c0 - 2 .. c0 + TW + 1
+      constexpr int ITEMS = NPAIR * XROWS * NG;
+      constexpr int IT = (ITEMS + NT - 1) / NT;
+      f32x2 v[IT][8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int ci = grp * 8 + e;
-        v[e] = 0.0f;
-        if (in && ci < a.cin)
-          v[e] = a.x[(static_cast<int64_t>(s) * a.cin + ci) * P + static_cast<int64_t>(gi2) * n1 + gi1];
+      for (int it = 0; it < IT; ++it) {
+        const int i = tid + it * NT;
+        const int pr = i % NPAIR, rr = (i / NPAIR) % XROWS, grp = i / (NPAIR * XROWS);
+        const int gi1 = c0 + 2 * pr - 2, gi2 = r0 + rr - 1;
+        const bool in = i < ITEMS && gi1 >= 0 && gi1 < n1 && gi2 >= 0 && gi2 < n2;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int ci = grp * 8 + e;
+          v[it][e] = f32x2{0.0f, 0.0f};
+          if (in && ci < a.cin)
+            v[it][e] = *reinterpret_cast<const f32x2*>(
+                a.x + (static_cast<int64_t>(s) * a.cin + ci) * P + static_cast<int64_t>(gi2) * n1 + gi1);
+        }
       }
-      const u32x4 pk = {pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]), pack_bf16(v[4], v[5]),
-                        pack_bf16(v[6], v[7])};
-      *reinterpret_cast<u32x4*>(&sX[(rr * XPOS + pos) * XS + grp * 8]) = pk;
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int i = tid + it * NT;
+        if (i >= ITEMS) continue;
+        const int pr = i % NPAIR, rr = (i / NPAIR) % XROWS, grp = i / (NPAIR * XROWS);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int pos = 2 * pr - 1 + h;  // LDS position of image column c0 + pos - 1
+          if (pos < 0 || pos >= XPOS) continue;
+          const u32x4 pk = {pack_bf16(v[it][0][h], v[it][1][h]), pack_bf16(v[it][2][h], v[it][3][h]),
+                            pack_bf16(v[it][4][h], v[it][5][h]), pack_bf16(v[it][6][h], v[it][7][h])};
+          *reinterpret_cast<u32x4*>(&sX[(rr * XPOS + pos) * XS + grp * 8]) = pk;
+        }
+      }
     }
     __syncthreads();
 
@@ -206,37 +229,64 @@ __global__ __launch_bounds__(NT) void k_wgrad(WgradArgs a, float* part, int ntil
     const int cb = t % ncb, rb = (t / ncb) % nrb, s = t / (ncb * nrb);
     const int c0 = cb * TW, r0 = rb * TR;
     __syncthreads();
-    // dout tile [co][TR * TW], 8 pixels per item
-    for (int i = tid; i < MB * 16 * TR * (TW / 8); i += NT) {
-      const int c8 = i % (TW / 8), rr = (i / (TW / 8)) % TR, co = i / (TR * (TW / 8));
-      const int gi2 = r0 + rr;
-      float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      if (co < a.cout && gi2 < n2) {
-        const float* src = a.dout + (static_cast<int64_t>(s) * a.cout + co) * P +
-                           static_cast<int64_t>(gi2) * n1 + c0 + c8 * 8;
-        const f32x4 lo = *reinterpret_cast<const f32x4*>(src);
-        const f32x4 hi = *reinterpret_cast<const f32x4*>(src + 4);
-        v[0] = lo[0]; v[1] = lo[1]; v[2] = lo[2]; v[3] = lo[3];
-        v[4] = hi[0]; v[5] = hi[1]; v[6] = hi[2]; v[7] = hi[3];
+    // dout tile [co][TR * TW], 8 pixels per item; all loads of a thread are
+    // issued before its LDS stores
+    {
+      constexpr int ITEMS = MB * 16 * TR * (TW / 8);
+      constexpr int IT = (ITEMS + NT - 1) / NT;
+      f32x4 lo[IT], hi[IT];
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int i = tid + it * NT;
+        const int c8 = i % (TW / 8), rr = (i / (TW / 8)) % TR, co = i / (TR * (TW / 8));
+        const int gi2 = r0 + rr;
+        lo[it] = hi[it] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (i < ITEMS && co < a.cout && gi2 < n2) {
+          const float* src = a.dout + (static_cast<int64_t>(s) * a.cout + co) * P +
+                             static_cast<int64_t>(gi2) * n1 + c0 + c8 * 8;
+          lo[it] = *reinterpret_cast<const f32x4*>(src);
+          hi[it] = *reinterpret_cast<const f32x4*>(src + 4);
+        }
       }
-      const u32x4 pk = {pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]), pack_bf16(v[4], v[5]),
-                        pack_bf16(v[6], v[7])};
-      *reinterpret_cast<u32x4*>(&sD[co * DS + rr * TW + c8 * 8]) = pk;
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int i = tid + it * NT;
+        if (i >= ITEMS) continue;
+        const int c8 = i % (TW / 8), rr = (i / (TW / 8)) % TR, co = i / (TR * (TW / 8));
+        const u32x4 pk = {pack_bf16(lo[it][0], lo[it][1]), pack_bf16(lo[it][2], lo[it][3]),
+                          pack_bf16(hi[it][0], hi[it][1]), pack_bf16(hi[it][2], hi[it][3])};
+        *reinterpret_cast<u32x4*>(&sD[co * DS + rr * TW + c8 * 8]) = pk;
+      }
     }
-    // input halo [ci][XR rows][image columns c0 - 2 .. c0 + TW + 1], in pairs
-    constexpr int NPAIR = TW / 2 + 2;
-    for (int i = tid; i < CIN_PAD * XR * NPAIR; i += NT) {
-      const int pr = i % NPAIR, rr = (i / NPAIR) % XR, ci = i / (NPAIR * XR);
-      const int j = 2 * pr - 2;  // tile-relative column of the pair's first element
-      const int gi2 = r0 + rr - 1;
-      float v0 = 0.f, v1 = 0.f;
-      if (ci < a.cin && gi2 >= 0 && gi2 < n2) {
-        const float* row = a.x + (static_cast<int64_t>(s) * a.cin + ci) * P + static_cast<int64_t>(gi2) * n1;
-        const int gi1 = c0 + j;
-        if (gi1 >= 0 && gi1 < n1) v0 = row[gi1];
-        if (gi1 + 1 >= 0 && gi1 + 1 < n1) v1 = row[gi1 + 1];
+    // input halo [ci][XR rows][image columns c0 - 2 .. c0 + TW + 1] in pairs
+    // starting at even columns (one 8-byte load each; a pair is either inside
+    // the image or outside it, as n1 is a multiple of TW), in chunks of CH
+    // pairs per thread whose loads are issued before their stores
+    {
+      constexpr int NPAIR = TW / 2 + 2;
+      constexpr int ITEMS = CIN_PAD * XR * NPAIR;
+      constexpr int CH = 8;
+      for (int base = 0; base < ITEMS; base += CH * NT) {
+        f32x2 v[CH];
+#pragma unroll
+        for (int it = 0; it < CH; ++it) {
+          const int i = base + tid + it * NT;
+          const int pr = i % NPAIR, rr = (i / NPAIR) % XR, ci = i / (NPAIR * XR);
+          const int gi1 = c0 + 2 * pr - 2, gi2 = r0 + rr - 1;
+          v[it] = f32x2{0.f, 0.f};
+          if (i < ITEMS && ci < a.cin && gi2 >= 0 && gi2 < n2 && gi1 >= 0 && gi1 < n1)
+            v[it] = *reinterpret_cast<const f32x2*>(
+                a.x + (static_cast<int64_t>(s) * a.cin + ci) * P + static_cast<int64_t>(gi2) * n1 + gi1);
+        }
+#pragma unroll
+        for (int it = 0; it < CH; ++it) {
+          const int i = base + tid + it * NT;
+          if (i >= ITEMS) continue;
+          const int pr = i % NPAIR, rr = (i / NPAIR) % XR, ci = i / (NPAIR * XR);
+          reinterpret_cast<unsigned*>(sX)[((ci * XR + rr) * XW + 8 + 2 * pr - 2) / 2] =
+              pack_bf16(v[it][0], v[it][1]);
+        }
       }
-      reinterpret_cast<unsigned*>(sX)[((ci * XR + rr) * XW + 8 + j) / 2] = pack_bf16(v0, v1);
     }
     __syncthreads();
 
