@@ -367,7 +367,20 @@ def bench_surrogate(args):
         torch.cuda.synchronize()
         tp = time.perf_counter() - t0
         err = float(torch.linalg.vector_norm(ua - ub).item() / torch.linalg.vector_norm(ub).item())
-        rows.append((stats, tg, tp, err))
+        # the plain FP64 form to the same time, from the same state
+        p64 = cgl.Plan(p.n, p.coeffs, p.tau, precision="fp64")
+        p64.set_fd_operators(p.a, p.b, p.bc, p.coeffs)
+        uf = u.to(torch.complex128)
+        p64.run("lawson4", uf.clone(), M)  # graph and launch setup
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        assert p64.run("lawson4", uf, JUMPS * M) == 0
+        torch.cuda.synchronize()
+        tf = time.perf_counter() - t0
+        e64 = float(torch.linalg.vector_norm(ua.to(torch.complex128) - uf).item()
+                    / torch.linalg.vector_norm(uf).item())
+        p64.destroy()
+        rows.append((stats, tg, tp, err, tf, e64))
         plan.destroy()
     net.destroy()
     tg = sum(r[1] for r in rows)
@@ -396,6 +409,8 @@ def bench_surrogate(args):
                       "gated_ms": 1e3 * tg / len(rows), "plain_ms": 1e3 * tp / len(rows),
                       "gain_vs_plain": tp / tg, "accepted_fraction": acc,
                       "final_rel_l2_vs_plain_max": max(r[3] for r in rows),
+                      "fp64_plain_ms": 1e3 * sum(r[4] for r in rows) / len(rows),
+                      "final_rel_l2_vs_fp64_plain_max": max(r[5] for r in rows),
                       "stats": [r[0] for r in rows]},
         "cpu_baseline": cpu,
     }

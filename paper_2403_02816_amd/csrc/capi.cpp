@@ -302,17 +302,38 @@ int build_tables(cgl_plan_s* p) {
                           reinterpret_cast<void**>(&p->dinst[mu]));
     if (st != CGL_OK) return st;
     for (int t = 0; t < SPLIT_NTILES; ++t) {
-      std::vector<std::pair<int, BatchTile>> order;
+      // Groups of work items that read the same operator rows (the fibre
+      // tiles of one row tile of one instance), largest contraction first,
+      // each put in the shortest of XCDS columns; the table interleaves the
+      // columns (entry XCDS * r + x = item r of column x).  Workgroup w runs
+      // on XCD w % XCDS and takes entries w, w + G, ..., so the items of a
+      // group run at about the same time on one XCD and share its L2.
+      constexpr int XCDS = 8;
+      std::vector<std::pair<int, std::vector<BatchTile>>> groups;
       for (int j = 0; j < p->batch; ++j) {
         const int nP = inst[j].Pp[t] / SPLIT_TILES[t].PT;
         const int nF = (inst[j].F + SP_FT - 1) / SP_FT;
-        for (int pt = 0; pt < nP; ++pt)
-          for (int ft = 0; ft < nF; ++ft) order.push_back({inst[j].Kp[t], BatchTile{j, pt, ft}});
+        for (int pt = 0; pt < nP; ++pt) {
+          std::vector<BatchTile> g;
+          for (int ft = 0; ft < nF; ++ft) g.push_back(BatchTile{j, pt, ft});
+          groups.push_back({inst[j].Kp[t], std::move(g)});
+        }
       }
-      std::stable_sort(order.begin(), order.end(),
+      std::stable_sort(groups.begin(), groups.end(),
                        [](const auto& x, const auto& y) { return x.first > y.first; });
+      std::vector<std::vector<BatchTile>> col(XCDS);
+      for (auto& g : groups) {
+        size_t x = 0;
+        for (size_t c = 1; c < col.size(); ++c)
+          if (col[c].size() < col[x].size()) x = c;
+        for (auto& it : g.second) col[x].push_back(it);
+      }
+      size_t rows = 0;
+      for (auto& c : col) rows = std::max(rows, c.size());
       std::vector<BatchTile> tl;
-      for (auto& o : order) tl.push_back(o.second);
+      for (size_t r = 0; r < rows; ++r)
+        for (int x = 0; x < XCDS; ++x)
+          tl.push_back(r < col[x].size() ? col[x][r] : BatchTile{-1, 0, 0});  // -1: no work
       p->ntiles[mu][t] = static_cast<int>(tl.size());
       st = upload_bytes(p, tl.data(), tl.size() * sizeof(BatchTile),
                         reinterpret_cast<void**>(&p->dtiles[mu][t]));

@@ -116,7 +116,7 @@ struct BatchInstance {
 };
 
 struct BatchTile {
-  int inst, pt, ft;
+  int inst, pt, ft;  // inst < 0: a padding entry (no work)
 };
 
 struct PassBatch {

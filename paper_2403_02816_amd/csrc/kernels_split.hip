@@ -408,6 +408,7 @@ __global__ __launch_bounds__(256, 2) void k_pass_split_batched(PassBatch b) {
   __shared__ __attribute__((aligned(16))) Lds<PT, KS> lds;
   for (int t = blockIdx.x; t < b.ntiles; t += gridDim.x) {
     const BatchTile tl = b.tiles[t];
+    if (tl.inst < 0) continue;  // padding entry of the table
     const BatchInstance& in = b.inst[tl.inst];
     PassSplit a{};
     const size_t esz_in = IN64 ? 16 : 8, esz_out = b.out_f64 ? 16 : 8;
