@@ -302,8 +302,8 @@ int build_tables(cgl_plan_s* p) {
                           reinterpret_cast<void**>(&p->dinst[mu]));
     if (st != CGL_OK) return st;
     for (int t = 0; t < SPLIT_NTILES; ++t) {
-      // Groups of work items that read the same operator rows (the fibre
-      // tiles of one row tile of one instance), largest contraction first,
+      // Groups of work items that read the same operator rows or the same
+      // state tiles (all items of one instance), largest contraction first,
       // each put in the shortest of XCDS columns; the table interleaves the
       // columns (entry XCDS * r + x = item r of column x).  Workgroup w runs
       // on XCD w % XCDS and takes entries w, w + G, ..., so the items of a
@@ -313,11 +313,10 @@ int build_tables(cgl_plan_s* p) {
       for (int j = 0; j < p->batch; ++j) {
         const int nP = inst[j].Pp[t] / SPLIT_TILES[t].PT;
         const int nF = (inst[j].F + SP_FT - 1) / SP_FT;
-        for (int pt = 0; pt < nP; ++pt) {
-          std::vector<BatchTile> g;
-          for (int ft = 0; ft < nF; ++ft) g.push_back(BatchTile{j, pt, ft});
-          groups.push_back({inst[j].Kp[t], std::move(g)});
-        }
+        std::vector<BatchTile> g;
+        for (int ft = 0; ft < nF; ++ft)
+          for (int pt = 0; pt < nP; ++pt) g.push_back(BatchTile{j, pt, ft});
+        groups.push_back({inst[j].Kp[t], std::move(g)});
       }
       std::stable_sort(groups.begin(), groups.end(),
                        [](const auto& x, const auto& y) { return x.first > y.first; });
