@@ -143,6 +143,31 @@ __global__ __launch_bounds__(NT) void k_conv(ConvArgs a, int ntiles) {
 
     const int gi2 = r0 + prow;
     if (gi2 >= n2) continue;
+    // auxiliary inputs of all of this lane's outputs are loaded before the
+    // first store (the stores may alias them, so interleaved they would wait
+    // out one memory latency each)
+    float xa[MB][2][4], xb[MB][2][4];
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int co = m * 16 + g * 4 + r;
+          const int64_t p = static_cast<int64_t>(gi2) * n1 + c0 + pcol[j];
+          const int64_t o = (static_cast<int64_t>(s) * a.cout + co) * P + p;
+          xa[m][j][r] = 0.0f;
+          xb[m][j][r] = 0.0f;
+          if (co >= a.cout) continue;
+          if constexpr (EPI == CEPI_RES) {
+            xa[m][j][r] = a.aux[o];
+          } else if constexpr (EPI == CEPI_OUT) {
+            xa[m][j][r] = a.aux[(static_cast<int64_t>(s) * a.aux_ch + co) * P + p];
+          } else if constexpr (EPI == CEPI_BWD) {
+            if (a.aux) xa[m][j][r] = a.aux[o];
+            if (a.out1) xb[m][j][r] = a.aux2[o];
+          }
+        }
 #pragma unroll
     for (int m = 0; m < MB; ++m)
 #pragma unroll
@@ -161,14 +186,14 @@ __global__ __launch_bounds__(NT) void k_conv(ConvArgs a, int ntiles) {
           } else if constexpr (EPI == CEPI_RES) {
             const float av = v + a.bias[co];
             if (a.out0) a.out0[o] = av;
-            a.out1[o] = a.aux[o] + av * sigmoid_f(av);
+            a.out1[o] = xa[m][j][r] + av * sigmoid_f(av);
           } else if constexpr (EPI == CEPI_OUT) {
-            a.out0[o] = a.aux[(static_cast<int64_t>(s) * a.aux_ch + co) * P + p] + v + a.bias[co];
+            a.out0[o] = xa[m][j][r] + v + a.bias[co];
           } else {
-            const float tot = a.aux ? v + a.aux[o] : v;
+            const float tot = v + xa[m][j][r];
             if (a.out0) a.out0[o] = tot;
             if (a.out1) {
-              const float z = a.aux2[o];
+              const float z = xb[m][j][r];
               const float sg = sigmoid_f(z);
               a.out1[o] = tot * (sg * (1.0f + z * (1.0f - sg)));
             }
