@@ -54,7 +54,8 @@ std::string device_tag() {
 }
 
 int autotune_pick(const std::string& key, int ncand,
-                  const std::function<hipError_t(int)>& launch, hipStream_t s, int reps) {
+                  const std::function<hipError_t(int)>& launch, hipStream_t s, int reps,
+                  const double* weight) {
   {
     std::lock_guard<std::mutex> g(g_mu);
     load_file();
@@ -82,9 +83,17 @@ int autotune_pick(const std::string& key, int ncand,
       if (best_t[c] < 0.0f || ms < best_t[c]) best_t[c] = ms;
     }
   }
+  if (weight)
+    for (int c = 0; c < ncand; ++c)
+      if (best_t[c] >= 0.0f) best_t[c] = static_cast<float>(best_t[c] * weight[c]);
   int best = -1;
   for (int c = 0; c < ncand; ++c)
     if (best_t[c] >= 0.0f && (best < 0 || best_t[c] < best_t[best])) best = c;
+  if (std::getenv("CGL_AUTOTUNE_VERBOSE")) {
+    std::fprintf(stderr, "autotune %s:", key.c_str());
+    for (int c = 0; c < ncand; ++c) std::fprintf(stderr, " %.4f", best_t[c] / reps);
+    std::fprintf(stderr, " -> %d\n", best);
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (best < 0) return 0;

@@ -61,7 +61,9 @@ struct cgl_plan_s {
   bool have_ops[3] = {false, false, false};
   CMat E[3], H[3];
   DeviceOp dE[3], dH[3];
-  int tile[3] = {-1, -1, -1};  // split tile shape per direction (autotuned)
+  // split tile shape per direction and prologue kind (autotuned; batched
+  // plans use tile[mu][PRO_NONE] for every pass)
+  int tile[3][3] = {{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}};
   // [0], [1]: ping-pong intermediates; [2..4]: Lawson4 stage tensors; [5], [6]:
   // ping-pong intermediates of the second branch
   void* stage[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -124,6 +126,8 @@ int upload_bytes(cgl_plan_s* p, const void* h, size_t bytes, void** dst) {
   return CGL_OK;
 }
 
+static_assert(SPLIT_NTILES_BATCHED <= SPLIT_MAX_TILES, "batched instance tables hold the batched tile shapes");
+
 // Upload one exponential in the plan's device form.
 int upload_op(cgl_plan_s* p, const CMat& M, DeviceOp& dst) {
   const int64_t n = M.n;
@@ -153,9 +157,10 @@ int upload_op(cgl_plan_s* p, const CMat& M, DeviceOp& dst) {
     dst.Kp[0] = Kp;
     return upload_bytes(p, h.data(), h.size() * sizeof(double), &dst.ptr[0]);
   }
-  for (int t = 0; t < SPLIT_NTILES; ++t) {
+  const int ntile = p->batch > 0 ? SPLIT_NTILES_BATCHED : SPLIT_NTILES;
+  for (int t = 0; t < ntile; ++t) {
     std::vector<uint16_t> h;
-    build_split_operator(M, SPLIT_TILES[t].PT, SPLIT_TILES[t].KS, h, dst.Pp[t], dst.Kp[t]);
+    build_split_operator(M, SPLIT_TILES[t], h, dst.Pp[t], dst.Kp[t]);
     const int st = upload_bytes(p, h.data(), h.size() * sizeof(uint16_t), &dst.ptr[t]);
     if (st != CGL_OK) return st;
   }
@@ -200,7 +205,9 @@ int pass(cgl_plan_s* p, int mu, int which, const void* in0, const void* aux, voi
     a.aux = aux;
     a.out0 = out0;
     a.out1 = out1;
-    const int t = p->tile[mu] >= 0 ? p->tile[mu] : 0;
+    int t = p->tile[mu][pro] >= 0 ? p->tile[mu][pro] : p->tile[mu][PRO_NONE];
+    if (t < 0) t = 0;
+    if (!rotated && SPLIT_TILES[t].dma) t = 1;  // the direct-to-LDS shapes need a contiguous axis
     a.op = static_cast<const uint16_t*>(op.ptr[t]);
     a.tile = t;
     a.R = rotated ? 1 : R;
@@ -228,7 +235,7 @@ int pass_batched(cgl_plan_s* p, int mu, int which, const void* in0, const void* 
   const int d = p->d;
   if (p->precision == CGL_SPLIT_BF16) {
     if (!p->tables) return CGL_ENOTREADY;
-    const int t = p->tile[mu] >= 0 ? p->tile[mu] : 0;
+    const int t = p->tile[mu][PRO_NONE] >= 0 ? p->tile[mu][PRO_NONE] : 0;
     PassBatch b{};
     b.in0 = in0;
     b.aux = aux;
@@ -290,7 +297,7 @@ int build_tables(cgl_plan_s* p) {
       b.off = p->boff[j];
       b.n = static_cast<int>(p->bn[k]);
       b.F = static_cast<int>(Nj / p->bn[k]);
-      for (int t = 0; t < SPLIT_NTILES; ++t) {
+      for (int t = 0; t < SPLIT_NTILES_BATCHED; ++t) {
         b.Pp[t] = p->bdE[k].Pp[t];
         b.Kp[t] = p->bdE[k].Kp[t];
         b.opE[t] = static_cast<const uint16_t*>(p->bdE[k].ptr[t]);
@@ -301,7 +308,7 @@ int build_tables(cgl_plan_s* p) {
     int st = upload_bytes(p, inst.data(), inst.size() * sizeof(BatchInstance),
                           reinterpret_cast<void**>(&p->dinst[mu]));
     if (st != CGL_OK) return st;
-    for (int t = 0; t < SPLIT_NTILES; ++t) {
+    for (int t = 0; t < SPLIT_NTILES_BATCHED; ++t) {
       // Groups of work items that read the same operator rows or the same
       // state tiles (all items of one instance), largest contraction first,
       // each put in the shortest of XCDS columns; the table interleaves the
@@ -395,42 +402,65 @@ int action(cgl_plan_s* p, int which, const void* in0, const void* aux, void* out
   return action_range(p, which, c, aux, out0, out1, pro, epi, out_f64, s, 0, 0, p->d);
 }
 
-// Picks the split tile shape of every direction by timing one pass of each
-// candidate on the plan's stream (stage buffers as scratch).  Runs outside
-// any graph capture; a no-op for FP64 plans and directions already tuned.
+// Picks the split tile shape of every direction by timing passes of each
+// candidate on the plan's stream (stage buffers as scratch).  The first pass
+// of an action (direction 0) carries the prologue of the stepper (the Strang
+// sub-flow, or g for Lawson4), evaluated once per p-tile workgroup, so it is
+// tuned separately for each prologue kind.  Runs outside any graph capture; a
+// no-op for FP64 plans and choices already made.
 int ensure_tuned(cgl_plan_s* p) {
   if (p->precision != CGL_SPLIT_BF16) return CGL_OK;
   const int bt = build_tables(p);
   if (bt != CGL_OK) return bt;
   // CGL_SPLIT_TILE=<index> fixes the tile shape (tests of every shape, tuning studies)
   const char* forced = std::getenv("CGL_SPLIT_TILE");
+  const int ncand = p->batch > 0 ? SPLIT_NTILES_BATCHED : SPLIT_NTILES;
   for (int mu = 0; mu < p->d; ++mu) {
-    if (p->tile[mu] >= 0) continue;
-    if (forced) {
-      const int t = std::atoi(forced);
-      if (t < 0 || t >= SPLIT_NTILES) return CGL_EINVAL;
-      p->tile[mu] = t;
-      continue;
+    for (int pro : {PRO_NONE, PRO_FLOW, PRO_G}) {
+      if (pro != PRO_NONE && (mu != 0 || p->batch > 0)) continue;
+      if (p->tile[mu][pro] >= 0) continue;
+      if (forced) {
+        const int t = std::atoi(forced);
+        if (t < 0 || t >= ncand) return CGL_EINVAL;
+        p->tile[mu][pro] = t;
+        continue;
+      }
+      std::string key;
+      if (p->batch > 0) {
+        uint64_t h = 1469598103934665603ull;  // FNV-1a over the instance sizes
+        for (int64_t v : p->bn) h = (h ^ static_cast<uint64_t>(v)) * 1099511628211ull;
+        key = device_tag() + ":splitbatch:b" + std::to_string(p->batch) + ":mu" +
+              std::to_string(mu) + ":h" + std::to_string(h);
+      } else {
+        const int64_t n = p->n[mu];
+        key = device_tag() + ":split:n" + std::to_string(n) + ":F" + std::to_string(p->N / n) +
+              ":pro" + std::to_string(pro) + (p->nl.exact ? ":x" : "");
+      }
+      int saved[3];
+      for (int q = 0; q < 3; ++q) saved[q] = p->tile[mu][q];
+      auto launch = [&](int t) -> hipError_t {
+        for (int q = 0; q < 3; ++q) p->tile[mu][q] = t;
+        const int st = pass(p, mu, CGL_H, p->stage[0], nullptr, p->stage[1], nullptr, pro,
+                            EPI_NONE, false, false, true, p->ustream);
+        for (int q = 0; q < 3; ++q) p->tile[mu][q] = saved[q];
+        return st == CGL_OK ? hipSuccess : hipErrorInvalidValue;
+      };
+      // Every p-tile workgroup re-reads and re-splits the state of its fibre
+      // tile.  Timed alone a pass hides that cost (its input stays in
+      // cache); inside a step, where two actions run side by side and every
+      // pass reads what the previous one wrote, it shows: measured at 256^3,
+      // 64 x 16 tiles (4 p-tiles) win a lone pass by 3% and lose the step by
+      // 2-3% to 128 x 16 tiles (2 p-tiles).  Each p-tile beyond the first
+      // therefore counts 4% of the measured time.
+      double weight[SPLIT_NTILES];
+      for (int t = 0; t < ncand; ++t) {
+        const int64_t n = p->batch > 0 ? 0 : p->n[mu];
+        const int64_t np = (n + SPLIT_TILES[t].PT - 1) / SPLIT_TILES[t].PT;
+        weight[t] = 1.0 + 0.04 * static_cast<double>(np > 1 ? np - 1 : 0);
+      }
+      p->tile[mu][pro] = autotune_pick(key + ":t" + std::to_string(SPLIT_NTILES) + ":w4", ncand,
+                                       launch, p->ustream, 8, weight);
     }
-    std::string key;
-    if (p->batch > 0) {
-      uint64_t h = 1469598103934665603ull;  // FNV-1a over the instance sizes
-      for (int64_t v : p->bn) h = (h ^ static_cast<uint64_t>(v)) * 1099511628211ull;
-      key = device_tag() + ":splitbatch:b" + std::to_string(p->batch) + ":mu" +
-            std::to_string(mu) + ":h" + std::to_string(h);
-    } else {
-      const int64_t n = p->n[mu];
-      key = device_tag() + ":split:n" + std::to_string(n) + ":F" + std::to_string(p->N / n);
-    }
-    const int saved = p->tile[mu];
-    auto launch = [&](int t) -> hipError_t {
-      p->tile[mu] = t;
-      const int st = pass(p, mu, CGL_H, p->stage[0], nullptr, p->stage[1], nullptr, PRO_NONE,
-                          EPI_NONE, false, false, true, p->ustream);
-      p->tile[mu] = saved;
-      return st == CGL_OK ? hipSuccess : hipErrorInvalidValue;
-    };
-    p->tile[mu] = autotune_pick(key, SPLIT_NTILES, launch, p->ustream, 8);
   }
   return CGL_OK;
 }

@@ -35,6 +35,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4u __attribute__((ext_vector_type(4), aligned(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -135,6 +136,92 @@ struct Lds {
   unsigned short B[6][FT][PITCH];
 };
 
+// Epilogue of a tile: the accumulators of a wave (PB blocks of 32 x 32; lane
+// holds rows 8q + 4(lane/32) + s (q, s < 4) of fibre column lane%32) written
+// to the output with the output stride, through the pointwise epilogue when
+// there is one.  lds_mem: at least 64 x 65 float2 of workgroup memory that is
+// free (every wave is past its last read of the stage buffers).
+constexpr int EPI_LDS_BYTES = 64 * (SP_FT + 1) * 8;
+
+template <int PT>
+__device__ __forceinline__ void split_epilogue(const PassSplit& a, int pt, int64_t f0,
+                                               f32x16 (&accr)[PT / 64], f32x16 (&acci)[PT / 64],
+                                               unsigned& flag, void* lds_mem) {
+  constexpr int PB = PT / 64;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wp = wave & 1;
+  const int wf = wave >> 1;
+  const bool of64 = a.out_f64 != 0;
+  if (a.epi == EPI_NONE) {
+    const int64_t f = f0 + wf * 32 + (lane & 31);
+    if (f < a.F) {
+      const int64_t base = fibre_base(f, a.R_out, a.n);
+#pragma unroll
+      for (int b = 0; b < PB; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int m = pt * PT + wp * (PT / 2) + b * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          if (m >= a.n) continue;
+          const int64_t off = base + a.R_out * (int64_t)m;
+          if (of64)
+            reinterpret_cast<double2*>(a.out0)[off] =
+                double2{static_cast<double>(accr[b][r]), static_cast<double>(acci[b][r])};
+          else
+            reinterpret_cast<float2*>(a.out0)[off] = float2{accr[b][r], acci[b][r]};
+        }
+    }
+  } else {
+    // pointwise epilogues (flow, Lawson4 combinations) are long FP64 code:
+    // the accumulators go through LDS, 64 rows at a time, and one copy of
+    // the code runs in a loop over the elements (consecutive threads take
+    // consecutive fibres of one row)
+    constexpr int EP = FT + 1;  // row pitch in float2
+    float2* sE = reinterpret_cast<float2*>(lds_mem);
+#pragma unroll
+    for (int b = 0; b < PB; ++b) {
+      // rows wp * (PT / 2) + b * 32 + [0, 32) of the tile -> LDS rows wp * 32 + [0, 32)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int lr = wp * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        sE[lr * EP + wf * 32 + (lane & 31)] = float2{accr[b][r], acci[b][r]};
+      }
+      __syncthreads();
+#pragma unroll 1
+      for (int e = tid; e < 64 * FT; e += 256) {
+        const int lr = e / FT, fc = e % FT;
+        const int m = pt * PT + (lr / 32) * (PT / 2) + b * 32 + (lr % 32);
+        const int64_t f = f0 + fc;
+        if (m >= a.n || f >= a.F) continue;
+        const int64_t off = fibre_base(f, a.R_out, a.n) + a.R_out * (int64_t)m;
+        const float2 v = sE[lr * EP + fc];
+        const cd y = {static_cast<double>(v.x), static_cast<double>(v.y)};
+        if (a.epi == EPI_FLOW) {
+          const cd z = half_flow(y, a.nl, flag);
+          if (!finite2(z)) flag |= FLAG_NONFINITE;
+          store_c(a.out0, off, of64, z);
+        } else {
+          const cd x = load_c(a.aux, off, false);
+          if (a.epi == EPI_L4_R1) {  // y = Q, x = P
+            cd X, Y;
+            lawson_r1(x, y, a.nl, X, Y);
+            store_c(a.out0, off, of64, X);
+            store_c(a.out1, off, of64, Y);
+          } else {  // EPI_L4_R2: y = H Y, x = H X
+            const cd z = lawson_r2(x, y, a.nl);
+            if (!finite2(z)) flag |= FLAG_NONFINITE;
+            store_c(a.out0, off, of64, z);
+          }
+        }
+      }
+      // LDS is read here until every thread is done: the next block, or the
+      // next work item of a persistent grid, stages into it afterwards
+      __syncthreads();
+    }
+  }
+}
+
 // One workgroup tile: output rows [pt*PT, pt*PT + PT) x fibres [f0, f0 + 64)
 // of the pass described by a.  Every thread of the workgroup calls it.
 template <int PT, int KS, bool CONTIG, int PRO, bool IN64>
@@ -157,7 +244,6 @@ __device__ __forceinline__ void split_tile(const PassSplit& a, int pt, int64_t f
   const int nKS = a.Kp / KS;
   const u32x4* opblk =
       reinterpret_cast<const u32x4*>(a.op + static_cast<size_t>(pt) * nKS * (6 * PT * KS));
-  const bool of64 = a.out_f64 != 0;
   // every fibre of the tile exists and every stage is full: no masks needed
   const bool full = (f0 + FT <= a.F) && (a.n % KS == 0);
 
@@ -319,75 +405,202 @@ __device__ __forceinline__ void split_tile(const PassSplit& a, int pt, int64_t f
     __syncthreads();
   }
 
-  // ---- epilogue: in each block, lane holds rows 8q + 4(lane/32) + s (q, s < 4)
-  // of fibre column lane%32; the output (and aux) use the output stride
-  if (a.epi == EPI_NONE) {
-    const int64_t f = f0 + wf * 32 + (lane & 31);
-    if (f < a.F) {
-      const int64_t base = fibre_base(f, a.R_out, a.n);
+  static_assert(EPI_LDS_BYTES <= static_cast<int>(sizeof(Lds<PT, KS>)), "epilogue staging fits");
+  split_epilogue<PT>(a, pt, f0, accr, acci, flag, &lds);
+  if (flag) atomicOr(a.flag, flag);
+}
+
+// ---- Direct-to-LDS variant (contiguous contraction axis, 16-deep stages).
+//
+// The operator planes of a stage are stored in global memory as the exact
+// image of their LDS tile, so they are copied with buffer loads that write
+// LDS directly (no registers, no LDS store instructions).  Both the operator
+// and the state tiles are double-buffered and unpadded; 16-byte chunks are
+// XOR-swizzled by row so that the MFMA operand reads of eight consecutive
+// lanes (eight rows, one chunk) fall on distinct banks.  One barrier per
+// stage: during stage ks the waves read their stage-ks fragments, start the
+// copy of the operator of stage ks + 1 into the other buffer, issue the
+// state loads of stage ks + 2, run the MFMAs, and split the state of stage
+// ks + 1 into the other state buffer.
+template <int PT, int KS>
+struct LdsD {
+  unsigned short A[2][6 * PT * KS];
+  unsigned short B[2][6 * FT * KS];
+};
+
+// position (in 8-element chunks) of chunk c of row `row` in a KS-wide plane
+template <int KS>
+__device__ __forceinline__ int swz_chunk(int row, int c) {
+  return c ^ ((row / (64 / KS)) % (KS / 8));
+}
+
+template <int PT, int KS, int PRO, bool IN64>
+__device__ __forceinline__ void split_tile_dma(const PassSplit& a, int pt, int64_t f0,
+                                               LdsD<PT, KS>& lds) {
+  static_assert(KS == 16, "one 16-deep MFMA step per stage");
+  constexpr int KJ = KS / 4;               // state elements per thread and stage
+  constexpr int PB = PT / 64;              // 32-row blocks per wave
+  constexpr int ABYTES = 12 * PT * KS;     // operator image of one stage
+  constexpr int NDMA = ABYTES / 4096;      // 1 KB copies per wave and stage
+  static_assert(NDMA * 4096 == ABYTES, "operator stage must split evenly");
+  constexpr int ESZ = IN64 ? 16 : 8;
+  constexpr unsigned OOR = 0x80000000u;    // out of range of both buffers
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wp = wave & 1;
+  const int wf = wave >> 1;
+  const int nKS = a.Kp / KS;
+  const __amdgpu_buffer_rsrc_t ors = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint16_t*>(a.op + static_cast<size_t>(pt) * nKS * (6 * PT * KS)), 0,
+      nKS * ABYTES, 0x00020000);
+  // state: 8 consecutive lanes take 8 fibres at one index chunk; the buffer
+  // range ends at the end of the tensor (fibres past F read zero)
+  const int fl = (tid & 7) + 8 * (tid >> 5);
+  const int k0t = KJ * ((tid >> 3) & 3);
+  const int64_t srem = (a.F - f0) * static_cast<int64_t>(a.n) * ESZ;
+  const __amdgpu_buffer_rsrc_t srs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<char*>(reinterpret_cast<const char*>(a.in0) + f0 * static_cast<int64_t>(a.n) * ESZ),
+      0, static_cast<int>(srem < 0x7fffffffll ? srem : 0x7fffffffll), 0x00020000);
+  const unsigned svo = static_cast<unsigned>((fl * a.n + k0t) * ESZ);
+
+  auto copy_op = [&](int ks, int buf) __attribute__((always_inline)) {
+    const unsigned o = ks < nKS ? static_cast<unsigned>(ks * ABYTES) : OOR;
 #pragma unroll
-      for (int b = 0; b < PB; ++b)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int m = pt * PT + wp * (PT / 2) + b * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-          if (m >= a.n) continue;
-          const int64_t off = base + a.R_out * (int64_t)m;
-          if (of64)
-            reinterpret_cast<double2*>(a.out0)[off] =
-                double2{static_cast<double>(accr[b][r]), static_cast<double>(acci[b][r])};
-          else
-            reinterpret_cast<float2*>(a.out0)[off] = float2{accr[b][r], acci[b][r]};
-        }
+    for (int j = 0; j < NDMA; ++j) {
+      const int blk = wave + 4 * j;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          ors, (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(lds.A[buf]) + blk * 1024),
+          16, o + static_cast<unsigned>(blk * 1024 + lane * 16), 0, 0, 0);
     }
-  } else {
-    // pointwise epilogues (flow, Lawson4 combinations) are long FP64 code:
-    // the accumulators go through LDS, 64 rows at a time, and one copy of
-    // the code runs in a loop over the elements (consecutive threads take
-    // consecutive fibres of one row)
-    constexpr int EP = FT + 1;  // row pitch in float2
-    static_assert(64 * EP * 8 <= static_cast<int>(sizeof(Lds<PT, KS>)), "epilogue staging fits");
-    float2* sE = reinterpret_cast<float2*>(&lds);
+  };
+  auto load_state = [&](int ks, f32x4 (&v)[KJ / 2]) __attribute__((always_inline)) {
+    const unsigned o = ks < nKS ? svo + static_cast<unsigned>(ks * KS * ESZ) : OOR;
+#pragma unroll
+    for (int j = 0; j < KJ; j += 2) {
+      if constexpr (IN64) {
+        const double2 x = __builtin_bit_cast(
+            double2, __builtin_amdgcn_raw_buffer_load_b128(srs, o + j * 16, 0, 0));
+        const double2 y = __builtin_bit_cast(
+            double2, __builtin_amdgcn_raw_buffer_load_b128(srs, o + j * 16 + 16, 0, 0));
+        v[j / 2] = f32x4{static_cast<float>(x.x), static_cast<float>(x.y),
+                         static_cast<float>(y.x), static_cast<float>(y.y)};
+      } else {
+        v[j / 2] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(srs, o + j * 8, 0, 0));
+      }
+    }
+  };
+  unsigned flag = 0;
+  // prologue flow, bf16 split and store of the state of stage ks (indices
+  // k >= n, read from the next fibre, become zero)
+  auto store_state = [&](int ks, const f32x4 (&v)[KJ / 2], int buf) __attribute__((always_inline)) {
+    cf w[KJ];
+#pragma unroll
+    for (int j = 0; j < KJ; ++j) {
+      w[j] = cf{v[j / 2][2 * (j % 2)], v[j / 2][2 * (j % 2) + 1]};
+      if (ks * KS + k0t + j >= a.n) w[j] = cf{0.0f, 0.0f};
+      if (PRO == PRO_FLOW) w[j] = half_flow_f(w[j], a.nl, flag);
+      else if (PRO == PRO_G) w[j] = g_cgl_f(w[j], a.nl);
+    }
+    unsigned tr[3][KJ / 2], ti[3][KJ / 2];
+#pragma unroll
+    for (int j = 0; j < KJ; j += 2) {
+      unsigned t3[3];
+      split3x2(w[j].re, w[j + 1].re, t3);
+#pragma unroll
+      for (int t = 0; t < 3; ++t) tr[t][j / 2] = t3[t];
+      split3x2(w[j].im, w[j + 1].im, t3);
+#pragma unroll
+      for (int t = 0; t < 3; ++t) ti[t][j / 2] = t3[t];
+    }
+    const int off = fl * KS + swz_chunk<KS>(fl, k0t / 8) * 8 + k0t % 8;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      store_terms<KJ>(&lds.B[buf][t * FT * KS + off], tr[t]);
+      store_terms<KJ>(&lds.B[buf][(3 + t) * FT * KS + off], ti[t]);
+    }
+  };
+
+  f32x16 accr[PB], acci[PB];
+#pragma unroll
+  for (int b = 0; b < PB; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      accr[b][r] = 0.0f;
+      acci[b][r] = 0.0f;
+    }
+  const int row = lane & 31;
+  const int ch = lane >> 5;  // chunk of the 16-deep step this lane supplies
+
+  // stage ks: fragments of buffer ks % 2, copies into the other buffer
+  auto stage = [&](int ks, f32x4 (&vload)[KJ / 2], const f32x4 (&vstore)[KJ / 2])
+      __attribute__((always_inline)) {
+    const int cur = ks & 1;
+    bf16x8 br[3], bi[3], ar[PB][3], ai[PB][3];
+    {
+      const int rb = wf * 32 + row;
+      const int o = rb * KS + swz_chunk<KS>(rb, ch) * 8;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        br[t] = *reinterpret_cast<const bf16x8*>(&lds.B[cur][t * FT * KS + o]);
+        bi[t] = *reinterpret_cast<const bf16x8*>(&lds.B[cur][(3 + t) * FT * KS + o]);
+      }
+    }
 #pragma unroll
     for (int b = 0; b < PB; ++b) {
-      // rows wp * (PT / 2) + b * 32 + [0, 32) of the tile -> LDS rows wp * 32 + [0, 32)
+      const int ra = wp * (PT / 2) + b * 32 + row;
+      const int o = ra * KS + swz_chunk<KS>(ra, ch) * 8;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int lr = wp * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        sE[lr * EP + wf * 32 + (lane & 31)] = float2{accr[b][r], acci[b][r]};
+      for (int t = 0; t < 3; ++t) {
+        ar[b][t] = *reinterpret_cast<const bf16x8*>(&lds.A[cur][t * PT * KS + o]);
+        ai[b][t] = *reinterpret_cast<const bf16x8*>(&lds.A[cur][(3 + t) * PT * KS + o]);
       }
-      __syncthreads();
-#pragma unroll 1
-      for (int e = tid; e < 64 * FT; e += 256) {
-        const int lr = e / FT, fc = e % FT;
-        const int m = pt * PT + (lr / 32) * (PT / 2) + b * 32 + (lr % 32);
-        const int64_t f = f0 + fc;
-        if (m >= a.n || f >= a.F) continue;
-        const int64_t off = fibre_base(f, a.R_out, a.n) + a.R_out * (int64_t)m;
-        const float2 v = sE[lr * EP + fc];
-        const cd y = {static_cast<double>(v.x), static_cast<double>(v.y)};
-        if (a.epi == EPI_FLOW) {
-          const cd z = half_flow(y, a.nl, flag);
-          if (!finite2(z)) flag |= FLAG_NONFINITE;
-          store_c(a.out0, off, of64, z);
-        } else {
-          const cd x = load_c(a.aux, off, false);
-          if (a.epi == EPI_L4_R1) {  // y = Q, x = P
-            cd X, Y;
-            lawson_r1(x, y, a.nl, X, Y);
-            store_c(a.out0, off, of64, X);
-            store_c(a.out1, off, of64, Y);
-          } else {  // EPI_L4_R2: y = H Y, x = H X
-            const cd z = lawson_r2(x, y, a.nl);
-            if (!finite2(z)) flag |= FLAG_NONFINITE;
-            store_c(a.out0, off, of64, z);
-          }
-        }
-      }
-      // LDS is read here until every thread is done: the next block, or the
-      // next work item of a persistent grid, stages into it afterwards
-      __syncthreads();
     }
+    load_state(ks + 2, vload);
+    copy_op(ks + 1, cur ^ 1);
+    // the copies and loads go out before the MFMAs (the scheduler would sink
+    // them behind the math; the barrier at the end of the stage waits for
+    // them, so they get the whole stage to arrive)
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int b = 0; b < PB; ++b) {
+      bf16x8 an[3];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) an[t] = neg8(ai[b][t]);
+      constexpr int PI[6] = {2, 1, 0, 1, 0, 0};
+      constexpr int PJ[6] = {0, 1, 2, 0, 1, 0};
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const int ti_ = PI[q], tj = PJ[q];
+        accr[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[b][ti_], br[tj], accr[b], 0, 0, 0);
+        acci[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ai[b][ti_], br[tj], acci[b], 0, 0, 0);
+        accr[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an[ti_], bi[tj], accr[b], 0, 0, 0);
+        acci[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[b][ti_], bi[tj], acci[b], 0, 0, 0);
+      }
+    }
+    store_state(ks + 1, vstore, cur ^ 1);
+    __syncthreads();
+  };
+
+  f32x4 sv[2][KJ / 2];
+  copy_op(0, 0);
+  load_state(0, sv[0]);
+  load_state(1, sv[1]);
+  store_state(0, sv[0], 0);
+  __syncthreads();
+  int ks = 0;
+  for (; ks + 1 < nKS; ks += 2) {
+    stage(ks, sv[0], sv[1]);
+    stage(ks + 1, sv[1], sv[0]);
   }
+  if (ks < nKS) stage(ks, sv[0], sv[1]);
+  // the copies issued by the last stage (out of range: zeros) still write
+  // the other operator buffer, which the epilogue reuses
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+  __syncthreads();
+  static_assert(EPI_LDS_BYTES <= static_cast<int>(sizeof(LdsD<PT, KS>)), "epilogue staging fits");
+  split_epilogue<PT>(a, pt, f0, accr, acci, flag, &lds);
   if (flag) atomicOr(a.flag, flag);
 }
 
@@ -398,6 +611,15 @@ __global__ __launch_bounds__(256, 2) void k_pass_split(PassSplit a) {
   const unsigned w = xcd_remap(blockIdx.x, gridDim.x);
   split_tile<PT, KS, CONTIG, PRO, IN64>(a, static_cast<int>(w % nP),
                                        static_cast<int64_t>(w / nP) * FT, lds);
+}
+
+template <int PT, int KS, int PRO, bool IN64>
+__global__ __launch_bounds__(256, 2) void k_pass_split_dma(PassSplit a) {
+  __shared__ __attribute__((aligned(16))) LdsD<PT, KS> lds;
+  const int nP = a.Pp / PT;
+  const unsigned w = xcd_remap(blockIdx.x, gridDim.x);
+  split_tile_dma<PT, KS, PRO, IN64>(a, static_cast<int>(w % nP), static_cast<int64_t>(w / nP) * FT,
+                                    lds);
 }
 
 // Batched form: a persistent grid walks a table of (instance, p-tile, fibre
@@ -460,6 +682,24 @@ void launch_tile(const PassSplit& a, dim3 grid, hipStream_t s) {
     launch_contig<PT, KS, false>(a, grid, s);
 }
 
+template <int PT, int KS, int PRO>
+void launch_dma_pro(const PassSplit& a, dim3 grid, hipStream_t s) {
+  if (a.in_f64)
+    hipLaunchKernelGGL((k_pass_split_dma<PT, KS, PRO, true>), grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_pass_split_dma<PT, KS, PRO, false>), grid, dim3(256), 0, s, a);
+}
+
+template <int PT, int KS>
+void launch_tile_dma(const PassSplit& a, dim3 grid, hipStream_t s) {
+  if (a.pro == PRO_FLOW)
+    launch_dma_pro<PT, KS, PRO_FLOW>(a, grid, s);
+  else if (a.pro == PRO_G)
+    launch_dma_pro<PT, KS, PRO_G>(a, grid, s);
+  else
+    launch_dma_pro<PT, KS, PRO_NONE>(a, grid, s);
+}
+
 }  // namespace
 
 template <int PT, int KS>
@@ -483,7 +723,8 @@ void launch_batched_tile(const PassBatch& b, dim3 grid, hipStream_t s) {
 }
 
 hipError_t launch_pass_split_batched(const PassBatch& b, int nwg, hipStream_t s) {
-  if (b.tile < 0 || b.tile >= SPLIT_NTILES || b.ntiles <= 0 || nwg <= 0) return hipErrorInvalidValue;
+  if (b.tile < 0 || b.tile >= SPLIT_NTILES_BATCHED || b.ntiles <= 0 || nwg <= 0)
+    return hipErrorInvalidValue;
   if (!b.in0 || !b.out0 || !b.inst || !b.tiles || !b.flag) return hipErrorInvalidValue;
   if ((b.epi == EPI_L4_R1 || b.epi == EPI_L4_R2) && !b.aux) return hipErrorInvalidValue;
   if (b.epi == EPI_L4_R1 && !b.out1) return hipErrorInvalidValue;
@@ -510,10 +751,13 @@ hipError_t launch_pass_split(const PassSplit& a, hipStream_t s) {
   const int64_t G = nF * (a.Pp / PT);
   if (G > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 grid(static_cast<unsigned>(G));
-  if (a.tile == 0)
-    launch_tile<64, 32>(a, grid, s);
-  else
-    launch_tile<128, 16>(a, grid, s);
+  if (SPLIT_TILES[a.tile].dma && a.R != 1) return hipErrorInvalidValue;
+  switch (a.tile) {
+    case 0: launch_tile<64, 32>(a, grid, s); break;
+    case 1: launch_tile<128, 16>(a, grid, s); break;
+    case 2: launch_tile_dma<64, 16>(a, grid, s); break;
+    default: launch_tile_dma<128, 16>(a, grid, s); break;
+  }
   return hipGetLastError();
 }
 

@@ -2,8 +2,9 @@
 
 namespace cgl {
 
-void build_split_operator(const CMat& M, int PT, int KS, std::vector<uint16_t>& out, int& Pp,
-                          int& Kp) {
+void build_split_operator(const CMat& M, const SplitTile& tile, std::vector<uint16_t>& out,
+                          int& Pp, int& Kp) {
+  const int PT = tile.PT, KS = tile.KS;
   const int64_t n = M.n;
   Pp = static_cast<int>((n + PT - 1) / PT * PT);
   Kp = static_cast<int>((n + KS - 1) / KS * KS);
@@ -18,8 +19,11 @@ void build_split_operator(const CMat& M, int PT, int KS, std::vector<uint16_t>& 
       const int pt = static_cast<int>(m / PT), row = static_cast<int>(m % PT);
       const int ks = static_cast<int>(k / KS), kk = static_cast<int>(k % KS);
       uint16_t* b = out.data() + (static_cast<size_t>(pt) * nKS + ks) * block;
-      // within a plane: 16-byte chunk (kk / 8, row) at chunk index (kk / 8) * PT + row
-      const size_t c = static_cast<size_t>(kk / 8) * PT + row;
+      // within a plane: 16-byte chunk (kk / 8, row) at chunk index (kk / 8) * PT + row,
+      // or, for the LDS-image layout, row * KS / 8 + (kk / 8 swizzled by row)
+      const size_t c = tile.dma ? static_cast<size_t>(row) * (KS / 8) +
+                                      ((kk / 8) ^ ((row / (64 / KS)) % (KS / 8)))
+                                : static_cast<size_t>(kk / 8) * PT + row;
       for (int t = 0; t < 3; ++t) {
         b[(static_cast<size_t>(t) * PT * KS) + c * 8 + kk % 8] = tr[t];
         b[(static_cast<size_t>(3 + t) * PT * KS) + c * 8 + kk % 8] = ti[t];

@@ -22,16 +22,22 @@ namespace cgl {
 
 constexpr int SPK_Q = 6;  // planes per stage block
 
-// Tile shapes of the split kernel: (rows per workgroup, stage depth).
+// Tile shapes of the split kernel: (rows per workgroup, stage depth, layout).
+// dma = 0: the chunk layout above, staged through registers; dma = 1: each
+// (pt, ks) block is the image of its LDS tile (planes of PT rows x KS, rows
+// unpadded, 16-byte chunk c of row r at position c ^ ((r / (64 / KS)) %
+// (KS / 8))), copied by direct-to-LDS loads (contiguous contraction axis
+// only).  Batched plans use the first SPLIT_NTILES_BATCHED shapes.
 struct SplitTile {
-  int PT, KS;
+  int PT, KS, dma;
 };
-constexpr SplitTile SPLIT_TILES[2] = {{64, 32}, {128, 16}};
-constexpr int SPLIT_NTILES = 2;
+constexpr SplitTile SPLIT_TILES[4] = {{64, 32, 0}, {128, 16, 0}, {64, 16, 1}, {128, 16, 1}};
+constexpr int SPLIT_NTILES = 4;
+constexpr int SPLIT_NTILES_BATCHED = 2;
 
 // Builds the planes of M (3 bf16 terms of Re and Im of every entry) for tile
-// shape (PT, KS); Pp, Kp receive the padded row / contraction counts.
-void build_split_operator(const CMat& M, int PT, int KS, std::vector<uint16_t>& out, int& Pp,
+// shape t; Pp, Kp receive the padded row / contraction counts.
+void build_split_operator(const CMat& M, const SplitTile& t, std::vector<uint16_t>& out, int& Pp,
                           int& Kp);
 
 }  // namespace cgl

@@ -152,6 +152,44 @@ static void steppers(std::vector<int64_t> n, int precision, unsigned flags, cgl_
   cgl_destroy(p);
 }
 
+// The direct-to-LDS tile shapes (2: 64 x 16, 3: 128 x 16) against the
+// register-staged ones with the same row count and 16-deep steps (0: 64 x 32,
+// 1: 128 x 16): the same products in the same order, so Strang and Lawson4
+// steps must agree bit for bit.
+static void dma_tiles_bitwise(std::vector<int64_t> n, unsigned flags, cgl_coeffs c, double a,
+                              double b, int bc) {
+  const int d = static_cast<int>(n.size());
+  int64_t N = 1;
+  for (auto v : n) N *= v;
+  const bool c128 = (flags & CGL_FLAG_FP64_MASTER) != 0;
+  const size_t bytes = static_cast<size_t>(N) * (c128 ? 16 : 8);
+  std::vector<std::vector<unsigned char>> res;
+  for (const char* t : {"0", "2", "1", "3"}) {
+    setenv("CGL_SPLIT_TILE", t, 1);
+    cgl_plan_t p = nullptr;
+    expect(cgl_plan(&p, d, n.data(), &c, 0.005, CGL_SPLIT_BF16, flags, nullptr) == CGL_OK, "plan");
+    for (int mu = 0; mu < d; ++mu) {
+      std::vector<cd> A(n[mu] * n[mu]);
+      expect(cgl_fd_operator(n[mu], a, b, bc, &c, d, reinterpret_cast<double*>(A.data())) == CGL_OK,
+             "fd");
+      expect(cgl_set_operators(p, mu, reinterpret_cast<double*>(A.data())) == CGL_OK, "set");
+    }
+    auto U = rnd(N, 11, 0.3);
+    std::vector<cd> u64 = U;
+    std::vector<std::complex<float>> u32 = cast<float>(U);
+    void* u = c128 ? static_cast<void*>(u64.data()) : static_cast<void*>(u32.data());
+    expect(cgl_step_lawson4(p, u, 2) == CGL_OK, "lawson4");
+    expect(cgl_step_strang(p, u, 1) == CGL_OK, "strang");
+    expect(cgl_status(p) == CGL_OK, "status");
+    const unsigned char* q = static_cast<const unsigned char*>(u);
+    res.emplace_back(q, q + bytes);
+    cgl_destroy(p);
+  }
+  expect(res[0] == res[1], "64-row tiles: direct-to-LDS == register staged");
+  expect(res[2] == res[3], "128-row tiles: direct-to-LDS == register staged");
+  std::printf("  dma tiles bitwise d=%d flags=%u ok\n", d, flags);
+}
+
 static void run_steps(std::vector<int64_t> n, int precision, unsigned flags, cgl_coeffs c,
                       double a, double b, int bc, double tau, int method, int m) {
   const int d = static_cast<int>(n.size());
@@ -391,6 +429,13 @@ int main(int argc, char** argv) {
     kernel_parity({32, 64, 3}, CGL_SPLIT_BF16, 6);
     steppers({32, 64}, CGL_SPLIT_BF16, 0, cub, -10, 10, CGL_DIRICHLET);
     steppers({7, 6, 5}, CGL_SPLIT_BF16, CGL_FLAG_FP64_MASTER, cq, -15, 15, CGL_NEUMANN);
+    const char* keep = std::getenv("CGL_SPLIT_TILE");
+    const std::string saved = keep ? keep : "";
+    dma_tiles_bitwise({32, 64}, 0, cub, -10, 10, CGL_DIRICHLET);     // full tiles
+    dma_tiles_bitwise({20, 9, 7}, 0, cq, -15, 15, CGL_NEUMANN);      // ragged: n % 16, F % 64
+    dma_tiles_bitwise({37}, CGL_FLAG_FP64_MASTER, cub, -10, 10, CGL_DIRICHLET);
+    dma_tiles_bitwise({7, 6, 5}, CGL_FLAG_FP64_MASTER, cq, -15, 15, CGL_NEUMANN);
+    if (keep) setenv("CGL_SPLIT_TILE", saved.c_str(), 1); else unsetenv("CGL_SPLIT_TILE");
   } else {
     // quick: every kernel variant (mu = 1 contiguous, mu > 1 strided, ragged
     // tiles, both precisions) and every stepper path, on small grids

@@ -164,6 +164,45 @@ inline double atomicAdd(double* p, double v) {
   return o;
 }
 
+// raw buffer resource: base address and byte range; each dword of a load at
+// or past the range reads as zero (as the hardware's range check returns)
+struct emu_buffer_rsrc {
+  const char* base;
+  uint32_t num;
+};
+typedef emu_buffer_rsrc __amdgpu_buffer_rsrc_t;
+typedef unsigned emu_u32x4 __attribute__((ext_vector_type(4)));
+inline emu_buffer_rsrc __builtin_amdgcn_make_buffer_rsrc(void* p, short, int num, int) {
+  return {static_cast<const char*>(p), static_cast<uint32_t>(num)};
+}
+inline unsigned emu_buffer_dword(emu_buffer_rsrc r, uint64_t o) {
+  unsigned w = 0;
+  if (o + 4 <= r.num) std::memcpy(&w, r.base + o, 4);
+  return w;
+}
+inline emu_u32x4 __builtin_amdgcn_raw_buffer_load_b128(emu_buffer_rsrc r, unsigned voff, int soff,
+                                                       int) {
+  emu_u32x4 v;
+  for (int i = 0; i < 4; ++i)
+    v[i] = emu_buffer_dword(r, static_cast<uint64_t>(voff) + static_cast<uint64_t>(soff) + 4u * i);
+  return v;
+}
+// buffer load to LDS: lane l of the wave writes its `size` bytes at
+// lds + offset + l * size
+inline void __builtin_amdgcn_raw_ptr_buffer_load_lds(emu_buffer_rsrc r,
+                                                     __attribute__((address_space(3))) void* lds,
+                                                     unsigned size, unsigned voff, unsigned soff,
+                                                     unsigned off, unsigned) {
+  char* d = reinterpret_cast<char*>(reinterpret_cast<uintptr_t>(lds)) + off +
+            (emu::tIdx.x % 64u) * size;
+  for (unsigned i = 0; i < size; i += 4) {
+    const unsigned w = emu_buffer_dword(r, static_cast<uint64_t>(voff) + soff + off + i);
+    std::memcpy(d + i, &w, 4);
+  }
+}
+#define __builtin_amdgcn_sched_barrier(x) ((void)0)
+#define __builtin_amdgcn_s_waitcnt(x) ((void)0)
+
 #define __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, x, y, z) emu_mfma_f64((a), (b), (c))
 #define __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, x, y, z) emu_mfma_bf16_32((a), (b), (c))
 #define __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, x, y, z) emu_mfma_bf16_16((a), (b), (c))

@@ -138,11 +138,13 @@ def test_split_graph_replay_equals_eager_bitwise():
     plan.destroy()
 
 
-@pytest.mark.parametrize("tile", ["0", "1"])
+@pytest.mark.parametrize("tile", ["0", "1", "2", "3"])
 def test_split_every_tile_shape(tile, monkeypatch):
-    """Both compiled tile shapes (64 rows x 32-deep stages, 128 rows x 16-deep
-    stages), forced instead of autotuned: kernel parity on a ragged shape and
-    the one-step gate on full tiles."""
+    """Every compiled tile shape (64 rows x 32-deep and 128 rows x 16-deep
+    stages staged through registers; 64 x 16 and 128 x 16 copied straight to
+    LDS), forced instead of autotuned: kernel parity on a ragged shape (the
+    single mode products of the direct-to-LDS shapes run on the 128 x 16
+    register shape: they need a contiguous axis) and the one-step gate."""
     monkeypatch.setenv("CGL_SPLIT_TILE", tile)
     torch = require_gpu()
     p, Es, Hs = _random_plan((130, 70, 9), 500)
@@ -159,3 +161,28 @@ def test_split_every_tile_shape(tile, monkeypatch):
     p.destroy()
     for method in ("strang", "lawson4"):
         assert _one_step_gate(ci.scaled(ci.C2, (64, 32, 48)), method) < 1e-6
+
+
+@pytest.mark.parametrize("shape,method", [((96, 80, 40), "lawson4"), ((130, 70, 9), "strang"),
+                                          ((256, 256), "lawson4")])
+def test_dma_tiles_match_register_tiles_bitwise(shape, method, monkeypatch):
+    """The direct-to-LDS shapes compute the same products in the same order as
+    the register-staged shapes with the same rows per workgroup: 64 x 16
+    against 64 x 32 and 128 x 16 against 128 x 16, bit for bit."""
+    torch = require_gpu()
+    from paper_2403_02816_amd import cgl
+    p = ci.scaled(ci.C1, shape) if len(shape) == 3 else ci.scaled(ci.C0, shape)
+    u0 = ci.initial_state(p)
+    out = {}
+    for tile in ("0", "2", "1", "3"):
+        monkeypatch.setenv("CGL_SPLIT_TILE", tile)
+        plan = make_plan(p, "split")
+        u = plan.to_device(u0)
+        assert plan.run(method, u, 4, 4) == 0
+        torch.cuda.synchronize()
+        out[tile] = plan.to_host(u)
+        plan.destroy()
+    log(f"dma tiles {shape} {method}: 64-row equal {np.array_equal(out['0'], out['2'])}, "
+        f"128-row equal {np.array_equal(out['1'], out['3'])}")
+    assert np.array_equal(out["0"], out["2"])
+    assert np.array_equal(out["1"], out["3"])
