@@ -513,7 +513,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved_tf, "peak": MI355X_PEAK_BF16_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tf / MI355X_PEAK_BF16_TFLOPS,
                      "traffic": traffic,
-                     "kernel": "k_pass_split (all mu-mode passes of a step)",
+                     "kernel": "k_pass_split_dma / k_pass_split (the autotuned split pass; all mu-mode passes of a step)",
                      "launch_ms": launch_ms,
                      "hbm_gbs": alg_bytes / (launch_ms * 1e-3) / 1e9},
         "accuracy": {"one_step_rel_l2_vs_fp64_oracle": gate, "gate": 1e-6,

@@ -416,23 +416,17 @@ __device__ __forceinline__ void split_tile(const PassSplit& a, int pt, int64_t f
 // image of their LDS tile, so they are copied with buffer loads that write
 // LDS directly (no registers, no LDS store instructions).  Both the operator
 // and the state tiles are double-buffered and unpadded; 16-byte chunks are
-// XOR-swizzled by row so that the MFMA operand reads of eight consecutive
-// lanes (eight rows, one chunk) fall on distinct banks.  One barrier per
-// stage: during stage ks the waves read their stage-ks fragments, start the
-// copy of the operator of stage ks + 1 into the other buffer, issue the
-// state loads of stage ks + 2, run the MFMAs, and split the state of stage
-// ks + 1 into the other state buffer.
+// XOR-swizzled by row (dma_chunk) so that the MFMA operand reads of
+// consecutive lanes (consecutive rows, one chunk) fall on distinct banks.
+// One barrier per stage: during stage ks the waves read their stage-ks
+// fragments, start the copy of the operator of stage ks + 1 into the other
+// buffer, issue the state loads of stage ks + 2, run the MFMAs, and split the
+// state of stage ks + 1 into the other state buffer.
 template <int PT, int KS>
 struct LdsD {
   unsigned short A[2][6 * PT * KS];
   unsigned short B[2][6 * FT * KS];
 };
-
-// position (in 8-element chunks) of chunk c of row `row` in a KS-wide plane
-template <int KS>
-__device__ __forceinline__ int swz_chunk(int row, int c) {
-  return c ^ ((row / (64 / KS)) % (KS / 8));
-}
 
 template <int PT, int KS, int PRO, bool IN64>
 __device__ __forceinline__ void split_tile_dma(const PassSplit& a, int pt, int64_t f0,
@@ -514,7 +508,7 @@ __device__ __forceinline__ void split_tile_dma(const PassSplit& a, int pt, int64
 #pragma unroll
       for (int t = 0; t < 3; ++t) ti[t][j / 2] = t3[t];
     }
-    const int off = fl * KS + swz_chunk<KS>(fl, k0t / 8) * 8 + k0t % 8;
+    const int off = fl * KS + dma_chunk(fl, k0t / 8) * 8 + k0t % 8;
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
       store_terms<KJ>(&lds.B[buf][t * FT * KS + off], tr[t]);
@@ -540,7 +534,7 @@ __device__ __forceinline__ void split_tile_dma(const PassSplit& a, int pt, int64
     bf16x8 br[3], bi[3], ar[PB][3], ai[PB][3];
     {
       const int rb = wf * 32 + row;
-      const int o = rb * KS + swz_chunk<KS>(rb, ch) * 8;
+      const int o = rb * KS + dma_chunk(rb, ch) * 8;
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
         br[t] = *reinterpret_cast<const bf16x8*>(&lds.B[cur][t * FT * KS + o]);
@@ -550,7 +544,7 @@ __device__ __forceinline__ void split_tile_dma(const PassSplit& a, int pt, int64
 #pragma unroll
     for (int b = 0; b < PB; ++b) {
       const int ra = wp * (PT / 2) + b * 32 + row;
-      const int o = ra * KS + swz_chunk<KS>(ra, ch) * 8;
+      const int o = ra * KS + dma_chunk(ra, ch) * 8;
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
         ar[b][t] = *reinterpret_cast<const bf16x8*>(&lds.A[cur][t * PT * KS + o]);

@@ -4,7 +4,7 @@ namespace cgl {
 
 void build_split_operator(const CMat& M, const SplitTile& tile, std::vector<uint16_t>& out,
                           int& Pp, int& Kp) {
-  const int PT = tile.PT, KS = tile.KS;
+  const int PT = tile.PT, KS = tile.KS;  // KS == 16 when tile.dma
   const int64_t n = M.n;
   Pp = static_cast<int>((n + PT - 1) / PT * PT);
   Kp = static_cast<int>((n + KS - 1) / KS * KS);
@@ -21,8 +21,7 @@ void build_split_operator(const CMat& M, const SplitTile& tile, std::vector<uint
       uint16_t* b = out.data() + (static_cast<size_t>(pt) * nKS + ks) * block;
       // within a plane: 16-byte chunk (kk / 8, row) at chunk index (kk / 8) * PT + row,
       // or, for the LDS-image layout, row * KS / 8 + (kk / 8 swizzled by row)
-      const size_t c = tile.dma ? static_cast<size_t>(row) * (KS / 8) +
-                                      ((kk / 8) ^ ((row / (64 / KS)) % (KS / 8)))
+      const size_t c = tile.dma ? static_cast<size_t>(row) * (KS / 8) + dma_chunk(row, kk / 8)
                                 : static_cast<size_t>(kk / 8) * PT + row;
       for (int t = 0; t < 3; ++t) {
         b[(static_cast<size_t>(t) * PT * KS) + c * 8 + kk % 8] = tr[t];

@@ -23,16 +23,22 @@ namespace cgl {
 constexpr int SPK_Q = 6;  // planes per stage block
 
 // Tile shapes of the split kernel: (rows per workgroup, stage depth, layout).
-// dma = 0: the chunk layout above, staged through registers; dma = 1: each
-// (pt, ks) block is the image of its LDS tile (planes of PT rows x KS, rows
-// unpadded, 16-byte chunk c of row r at position c ^ ((r / (64 / KS)) %
-// (KS / 8))), copied by direct-to-LDS loads (contiguous contraction axis
-// only).  Batched plans use the first SPLIT_NTILES_BATCHED shapes.
+// dma = 0: the chunk layout above, staged through registers; dma = 1 (KS =
+// 16 only): each (pt, ks) block is the image of its LDS tile (planes of PT
+// rows x 16, rows unpadded, 16-byte chunk c of row r at position
+// dma_chunk(r, c)), copied by direct-to-LDS loads (contiguous contraction
+// axis only).  Batched plans use the first SPLIT_NTILES_BATCHED shapes.
 struct SplitTile {
   int PT, KS, dma;
 };
 constexpr SplitTile SPLIT_TILES[4] = {{64, 32, 0}, {128, 16, 0}, {64, 16, 1}, {128, 16, 1}};
 constexpr int SPLIT_NTILES = 4;
+
+// Position of 16-byte chunk c (0 or 1) of row r in a 32-byte row of the
+// direct-to-LDS layout.  Rows r and r + 4 (128 bytes apart) and rows r and
+// r + 8 (256 bytes apart) take opposite positions, so the 16-byte reads of 8
+// or 16 consecutive lanes (consecutive rows, one chunk) hit distinct banks.
+constexpr int dma_chunk(int r, int c) { return c ^ (((r >> 2) ^ (r >> 3)) & 1); }
 constexpr int SPLIT_NTILES_BATCHED = 2;
 
 // Builds the planes of M (3 bf16 terms of Re and Im of every entry) for tile
