@@ -98,7 +98,7 @@ struct PassSplit {
 };
 
 constexpr int SP_FT = 64;    // fibres per workgroup (rows/stage sizes: split_layout.hpp)
-constexpr int SPLIT_MAX_TILES = 2;
+constexpr int SPLIT_MAX_TILES = 4;
 constexpr int SP_TERMS = 3;  // bf16 terms per operand
 
 hipError_t launch_pass_split(const PassSplit& a, hipStream_t s);

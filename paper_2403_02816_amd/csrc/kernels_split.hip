@@ -22,6 +22,8 @@
 // (PT, KS) = (64, 32) and (128, 16); the plan's autotuner picks one per
 // direction.  The next stage's global loads are issued into registers before
 // the current stage's MFMAs, so their latency overlaps the math.
+#include <type_traits>
+
 #include "kernels.hpp"
 #include "pointwise.hpp"
 #include "split_layout.hpp"
@@ -619,9 +621,10 @@ __global__ __launch_bounds__(256, 2) void k_pass_split_dma(PassSplit a) {
 // Batched form: a persistent grid walks a table of (instance, p-tile, fibre
 // tile) entries; each instance has its own grid size, coefficients and
 // operator planes, and lives at its own offset in every batched tensor.
-template <int PT, int KS, int PRO, bool IN64>
+template <int PT, int KS, int PRO, bool IN64, bool DMA>
 __global__ __launch_bounds__(256, 2) void k_pass_split_batched(PassBatch b) {
-  __shared__ __attribute__((aligned(16))) Lds<PT, KS> lds;
+  // DMA: the direct-to-LDS tile (operator planes in the LDS-image layout)
+  __shared__ __attribute__((aligned(16))) std::conditional_t<DMA, LdsD<PT, KS>, Lds<PT, KS>> lds;
   for (int t = blockIdx.x; t < b.ntiles; t += gridDim.x) {
     const BatchTile tl = b.tiles[t];
     if (tl.inst < 0) continue;  // padding entry of the table
@@ -646,7 +649,10 @@ __global__ __launch_bounds__(256, 2) void k_pass_split_batched(PassBatch b) {
     a.tile = b.tile;
     a.nl = in.nl;
     a.flag = b.flag;
-    split_tile<PT, KS, true, PRO, IN64>(a, tl.pt, static_cast<int64_t>(tl.ft) * FT, lds);
+    if constexpr (DMA)
+      split_tile_dma<PT, KS, PRO, IN64>(a, tl.pt, static_cast<int64_t>(tl.ft) * FT, lds);
+    else
+      split_tile<PT, KS, true, PRO, IN64>(a, tl.pt, static_cast<int64_t>(tl.ft) * FT, lds);
   }
 }
 
@@ -696,23 +702,23 @@ void launch_tile_dma(const PassSplit& a, dim3 grid, hipStream_t s) {
 
 }  // namespace
 
-template <int PT, int KS>
+template <int PT, int KS, bool DMA>
 void launch_batched_tile(const PassBatch& b, dim3 grid, hipStream_t s) {
   if (b.pro == PRO_G) {
     if (b.in_f64)
-      hipLaunchKernelGGL((k_pass_split_batched<PT, KS, PRO_G, true>), grid, dim3(256), 0, s, b);
+      hipLaunchKernelGGL((k_pass_split_batched<PT, KS, PRO_G, true, DMA>), grid, dim3(256), 0, s, b);
     else
-      hipLaunchKernelGGL((k_pass_split_batched<PT, KS, PRO_G, false>), grid, dim3(256), 0, s, b);
+      hipLaunchKernelGGL((k_pass_split_batched<PT, KS, PRO_G, false, DMA>), grid, dim3(256), 0, s, b);
   } else if (b.pro == PRO_FLOW) {
     if (b.in_f64)
-      hipLaunchKernelGGL((k_pass_split_batched<PT, KS, PRO_FLOW, true>), grid, dim3(256), 0, s, b);
+      hipLaunchKernelGGL((k_pass_split_batched<PT, KS, PRO_FLOW, true, DMA>), grid, dim3(256), 0, s, b);
     else
-      hipLaunchKernelGGL((k_pass_split_batched<PT, KS, PRO_FLOW, false>), grid, dim3(256), 0, s, b);
+      hipLaunchKernelGGL((k_pass_split_batched<PT, KS, PRO_FLOW, false, DMA>), grid, dim3(256), 0, s, b);
   } else {
     if (b.in_f64)
-      hipLaunchKernelGGL((k_pass_split_batched<PT, KS, PRO_NONE, true>), grid, dim3(256), 0, s, b);
+      hipLaunchKernelGGL((k_pass_split_batched<PT, KS, PRO_NONE, true, DMA>), grid, dim3(256), 0, s, b);
     else
-      hipLaunchKernelGGL((k_pass_split_batched<PT, KS, PRO_NONE, false>), grid, dim3(256), 0, s, b);
+      hipLaunchKernelGGL((k_pass_split_batched<PT, KS, PRO_NONE, false, DMA>), grid, dim3(256), 0, s, b);
   }
 }
 
@@ -724,10 +730,12 @@ hipError_t launch_pass_split_batched(const PassBatch& b, int nwg, hipStream_t s)
   if (b.epi == EPI_L4_R1 && !b.out1) return hipErrorInvalidValue;
   if (b.pro != PRO_NONE && b.pro != PRO_FLOW && b.pro != PRO_G) return hipErrorInvalidValue;
   const dim3 grid(static_cast<unsigned>(nwg < b.ntiles ? nwg : b.ntiles));
-  if (b.tile == 0)
-    launch_batched_tile<64, 32>(b, grid, s);
-  else
-    launch_batched_tile<128, 16>(b, grid, s);
+  switch (b.tile) {
+    case 0: launch_batched_tile<64, 32, false>(b, grid, s); break;
+    case 1: launch_batched_tile<128, 16, false>(b, grid, s); break;
+    case 2: launch_batched_tile<64, 16, true>(b, grid, s); break;
+    default: launch_batched_tile<128, 16, true>(b, grid, s); break;
+  }
   return hipGetLastError();
 }
 

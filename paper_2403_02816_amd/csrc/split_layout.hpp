@@ -27,7 +27,7 @@ constexpr int SPK_Q = 6;  // planes per stage block
 // 16 only): each (pt, ks) block is the image of its LDS tile (planes of PT
 // rows x 16, rows unpadded, 16-byte chunk c of row r at position
 // dma_chunk(r, c)), copied by direct-to-LDS loads (contiguous contraction
-// axis only).  Batched plans use the first SPLIT_NTILES_BATCHED shapes.
+// axis only).
 struct SplitTile {
   int PT, KS, dma;
 };
@@ -39,7 +39,7 @@ constexpr int SPLIT_NTILES = 4;
 // r + 8 (256 bytes apart) take opposite positions, so the 16-byte reads of 8
 // or 16 consecutive lanes (consecutive rows, one chunk) hit distinct banks.
 constexpr int dma_chunk(int r, int c) { return c ^ (((r >> 2) ^ (r >> 3)) & 1); }
-constexpr int SPLIT_NTILES_BATCHED = 2;
+constexpr int SPLIT_NTILES_BATCHED = SPLIT_NTILES;  // every shape has a batched form
 
 // Builds the planes of M (3 bf16 terms of Re and Im of every entry) for tile
 // shape t; Pp, Kp receive the padded row / contraction counts.

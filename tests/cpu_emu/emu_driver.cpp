@@ -435,6 +435,10 @@ int main(int argc, char** argv) {
     dma_tiles_bitwise({20, 9, 7}, 0, cq, -15, 15, CGL_NEUMANN);      // ragged: n % 16, F % 64
     dma_tiles_bitwise({37}, CGL_FLAG_FP64_MASTER, cub, -10, 10, CGL_DIRICHLET);
     dma_tiles_bitwise({7, 6, 5}, CGL_FLAG_FP64_MASTER, cq, -15, 15, CGL_NEUMANN);
+    for (const char* t : {"2", "3"}) {  // the batched pass on the direct-to-LDS shapes
+      setenv("CGL_SPLIT_TILE", t, 1);
+      batched_vs_single(CGL_SPLIT_BF16);
+    }
     if (keep) setenv("CGL_SPLIT_TILE", saved.c_str(), 1); else unsetenv("CGL_SPLIT_TILE");
   } else {
     // quick: every kernel variant (mu = 1 contiguous, mu > 1 strided, ragged

@@ -54,7 +54,7 @@ def test_batched_split_one_step_gate_every_instance():
     bp.destroy()
 
 
-@pytest.mark.parametrize("tile", ["0", "1"])
+@pytest.mark.parametrize("tile", ["0", "1", "2", "3"])
 def test_batched_equals_plain_plans_bitwise(tile, monkeypatch):
     monkeypatch.setenv("CGL_SPLIT_TILE", tile)
     torch = require_gpu()
