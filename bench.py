@@ -33,7 +33,7 @@ MI355X_PEAK_HBM_GBS = 8000.0
 # rocprofv3 counter runs (FETCH_SIZE x 2 + WRITE_SIZE, scale factors measured
 # on a 256 MiB device copy; profiles/split_pass_c1_128_lawson4.md), valid for
 # the kernel sources whose digest is recorded with them.
-SPLIT_TRAFFIC_C1 = {"bytes_per_launch": 39472685.0, "sources_sha256_16": "6ce8f6645db77cb4"}
+SPLIT_TRAFFIC_C1 = {"bytes_per_launch": 63244549.0, "sources_sha256_16": "d5f92b8d13351096"}
 SPLIT_SOURCES = ("kernels_split.hip", "kernels.hpp", "pointwise.hpp", "split_layout.cpp",
                  "split_layout.hpp")
 
@@ -74,10 +74,19 @@ def workload(name):
     return ci.C2, "lawson4"
 
 
-def launches_per_step(method, d):
+def paired_lawson4(method, precision="split"):
+    """Split-form Lawson4 runs both actions of a round in one paired pass per
+    direction unless CGL_LAWSON_PAIRED=0."""
+    return method == "lawson4" and precision == "split" and os.environ.get("CGL_LAWSON_PAIRED", "1") != "0"
+
+
+def launches_per_step(method, d, paired=False):
     """mu-mode pass launches per step: one exponential action (d passes) for
-    Strang, four actions of e^{tau K/2} for Lawson4."""
-    return d if method == "strang" else 4 * d
+    Strang, four actions of e^{tau K/2} for Lawson4 (two rounds of d paired
+    passes when paired)."""
+    if method == "strang":
+        return d
+    return 2 * d if paired else 4 * d
 
 
 def time_form(p, method, precision, steps, warmup, u0):
@@ -460,15 +469,18 @@ def main():
     plan, u, ms, wall = time_form(p, method, "split", K, W, u0)
     ms_step = ms / K
     value = p.N * K / (ms * 1e-3)
-    nl = launches_per_step(method, p.d)
+    paired = paired_lawson4(method)
+    nl = launches_per_step(method, p.d, paired)
     launch_ms = ms / (K * nl)
     # algorithmic work of one launch: every grid point gets one complex
-    # mu-mode product of length n (8 n real flops); the split form issues 6
-    # bf16 term products for each, so its MFMA work is 6x that
+    # mu-mode product of length n (8 n real flops) per product (two in a
+    # paired pass); the split form issues 6 bf16 term products for each, so
+    # its MFMA work is 6x that
+    prod = 2 if paired else 1
     n_mu = p.n[0]
-    alg_flops = 8.0 * p.N * n_mu
+    alg_flops = 8.0 * p.N * n_mu * prod
     mfma_flops = 6.0 * alg_flops
-    alg_bytes = p.N * (8 + 8)
+    alg_bytes = p.N * (8 + 8) * prod
     achieved_tf = mfma_flops / (launch_ms * 1e-3) / 1e12
     gate = one_step_gate(p, method, plan)
     split_state = u.clone()
@@ -513,7 +525,8 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved_tf, "peak": MI355X_PEAK_BF16_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tf / MI355X_PEAK_BF16_TFLOPS,
                      "traffic": traffic,
-                     "kernel": "k_pass_split_dma / k_pass_split (the autotuned split pass; all mu-mode passes of a step)",
+                     "kernel": ("k_pass_split_pair (both actions of a Lawson4 round per launch)" if paired
+                                else "k_pass_split_dma / k_pass_split (the autotuned split pass)"),
                      "launch_ms": launch_ms,
                      "hbm_gbs": alg_bytes / (launch_ms * 1e-3) / 1e9},
         "accuracy": {"one_step_rel_l2_vs_fp64_oracle": gate, "gate": 1e-6,

@@ -64,6 +64,9 @@ struct cgl_plan_s {
   // split tile shape per direction and prologue kind (autotuned; batched
   // plans use tile[mu][PRO_NONE] for every pass)
   int tile[3][3] = {{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}};
+  // split form, one plan: Lawson4 rounds as paired passes on one stream
+  // instead of two concurrent actions
+  bool paired = false;
   // [0], [1]: ping-pong intermediates; [2..4]: Lawson4 stage tensors; [5], [6]:
   // ping-pong intermediates of the second branch
   void* stage[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -500,11 +503,66 @@ int lawson_round(cgl_plan_s* p, const void* in_a, void* out_a, bool a_in64, cons
   return st;
 }
 
+// One direction of both actions of a round (split form, one plan): the
+// paired kernel on the 64 x 16 direct-to-LDS planes of e^{tau A_mu / 2}.
+int pass_pair(cgl_plan_s* p, int mu, const void* in0, const void* in1, void* out0, void* out1,
+              bool sameg, int epi, bool in_f64, bool out_f64, hipStream_t s) {
+  const DeviceOp& op = p->dH[mu];
+  const int n = static_cast<int>(p->n[mu]);
+  PassSplit a{};
+  a.in0 = in0;
+  a.in1 = in1;
+  a.out0 = out0;
+  a.out1 = out1;
+  a.op = static_cast<const uint16_t*>(op.ptr[2]);
+  a.tile = 2;
+  a.R = 1;
+  a.R_out = p->N / n;
+  a.F = p->N / n;
+  a.n = n;
+  a.Pp = op.Pp[2];
+  a.Kp = op.Kp[2];
+  a.pro = sameg ? PRO_G : PRO_NONE;
+  a.epi = epi;
+  a.in_f64 = in_f64 ? 1 : 0;
+  a.out_f64 = out_f64 ? 1 : 0;
+  a.nl = p->nl;
+  a.flag = p->dflag;
+  return launch_pass_split_pair(a, s) == hipSuccess ? CGL_OK : CGL_EDEVICE;
+}
+
+// Lawson4 on one stream with paired passes: round 1 takes u to (X, Y) in d
+// passes that apply e^{tau A_mu / 2} to u and g(u) together, round 2 takes
+// (X, Y) to u_{n+1} in d passes; intermediate pairs alternate between
+// (stage[0], stage[5]) and (stage[1], stage[6]), (X, Y) live in stage[2] and
+// stage[3].
+int enqueue_lawson4_paired(cgl_plan_s* p, void* u, hipStream_t s) {
+  const bool m = master(p);
+  const int d = p->d;
+  const void* in0 = u;
+  const void* in1 = u;
+  for (int round = 0; round < 2; ++round) {
+    for (int mu = 0; mu < d; ++mu) {
+      const bool last = mu == d - 1;
+      void* o0 = last ? (round == 0 ? p->stage[2] : u) : p->stage[mu & 1];
+      void* o1 = last ? (round == 0 ? p->stage[3] : nullptr) : p->stage[5 + (mu & 1)];
+      const int epi = last ? (round == 0 ? EPI_L4_R1 : EPI_L4_R2) : EPI_NONE;
+      const int st = pass_pair(p, mu, in0, in1, o0, o1, round == 0 && mu == 0, epi,
+                               round == 0 && mu == 0 && m, round == 1 && last && m, s);
+      if (st != CGL_OK) return st;
+      in0 = o0;
+      in1 = o1;
+    }
+  }
+  return CGL_OK;
+}
+
 // Lawson4 (eq. lawson4) with e^{tau K} = e^{tau K/2} e^{tau K/2}: four
 // actions of e^{tau K/2} in two rounds,
 //   P = H u,  Q = H g(u) -> (X, Y) in the epilogue;  H X,  H Y -> u_{n+1},
 // where the stage combinations run in the last-pass epilogues.
 int enqueue_lawson4(cgl_plan_s* p, void* u, hipStream_t s) {
+  if (p->paired) return enqueue_lawson4_paired(p, u, s);
   const bool m = master(p);
   void* B0 = p->stage[2];
   void* B1 = p->stage[3];
@@ -634,7 +692,13 @@ int cgl_plan(cgl_plan_t* out, int d, const int64_t* n, const cgl_coeffs* c, doub
     if (n[mu] < 3 || n[mu] > 4096) return CGL_EINVAL;
     N *= n[mu];
   }
-  return create_plan(out, d, n, N, c, tau, precision, flags, hip_stream);
+  const int st = create_plan(out, d, n, N, c, tau, precision, flags, hip_stream);
+  if (st == CGL_OK && precision == CGL_SPLIT_BF16) {
+    // CGL_LAWSON_PAIRED=0 keeps the two concurrent actions (comparison runs)
+    const char* e = std::getenv("CGL_LAWSON_PAIRED");
+    (*out)->paired = !(e && e[0] == '0');
+  }
+  return st;
 }
 
 }  // extern "C"

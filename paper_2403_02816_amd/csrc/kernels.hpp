@@ -78,6 +78,7 @@ hipError_t launch_clear_flag(unsigned* flag, hipStream_t s);
 // state at the pass ends), bf16 operator terms, FP32 accumulation.
 struct PassSplit {
   const void* in0;
+  const void* in1;  // paired pass: the second action's input (see launch_pass_split_pair)
   const void* aux;  // complex64 stage tensor, in the output's layout
   void* out0;
   void* out1;
@@ -102,6 +103,11 @@ constexpr int SPLIT_MAX_TILES = 4;
 constexpr int SP_TERMS = 3;  // bf16 terms per operand
 
 hipError_t launch_pass_split(const PassSplit& a, hipStream_t s);
+// One direction of both actions of a Lawson4 round (64 x 16 direct-to-LDS
+// operator planes): out0 <- M in0, out1 <- M in1, or with pro == PRO_G out1
+// <- M g(in0); epi EPI_NONE, EPI_L4_R1 (out0 = X, out1 = Y) or EPI_L4_R2
+// (out0 = u_{n+1}).
+hipError_t launch_pass_split_pair(const PassSplit& a, hipStream_t s);
 
 // ---- batched split-precision passes (many independent instances)
 struct BatchInstance {

@@ -609,6 +609,256 @@ __global__ __launch_bounds__(256, 2) void k_pass_split(PassSplit a) {
                                        static_cast<int64_t>(w / nP) * FT, lds);
 }
 
+// ---- Paired pass: one direction of the two exponential actions of a
+// Lawson4 round in one launch.  A workgroup applies its operator tile to the
+// tiles of both inputs (in0 for the first action, in1 for the second, or, in
+// the first pass of the first round, in0 and g(in0)), so each operator stage
+// is copied to LDS once for two products, and the round's stage combination
+// runs in the epilogue with both results at hand (no auxiliary tensor, no
+// cross-stream join).  64 rows x 64 fibres, 16-deep stages, direct-to-LDS
+// operator copies as above; two accumulator sets per wave.
+template <int PT, int KS>
+struct LdsP {
+  unsigned short A[2][6 * PT * KS];
+  unsigned short B[2][2][6 * FT * KS];
+};
+
+// Epilogue of a paired tile: y0, y1 the two results of a point.  EPI_NONE:
+// out0 = y0, out1 = y1.  EPI_L4_R1: (P, Q) = (y0, y1) -> out0 = X, out1 = Y.
+// EPI_L4_R2: (HX, HY) = (y0, y1) -> out0 = u_{n+1}.  lds_mem: 64 x 65 x 2
+// float2 of free workgroup memory.
+constexpr int EPI2_LDS_BYTES = 2 * 64 * (SP_FT + 1) * 8;
+
+__device__ __forceinline__ void pair_epilogue(const PassSplit& a, int pt, int64_t f0,
+                                              f32x16 (&accr)[2], f32x16 (&acci)[2],
+                                              unsigned& flag, void* lds_mem) {
+  constexpr int PT = 64;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wp = wave & 1;
+  const int wf = wave >> 1;
+  const bool of64 = a.out_f64 != 0;
+  constexpr int EP = FT + 1;
+  float2* sE = reinterpret_cast<float2*>(lds_mem);
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int lr = wp * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      sE[(t * 64 + lr) * EP + wf * 32 + (lane & 31)] = float2{accr[t][r], acci[t][r]};
+    }
+  __syncthreads();
+#pragma unroll 1
+  for (int e = tid; e < 64 * FT; e += 256) {
+    const int lr = e / FT, fc = e % FT;
+    const int m = pt * PT + lr;
+    const int64_t f = f0 + fc;
+    if (m >= a.n || f >= a.F) continue;
+    const int64_t off = fibre_base(f, a.R_out, a.n) + a.R_out * (int64_t)m;
+    const float2 v0 = sE[lr * EP + fc], v1 = sE[(64 + lr) * EP + fc];
+    if (a.epi == EPI_NONE) {
+      reinterpret_cast<float2*>(a.out0)[off] = v0;
+      reinterpret_cast<float2*>(a.out1)[off] = v1;
+      continue;
+    }
+    const cd y0 = {static_cast<double>(v0.x), static_cast<double>(v0.y)};
+    const cd y1 = {static_cast<double>(v1.x), static_cast<double>(v1.y)};
+    if (a.epi == EPI_L4_R1) {
+      cd X, Y;
+      lawson_r1(y0, y1, a.nl, X, Y);
+      store_c(a.out0, off, false, X);
+      store_c(a.out1, off, false, Y);
+    } else {
+      const cd z = lawson_r2(y0, y1, a.nl);
+      if (!finite2(z)) flag |= FLAG_NONFINITE;
+      store_c(a.out0, off, of64, z);
+    }
+  }
+  __syncthreads();
+}
+
+// SAMEG: both products read in0; the second applies g first (P = H u and
+// Q = H g(u)).  Otherwise the inputs are in0 and in1 (complex64).
+template <bool SAMEG, bool IN64>
+__device__ __forceinline__ void split_tile_pair(const PassSplit& a, int pt, int64_t f0,
+                                                LdsP<64, 16>& lds) {
+  constexpr int PT = 64, KS = 16;
+  constexpr int KJ = KS / 4;
+  constexpr int ABYTES = 12 * PT * KS;
+  constexpr int NDMA = ABYTES / 4096;
+  constexpr int ESZ = IN64 ? 16 : 8;
+  constexpr int NIN = SAMEG ? 1 : 2;       // state tensors loaded
+  constexpr unsigned OOR = 0x80000000u;
+  static_assert(!IN64 || SAMEG, "a complex128 input occurs only in the first pass");
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wp = wave & 1;
+  const int wf = wave >> 1;
+  const int nKS = a.Kp / KS;
+  const __amdgpu_buffer_rsrc_t ors = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint16_t*>(a.op + static_cast<size_t>(pt) * nKS * (6 * PT * KS)), 0,
+      nKS * ABYTES, 0x00020000);
+  const int fl = (tid & 7) + 8 * (tid >> 5);
+  const int k0t = KJ * ((tid >> 3) & 3);
+  const int64_t srem = (a.F - f0) * static_cast<int64_t>(a.n) * ESZ;
+  const int rnum = static_cast<int>(srem < 0x7fffffffll ? srem : 0x7fffffffll);
+  const int64_t tile0 = f0 * static_cast<int64_t>(a.n) * ESZ;
+  __amdgpu_buffer_rsrc_t srs[NIN];
+  srs[0] = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<char*>(reinterpret_cast<const char*>(a.in0) + tile0), 0, rnum, 0x00020000);
+  if constexpr (!SAMEG)
+    srs[NIN - 1] = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<char*>(reinterpret_cast<const char*>(a.in1) + tile0), 0, rnum, 0x00020000);
+  const unsigned svo = static_cast<unsigned>((fl * a.n + k0t) * ESZ);
+
+  auto copy_op = [&](int ks, int buf) __attribute__((always_inline)) {
+    const unsigned o = ks < nKS ? static_cast<unsigned>(ks * ABYTES) : OOR;
+#pragma unroll
+    for (int j = 0; j < NDMA; ++j) {
+      const int blk = wave + 4 * j;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          ors, (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(lds.A[buf]) + blk * 1024),
+          16, o + static_cast<unsigned>(blk * 1024 + lane * 16), 0, 0, 0);
+    }
+  };
+  auto load_state = [&](int ks, f32x4 (&v)[NIN][KJ / 2]) __attribute__((always_inline)) {
+    const unsigned o = ks < nKS ? svo + static_cast<unsigned>(ks * KS * ESZ) : OOR;
+#pragma unroll
+    for (int i = 0; i < NIN; ++i)
+#pragma unroll
+      for (int j = 0; j < KJ; j += 2) {
+        if constexpr (IN64) {
+          const double2 x = __builtin_bit_cast(
+              double2, __builtin_amdgcn_raw_buffer_load_b128(srs[i], o + j * 16, 0, 0));
+          const double2 y = __builtin_bit_cast(
+              double2, __builtin_amdgcn_raw_buffer_load_b128(srs[i], o + j * 16 + 16, 0, 0));
+          v[i][j / 2] = f32x4{static_cast<float>(x.x), static_cast<float>(x.y),
+                              static_cast<float>(y.x), static_cast<float>(y.y)};
+        } else {
+          v[i][j / 2] =
+              __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(srs[i], o + j * 8, 0, 0));
+        }
+      }
+  };
+  unsigned flag = 0;
+  auto store_state = [&](int ks, const f32x4 (&v)[NIN][KJ / 2], int buf) __attribute__((always_inline)) {
+    const int off = fl * KS + dma_chunk(fl, k0t / 8) * 8 + k0t % 8;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      cf w[KJ];
+#pragma unroll
+      for (int j = 0; j < KJ; ++j) {
+        const int i = SAMEG ? 0 : t;
+        w[j] = cf{v[i][j / 2][2 * (j % 2)], v[i][j / 2][2 * (j % 2) + 1]};
+        if (ks * KS + k0t + j >= a.n) w[j] = cf{0.0f, 0.0f};
+        if (SAMEG && t == 1) w[j] = g_cgl_f(w[j], a.nl);
+      }
+      unsigned tr[3][KJ / 2], ti[3][KJ / 2];
+#pragma unroll
+      for (int j = 0; j < KJ; j += 2) {
+        unsigned t3[3];
+        split3x2(w[j].re, w[j + 1].re, t3);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) tr[q][j / 2] = t3[q];
+        split3x2(w[j].im, w[j + 1].im, t3);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) ti[q][j / 2] = t3[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        store_terms<KJ>(&lds.B[buf][t][q * FT * KS + off], tr[q]);
+        store_terms<KJ>(&lds.B[buf][t][(3 + q) * FT * KS + off], ti[q]);
+      }
+    }
+  };
+
+  f32x16 accr[2], acci[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      accr[t][r] = 0.0f;
+      acci[t][r] = 0.0f;
+    }
+  const int row = lane & 31;
+  const int ch = lane >> 5;
+
+  auto stage = [&](int ks, f32x4 (&vload)[NIN][KJ / 2], const f32x4 (&vstore)[NIN][KJ / 2])
+      __attribute__((always_inline)) {
+    const int cur = ks & 1;
+    bf16x8 br[2][3], bi[2][3], ar[3], ai[3];
+    {
+      const int rb = wf * 32 + row;
+      const int o = rb * KS + dma_chunk(rb, ch) * 8;
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          br[t][q] = *reinterpret_cast<const bf16x8*>(&lds.B[cur][t][q * FT * KS + o]);
+          bi[t][q] = *reinterpret_cast<const bf16x8*>(&lds.B[cur][t][(3 + q) * FT * KS + o]);
+        }
+    }
+    {
+      const int ra = wp * 32 + row;
+      const int o = ra * KS + dma_chunk(ra, ch) * 8;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        ar[q] = *reinterpret_cast<const bf16x8*>(&lds.A[cur][q * PT * KS + o]);
+        ai[q] = *reinterpret_cast<const bf16x8*>(&lds.A[cur][(3 + q) * PT * KS + o]);
+      }
+    }
+    load_state(ks + 2, vload);
+    copy_op(ks + 1, cur ^ 1);
+    __builtin_amdgcn_sched_barrier(0);
+    bf16x8 an[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) an[q] = neg8(ai[q]);
+    constexpr int PI[6] = {2, 1, 0, 1, 0, 0};
+    constexpr int PJ[6] = {0, 1, 2, 0, 1, 0};
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const int ti_ = PI[q], tj = PJ[q];
+        accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ti_], br[t][tj], accr[t], 0, 0, 0);
+        acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ai[ti_], br[t][tj], acci[t], 0, 0, 0);
+        accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an[ti_], bi[t][tj], accr[t], 0, 0, 0);
+        acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ti_], bi[t][tj], acci[t], 0, 0, 0);
+      }
+    store_state(ks + 1, vstore, cur ^ 1);
+    __syncthreads();
+  };
+
+  f32x4 sv[2][NIN][KJ / 2];
+  copy_op(0, 0);
+  load_state(0, sv[0]);
+  load_state(1, sv[1]);
+  store_state(0, sv[0], 0);
+  __syncthreads();
+  int ks = 0;
+  for (; ks + 1 < nKS; ks += 2) {
+    stage(ks, sv[0], sv[1]);
+    stage(ks + 1, sv[1], sv[0]);
+  }
+  if (ks < nKS) stage(ks, sv[0], sv[1]);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the last copies write the other buffer
+  __syncthreads();
+  static_assert(EPI2_LDS_BYTES <= static_cast<int>(sizeof(LdsP<64, 16>)), "epilogue staging fits");
+  pair_epilogue(a, pt, f0, accr, acci, flag, &lds);
+  if (flag) atomicOr(a.flag, flag);
+}
+
+template <bool SAMEG, bool IN64>
+__global__ __launch_bounds__(256, 2) void k_pass_split_pair(PassSplit a) {
+  __shared__ __attribute__((aligned(16))) LdsP<64, 16> lds;
+  const int nP = a.Pp / 64;
+  const unsigned w = xcd_remap(blockIdx.x, gridDim.x);
+  split_tile_pair<SAMEG, IN64>(a, static_cast<int>(w % nP), static_cast<int64_t>(w / nP) * FT, lds);
+}
+
 template <int PT, int KS, int PRO, bool IN64>
 __global__ __launch_bounds__(256, 2) void k_pass_split_dma(PassSplit a) {
   __shared__ __attribute__((aligned(16))) LdsD<PT, KS> lds;
@@ -735,6 +985,32 @@ hipError_t launch_pass_split_batched(const PassBatch& b, int nwg, hipStream_t s)
     case 1: launch_batched_tile<128, 16, false>(b, grid, s); break;
     case 2: launch_batched_tile<64, 16, true>(b, grid, s); break;
     default: launch_batched_tile<128, 16, true>(b, grid, s); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_split_pair(const PassSplit& a, hipStream_t s) {
+  // the operator planes must be those of the 64 x 16 direct-to-LDS shape
+  if (a.tile != 2 || a.R != 1 || a.Pp % 64 != 0 || a.Kp % 16 != 0 || a.Kp < a.n || a.Pp < a.n ||
+      a.F <= 0)
+    return hipErrorInvalidValue;
+  if (!a.in0 || !a.out0 || !a.op || !a.flag) return hipErrorInvalidValue;
+  const bool sameg = a.pro == PRO_G;
+  if (a.pro != PRO_NONE && !sameg) return hipErrorInvalidValue;
+  if (!sameg && (!a.in1 || a.in_f64)) return hipErrorInvalidValue;
+  if (a.epi != EPI_NONE && a.epi != EPI_L4_R1 && a.epi != EPI_L4_R2) return hipErrorInvalidValue;
+  if (a.epi != EPI_L4_R2 && (!a.out1 || a.out_f64)) return hipErrorInvalidValue;
+  const int64_t nF = (a.F + FT - 1) / FT;
+  const int64_t G = nF * (a.Pp / 64);
+  if (G > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>(G));
+  if (sameg) {
+    if (a.in_f64)
+      hipLaunchKernelGGL((k_pass_split_pair<true, true>), grid, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_pass_split_pair<true, false>), grid, dim3(256), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_pass_split_pair<false, false>), grid, dim3(256), 0, s, a);
   }
   return hipGetLastError();
 }

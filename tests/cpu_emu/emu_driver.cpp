@@ -190,6 +190,43 @@ static void dma_tiles_bitwise(std::vector<int64_t> n, unsigned flags, cgl_coeffs
   std::printf("  dma tiles bitwise d=%d flags=%u ok\n", d, flags);
 }
 
+// Lawson4 with both actions of a round in one paired pass per direction
+// (CGL_LAWSON_PAIRED=1) against the two concurrent actions: the same
+// products and combinations, so the steps must agree bit for bit.
+static void paired_bitwise(std::vector<int64_t> n, unsigned flags, cgl_coeffs c, double a,
+                           double b, int bc) {
+  const int d = static_cast<int>(n.size());
+  int64_t N = 1;
+  for (auto v : n) N *= v;
+  const bool c128 = (flags & CGL_FLAG_FP64_MASTER) != 0;
+  const size_t bytes = static_cast<size_t>(N) * (c128 ? 16 : 8);
+  std::vector<std::vector<unsigned char>> res;
+  for (const char* pv : {"0", "1"}) {
+    setenv("CGL_LAWSON_PAIRED", pv, 1);
+    cgl_plan_t p = nullptr;
+    expect(cgl_plan(&p, d, n.data(), &c, 0.005, CGL_SPLIT_BF16, flags, nullptr) == CGL_OK, "plan");
+    for (int mu = 0; mu < d; ++mu) {
+      std::vector<cd> A(n[mu] * n[mu]);
+      expect(cgl_fd_operator(n[mu], a, b, bc, &c, d, reinterpret_cast<double*>(A.data())) == CGL_OK,
+             "fd");
+      expect(cgl_set_operators(p, mu, reinterpret_cast<double*>(A.data())) == CGL_OK, "set");
+    }
+    auto U = rnd(N, 13, 0.3);
+    std::vector<cd> u64 = U;
+    std::vector<std::complex<float>> u32 = cast<float>(U);
+    void* u = c128 ? static_cast<void*>(u64.data()) : static_cast<void*>(u32.data());
+    expect(cgl_step_lawson4(p, u, 2) == CGL_OK, "lawson4");
+    expect(cgl_run(p, CGL_LAWSON4, u, 2, 2) == CGL_OK, "run lawson4");
+    expect(cgl_status(p) == CGL_OK, "status");
+    const unsigned char* q = static_cast<const unsigned char*>(u);
+    res.emplace_back(q, q + bytes);
+    cgl_destroy(p);
+  }
+  unsetenv("CGL_LAWSON_PAIRED");
+  expect(res[0] == res[1], "paired Lawson4 == two concurrent actions");
+  std::printf("  paired lawson4 bitwise d=%d flags=%u ok\n", d, flags);
+}
+
 static void run_steps(std::vector<int64_t> n, int precision, unsigned flags, cgl_coeffs c,
                       double a, double b, int bc, double tau, int method, int m) {
   const int d = static_cast<int>(n.size());
@@ -435,6 +472,10 @@ int main(int argc, char** argv) {
     dma_tiles_bitwise({20, 9, 7}, 0, cq, -15, 15, CGL_NEUMANN);      // ragged: n % 16, F % 64
     dma_tiles_bitwise({37}, CGL_FLAG_FP64_MASTER, cub, -10, 10, CGL_DIRICHLET);
     dma_tiles_bitwise({7, 6, 5}, CGL_FLAG_FP64_MASTER, cq, -15, 15, CGL_NEUMANN);
+    paired_bitwise({32, 64}, 0, cub, -10, 10, CGL_DIRICHLET);
+    paired_bitwise({20, 9, 7}, 0, cq, -15, 15, CGL_NEUMANN);
+    paired_bitwise({37}, CGL_FLAG_FP64_MASTER, cub, -10, 10, CGL_DIRICHLET);
+    paired_bitwise({7, 6, 5}, CGL_FLAG_FP64_MASTER, cq, -15, 15, CGL_NEUMANN);
     for (const char* t : {"2", "3"}) {  // the batched pass on the direct-to-LDS shapes
       setenv("CGL_SPLIT_TILE", t, 1);
       batched_vs_single(CGL_SPLIT_BF16);

@@ -186,3 +186,27 @@ def test_dma_tiles_match_register_tiles_bitwise(shape, method, monkeypatch):
         f"128-row equal {np.array_equal(out['1'], out['3'])}")
     assert np.array_equal(out["0"], out["2"])
     assert np.array_equal(out["1"], out["3"])
+
+
+@pytest.mark.parametrize("shape,master", [((128, 128, 128), False), ((96, 80, 40), True),
+                                          ((130, 70, 9), False), ((256, 256), False)])
+def test_paired_lawson4_matches_concurrent_actions_bitwise(shape, master, monkeypatch):
+    """Lawson4 with both actions of a round in one paired pass per direction
+    computes the same products and stage combinations as the two concurrent
+    actions: identical bits (complex64 and FP64-master states)."""
+    torch = require_gpu()
+    from paper_2403_02816_amd import cgl
+    p = ci.scaled(ci.C1, shape) if len(shape) == 3 else ci.scaled(ci.C0, shape)
+    u0 = ci.initial_state(p)
+    out = {}
+    for paired in ("0", "1"):
+        monkeypatch.setenv("CGL_LAWSON_PAIRED", paired)
+        plan = make_plan(p, "split", master=master)
+        u = plan.to_device(u0)
+        assert plan.run("lawson4", u, 3, 3) == 0
+        plan.step_lawson4(u, 1)
+        torch.cuda.synchronize()
+        out[paired] = plan.to_host(u)
+        plan.destroy()
+    log(f"paired lawson4 {shape} master={master}: equal {np.array_equal(out['0'], out['1'])}")
+    assert np.array_equal(out["0"], out["1"])
