@@ -198,7 +198,7 @@ def bench_batched(args):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
     Ntot = sum(p.N for p in probs)
-    launches = 4 * 2
+    launches = launches_per_step("lawson4", 2, paired_lawson4("lawson4"))  # persistent launches
     launch_ms = ms / (K * launches)
     mfma = sum(6.0 * 8.0 * p.N * (p.n[0] + p.n[1]) for p in probs) * 4 / launches
     achieved = mfma / (launch_ms * 1e-3) / 1e12
@@ -254,7 +254,7 @@ def bench_batched(args):
                    "grid_points": Ntot, "method": "lawson4", "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": MI355X_PEAK_BF16_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / MI355X_PEAK_BF16_TFLOPS,
-                     "traffic": None, "kernel": "k_pass_split_batched (persistent)",
+                     "traffic": None, "kernel": ("k_pass_split_batched_pair (persistent, both actions of a Lawson4 round)" if paired_lawson4("lawson4") else "k_pass_split_batched (persistent)"),
                      "launch_ms": launch_ms},
         "accuracy": {"one_step_rel_l2_vs_fp64_oracle_max_sampled": gate, "gate": 1e-6,
                      "sampled_instances": len(sample),

@@ -64,8 +64,8 @@ struct cgl_plan_s {
   // split tile shape per direction and prologue kind (autotuned; batched
   // plans use tile[mu][PRO_NONE] for every pass)
   int tile[3][3] = {{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}};
-  // split form, one plan: Lawson4 rounds as paired passes on one stream
-  // instead of two concurrent actions
+  // split form: Lawson4 rounds as paired passes on one stream instead of
+  // two concurrent actions
   bool paired = false;
   // [0], [1]: ping-pong intermediates; [2..4]: Lawson4 stage tensors; [5], [6]:
   // ping-pong intermediates of the second branch
@@ -503,10 +503,30 @@ int lawson_round(cgl_plan_s* p, const void* in_a, void* out_a, bool a_in64, cons
   return st;
 }
 
-// One direction of both actions of a round (split form, one plan): the
-// paired kernel on the 64 x 16 direct-to-LDS planes of e^{tau A_mu / 2}.
+// One direction of both actions of a round (split form): the paired kernel
+// on the 64 x 16 direct-to-LDS planes of e^{tau A_mu / 2}, for one plan or
+// every instance of a batched plan.
 int pass_pair(cgl_plan_s* p, int mu, const void* in0, const void* in1, void* out0, void* out1,
               bool sameg, int epi, bool in_f64, bool out_f64, hipStream_t s) {
+  if (p->batch > 0) {
+    if (!p->tables) return CGL_ENOTREADY;
+    PassBatch b{};
+    b.in0 = in0;
+    b.in1 = in1;
+    b.out0 = out0;
+    b.out1 = out1;
+    b.inst = p->dinst[mu];
+    b.tiles = p->dtiles[mu][2];
+    b.ntiles = p->ntiles[mu][2];
+    b.which = 1;
+    b.pro = sameg ? PRO_G : PRO_NONE;
+    b.epi = epi;
+    b.in_f64 = in_f64 ? 1 : 0;
+    b.out_f64 = out_f64 ? 1 : 0;
+    b.tile = 2;
+    b.flag = p->dflag;
+    return launch_pass_split_batched_pair(b, p->nwg, s) == hipSuccess ? CGL_OK : CGL_EDEVICE;
+  }
   const DeviceOp& op = p->dH[mu];
   const int n = static_cast<int>(p->n[mu]);
   PassSplit a{};
@@ -789,6 +809,10 @@ int cgl_plan_batched(cgl_plan_t* out, int batch, int d, const int64_t* n, const 
   int st = create_plan(&p, d, nullptr, N, &c[0], tau, precision, flags, hip_stream);
   if (st != CGL_OK) return st;
   p->batch = batch;
+  if (precision == CGL_SPLIT_BF16) {  // as for single plans (CGL_LAWSON_PAIRED=0: two actions)
+    const char* e = std::getenv("CGL_LAWSON_PAIRED");
+    p->paired = !(e && e[0] == '0');
+  }
   p->bn.assign(n, n + static_cast<size_t>(batch) * d);
   p->boff = boff;
   p->bnl.resize(batch);

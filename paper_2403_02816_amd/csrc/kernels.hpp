@@ -127,6 +127,7 @@ struct BatchTile {
 
 struct PassBatch {
   const void* in0;
+  const void* in1;  // paired pass: the second action's input
   const void* aux;
   void* out0;
   void* out1;
@@ -144,5 +145,9 @@ struct PassBatch {
 
 // launches a persistent grid of at most nwg workgroups over b.tiles
 hipError_t launch_pass_split_batched(const PassBatch& b, int nwg, hipStream_t s);
+// the paired pass (see launch_pass_split_pair) over every instance: b.tile
+// must be the 64 x 16 direct-to-LDS shape, b.pro PRO_G (the second product
+// reads g(in0)) or PRO_NONE (in0 and in1)
+hipError_t launch_pass_split_batched_pair(const PassBatch& b, int nwg, hipStream_t s);
 
 }  // namespace cgl

@@ -906,6 +906,38 @@ __global__ __launch_bounds__(256, 2) void k_pass_split_batched(PassBatch b) {
   }
 }
 
+// Paired pass over every instance of a batched plan (persistent grid).
+template <bool SAMEG, bool IN64>
+__global__ __launch_bounds__(256, 2) void k_pass_split_batched_pair(PassBatch b) {
+  __shared__ __attribute__((aligned(16))) LdsP<64, 16> lds;
+  for (int t = blockIdx.x; t < b.ntiles; t += gridDim.x) {
+    const BatchTile tl = b.tiles[t];
+    if (tl.inst < 0) continue;  // padding entry of the table
+    const BatchInstance& in = b.inst[tl.inst];
+    PassSplit a{};
+    const size_t esz_in = IN64 ? 16 : 8, esz_out = b.out_f64 ? 16 : 8;
+    a.in0 = static_cast<const char*>(b.in0) + in.off * esz_in;
+    a.in1 = b.in1 ? static_cast<const char*>(b.in1) + in.off * 8 : nullptr;
+    a.out0 = static_cast<char*>(b.out0) + in.off * esz_out;
+    a.out1 = b.out1 ? static_cast<char*>(b.out1) + in.off * 8 : nullptr;
+    a.op = b.which == 0 ? in.opE[2] : in.opH[2];
+    a.R = 1;
+    a.R_out = in.F;
+    a.F = in.F;
+    a.n = in.n;
+    a.Pp = in.Pp[2];
+    a.Kp = in.Kp[2];
+    a.pro = SAMEG ? PRO_G : PRO_NONE;
+    a.epi = b.epi;
+    a.in_f64 = IN64 ? 1 : 0;
+    a.out_f64 = b.out_f64;
+    a.tile = 2;
+    a.nl = in.nl;
+    a.flag = b.flag;
+    split_tile_pair<SAMEG, IN64>(a, tl.pt, static_cast<int64_t>(tl.ft) * FT, lds);
+  }
+}
+
 template <int PT, int KS, bool CONTIG, int PRO>
 void launch_pro(const PassSplit& a, dim3 grid, hipStream_t s) {
   if (a.in_f64)
@@ -985,6 +1017,26 @@ hipError_t launch_pass_split_batched(const PassBatch& b, int nwg, hipStream_t s)
     case 1: launch_batched_tile<128, 16, false>(b, grid, s); break;
     case 2: launch_batched_tile<64, 16, true>(b, grid, s); break;
     default: launch_batched_tile<128, 16, true>(b, grid, s); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_split_batched_pair(const PassBatch& b, int nwg, hipStream_t s) {
+  if (b.tile != 2 || b.ntiles <= 0 || nwg <= 0) return hipErrorInvalidValue;
+  if (!b.in0 || !b.out0 || !b.inst || !b.tiles || !b.flag) return hipErrorInvalidValue;
+  const bool sameg = b.pro == PRO_G;
+  if (b.pro != PRO_NONE && !sameg) return hipErrorInvalidValue;
+  if (!sameg && (!b.in1 || b.in_f64)) return hipErrorInvalidValue;
+  if (b.epi != EPI_NONE && b.epi != EPI_L4_R1 && b.epi != EPI_L4_R2) return hipErrorInvalidValue;
+  if (b.epi != EPI_L4_R2 && (!b.out1 || b.out_f64)) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>(nwg < b.ntiles ? nwg : b.ntiles));
+  if (sameg) {
+    if (b.in_f64)
+      hipLaunchKernelGGL((k_pass_split_batched_pair<true, true>), grid, dim3(256), 0, s, b);
+    else
+      hipLaunchKernelGGL((k_pass_split_batched_pair<true, false>), grid, dim3(256), 0, s, b);
+  } else {
+    hipLaunchKernelGGL((k_pass_split_batched_pair<false, false>), grid, dim3(256), 0, s, b);
   }
   return hipGetLastError();
 }
