@@ -139,7 +139,10 @@ int cgl_step_strang(cgl_plan_t p, void* u_dev, int64_t nsteps);
  * P = e^{tau K/2} u and Q = e^{tau K/2} g(u), from which the stages
  * X = P + tau g(u3), Y = P + tau/6 Q + tau/3 (g(u2) + g(u3)) are formed in
  * the last pass; then u4 = e^{tau K/2} X and
- * u_{n+1} = e^{tau K/2} Y + tau/6 g(u4).  Same errors as cgl_step_strang. */
+ * u_{n+1} = e^{tau K/2} Y + tau/6 g(u4).  The split form applies each
+ * direction of the two actions of a pair (P with Q, then X with Y) in one
+ * pass, both products sharing the operator; the FP64 form runs the two
+ * actions side by side.  Same errors as cgl_step_strang. */
 int cgl_step_lawson4(cgl_plan_t p, void* u_dev, int64_t nsteps);
 
 /* Advance u_dev by nsteps steps of method (CGL_STRANG / CGL_LAWSON4),
