@@ -639,6 +639,23 @@ __device__ __forceinline__ void pair_epilogue(const PassSplit& a, int pt, int64_
   const int wp = wave & 1;
   const int wf = wave >> 1;
   const bool of64 = a.out_f64 != 0;
+  if (a.epi == EPI_NONE) {
+    // plain passes store straight from the accumulators (lanes 0..31 of a
+    // row take 32 consecutive fibres)
+    const int64_t f = f0 + wf * 32 + (lane & 31);
+    if (f < a.F) {
+      const int64_t base = fibre_base(f, a.R_out, a.n);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = pt * PT + wp * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (m >= a.n) continue;
+        const int64_t off = base + a.R_out * (int64_t)m;
+        reinterpret_cast<float2*>(a.out0)[off] = float2{accr[0][r], acci[0][r]};
+        reinterpret_cast<float2*>(a.out1)[off] = float2{accr[1][r], acci[1][r]};
+      }
+    }
+    return;
+  }
   constexpr int EP = FT + 1;
   float2* sE = reinterpret_cast<float2*>(lds_mem);
 #pragma unroll
@@ -657,11 +674,6 @@ __device__ __forceinline__ void pair_epilogue(const PassSplit& a, int pt, int64_
     if (m >= a.n || f >= a.F) continue;
     const int64_t off = fibre_base(f, a.R_out, a.n) + a.R_out * (int64_t)m;
     const float2 v0 = sE[lr * EP + fc], v1 = sE[(64 + lr) * EP + fc];
-    if (a.epi == EPI_NONE) {
-      reinterpret_cast<float2*>(a.out0)[off] = v0;
-      reinterpret_cast<float2*>(a.out1)[off] = v1;
-      continue;
-    }
     const cd y0 = {static_cast<double>(v0.x), static_cast<double>(v0.y)};
     const cd y1 = {static_cast<double>(v1.x), static_cast<double>(v1.y)};
     if (a.epi == EPI_L4_R1) {
