@@ -623,15 +623,15 @@ struct LdsP {
   unsigned short B[2][2][6 * FT * KS];
 };
 
-// Epilogue of a paired tile: y0, y1 the two results of a point.  EPI_NONE:
+// Epilogue of a paired tile: y0, y1 the two results of a point, both held
+// by the same lane (the two accumulator sets have one layout).  EPI_NONE:
 // out0 = y0, out1 = y1.  EPI_L4_R1: (P, Q) = (y0, y1) -> out0 = X, out1 = Y.
-// EPI_L4_R2: (HX, HY) = (y0, y1) -> out0 = u_{n+1}.  lds_mem: 64 x 65 x 2
-// float2 of free workgroup memory.
-constexpr int EPI2_LDS_BYTES = 2 * 64 * (SP_FT + 1) * 8;
-
+// EPI_L4_R2: (HX, HY) = (y0, y1) -> out0 = u_{n+1}.  Every kind stores
+// straight from the accumulators: lanes 0..31 of a row take 32 consecutive
+// fibres, which are adjacent in the output (R_out = F).
 __device__ __forceinline__ void pair_epilogue(const PassSplit& a, int pt, int64_t f0,
                                               f32x16 (&accr)[2], f32x16 (&acci)[2],
-                                              unsigned& flag, void* lds_mem) {
+                                              unsigned& flag) {
   constexpr int PT = 64;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -639,55 +639,45 @@ __device__ __forceinline__ void pair_epilogue(const PassSplit& a, int pt, int64_
   const int wp = wave & 1;
   const int wf = wave >> 1;
   const bool of64 = a.out_f64 != 0;
+  const int64_t f = f0 + wf * 32 + (lane & 31);
+  if (f >= a.F) return;
+  const int64_t base = fibre_base(f, a.R_out, a.n);
+  const int m0 = pt * PT + wp * 32 + 4 * (lane >> 5);
   if (a.epi == EPI_NONE) {
-    // plain passes store straight from the accumulators (lanes 0..31 of a
-    // row take 32 consecutive fibres)
-    const int64_t f = f0 + wf * 32 + (lane & 31);
-    if (f < a.F) {
-      const int64_t base = fibre_base(f, a.R_out, a.n);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int m = pt * PT + wp * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        if (m >= a.n) continue;
-        const int64_t off = base + a.R_out * (int64_t)m;
-        reinterpret_cast<float2*>(a.out0)[off] = float2{accr[0][r], acci[0][r]};
-        reinterpret_cast<float2*>(a.out1)[off] = float2{accr[1][r], acci[1][r]};
-      }
-    }
-    return;
-  }
-  constexpr int EP = FT + 1;
-  float2* sE = reinterpret_cast<float2*>(lds_mem);
-#pragma unroll
-  for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int lr = wp * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      sE[(t * 64 + lr) * EP + wf * 32 + (lane & 31)] = float2{accr[t][r], acci[t][r]};
+      const int m = m0 + 8 * (r >> 2) + (r & 3);
+      if (m >= a.n) continue;
+      const int64_t off = base + a.R_out * (int64_t)m;
+      reinterpret_cast<float2*>(a.out0)[off] = float2{accr[0][r], acci[0][r]};
+      reinterpret_cast<float2*>(a.out1)[off] = float2{accr[1][r], acci[1][r]};
     }
-  __syncthreads();
-#pragma unroll 1
-  for (int e = tid; e < 64 * FT; e += 256) {
-    const int lr = e / FT, fc = e % FT;
-    const int m = pt * PT + lr;
-    const int64_t f = f0 + fc;
-    if (m >= a.n || f >= a.F) continue;
-    const int64_t off = fibre_base(f, a.R_out, a.n) + a.R_out * (int64_t)m;
-    const float2 v0 = sE[lr * EP + fc], v1 = sE[(64 + lr) * EP + fc];
-    const cd y0 = {static_cast<double>(v0.x), static_cast<double>(v0.y)};
-    const cd y1 = {static_cast<double>(v1.x), static_cast<double>(v1.y)};
-    if (a.epi == EPI_L4_R1) {
+  } else if (a.epi == EPI_L4_R1) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = m0 + 8 * (r >> 2) + (r & 3);
+      if (m >= a.n) continue;
+      const int64_t off = base + a.R_out * (int64_t)m;
+      const cd P = {static_cast<double>(accr[0][r]), static_cast<double>(acci[0][r])};
+      const cd Q = {static_cast<double>(accr[1][r]), static_cast<double>(acci[1][r])};
       cd X, Y;
-      lawson_r1(y0, y1, a.nl, X, Y);
+      lawson_r1(P, Q, a.nl, X, Y);
       store_c(a.out0, off, false, X);
       store_c(a.out1, off, false, Y);
-    } else {
-      const cd z = lawson_r2(y0, y1, a.nl);
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = m0 + 8 * (r >> 2) + (r & 3);
+      if (m >= a.n) continue;
+      const int64_t off = base + a.R_out * (int64_t)m;
+      const cd HX = {static_cast<double>(accr[0][r]), static_cast<double>(acci[0][r])};
+      const cd HY = {static_cast<double>(accr[1][r]), static_cast<double>(acci[1][r])};
+      const cd z = lawson_r2(HX, HY, a.nl);
       if (!finite2(z)) flag |= FLAG_NONFINITE;
       store_c(a.out0, off, of64, z);
     }
   }
-  __syncthreads();
 }
 
 // SAMEG: both products read in0; the second applies g first (P = H u and
@@ -858,8 +848,7 @@ __device__ __forceinline__ void split_tile_pair(const PassSplit& a, int pt, int6
   if (ks < nKS) stage(ks, sv[0], sv[1]);
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the last copies write the other buffer
   __syncthreads();
-  static_assert(EPI2_LDS_BYTES <= static_cast<int>(sizeof(LdsP<64, 16>)), "epilogue staging fits");
-  pair_epilogue(a, pt, f0, accr, acci, flag, &lds);
+  pair_epilogue(a, pt, f0, accr, acci, flag);
   if (flag) atomicOr(a.flag, flag);
 }
 
