@@ -641,42 +641,49 @@ __device__ __forceinline__ void pair_epilogue(const PassSplit& a, int pt, int64_
   const bool of64 = a.out_f64 != 0;
   const int64_t f = f0 + wf * 32 + (lane & 31);
   if (f >= a.F) return;
-  const int64_t base = fibre_base(f, a.R_out, a.n);
-  const int m0 = pt * PT + wp * 32 + 4 * (lane >> 5);
-  if (a.epi == EPI_NONE) {
+  // accumulator entry r holds row m1 + dm(r); its output element is o0 + R_out dm(r)
+  const int m1 = pt * PT + wp * 32 + 4 * (lane >> 5);
+  const int64_t Ro = a.R_out;
+  const int64_t o0 = fibre_base(f, a.R_out, a.n) + Ro * m1;
+  const bool full = pt * PT + PT <= a.n;  // uniform: the tile has no rows past n
+  auto each = [&](auto&& fn) __attribute__((always_inline)) {
+    if (full) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int m = m0 + 8 * (r >> 2) + (r & 3);
-      if (m >= a.n) continue;
-      const int64_t off = base + a.R_out * (int64_t)m;
-      reinterpret_cast<float2*>(a.out0)[off] = float2{accr[0][r], acci[0][r]};
-      reinterpret_cast<float2*>(a.out1)[off] = float2{accr[1][r], acci[1][r]};
+      for (int r = 0; r < 16; ++r) fn(r, Ro * (8 * (r >> 2) + (r & 3)));
+    } else {
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        if (m1 + 8 * (r >> 2) + (r & 3) < a.n) fn(r, Ro * (8 * (r >> 2) + (r & 3)));
     }
+  };
+  if (a.epi == EPI_NONE) {
+    float2* q0 = reinterpret_cast<float2*>(a.out0) + o0;
+    float2* q1 = reinterpret_cast<float2*>(a.out1) + o0;
+    each([&](int r, int64_t d) __attribute__((always_inline)) {
+      q0[d] = float2{accr[0][r], acci[0][r]};
+      q1[d] = float2{accr[1][r], acci[1][r]};
+    });
   } else if (a.epi == EPI_L4_R1) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int m = m0 + 8 * (r >> 2) + (r & 3);
-      if (m >= a.n) continue;
-      const int64_t off = base + a.R_out * (int64_t)m;
+    float2* q0 = reinterpret_cast<float2*>(a.out0) + o0;
+    float2* q1 = reinterpret_cast<float2*>(a.out1) + o0;
+    each([&](int r, int64_t d) __attribute__((always_inline)) {
       const cd P = {static_cast<double>(accr[0][r]), static_cast<double>(acci[0][r])};
       const cd Q = {static_cast<double>(accr[1][r]), static_cast<double>(acci[1][r])};
       cd X, Y;
       lawson_r1(P, Q, a.nl, X, Y);
-      store_c(a.out0, off, false, X);
-      store_c(a.out1, off, false, Y);
-    }
+      q0[d] = float2{static_cast<float>(X.re), static_cast<float>(X.im)};
+      q1[d] = float2{static_cast<float>(Y.re), static_cast<float>(Y.im)};
+    });
   } else {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int m = m0 + 8 * (r >> 2) + (r & 3);
-      if (m >= a.n) continue;
-      const int64_t off = base + a.R_out * (int64_t)m;
+    void* q0 = of64 ? static_cast<void*>(reinterpret_cast<double2*>(a.out0) + o0)
+                    : static_cast<void*>(reinterpret_cast<float2*>(a.out0) + o0);
+    each([&](int r, int64_t d) __attribute__((always_inline)) {
       const cd HX = {static_cast<double>(accr[0][r]), static_cast<double>(acci[0][r])};
       const cd HY = {static_cast<double>(accr[1][r]), static_cast<double>(acci[1][r])};
       const cd z = lawson_r2(HX, HY, a.nl);
       if (!finite2(z)) flag |= FLAG_NONFINITE;
-      store_c(a.out0, off, of64, z);
-    }
+      store_c(q0, d, of64, z);
+    });
   }
 }
 
