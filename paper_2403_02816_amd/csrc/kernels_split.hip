@@ -666,21 +666,23 @@ __device__ __forceinline__ void pair_epilogue(const PassSplit& a, int pt, int64_
   } else if (a.epi == EPI_L4_R1) {
     float2* q0 = reinterpret_cast<float2*>(a.out0) + o0;
     float2* q1 = reinterpret_cast<float2*>(a.out1) + o0;
+    const L4Coef c = lawson_coef(a.nl.tau);
     each([&](int r, int64_t d) __attribute__((always_inline)) {
       const cd P = {static_cast<double>(accr[0][r]), static_cast<double>(acci[0][r])};
       const cd Q = {static_cast<double>(accr[1][r]), static_cast<double>(acci[1][r])};
       cd X, Y;
-      lawson_r1(P, Q, a.nl, X, Y);
+      lawson_r1(P, Q, a.nl, c, X, Y);
       q0[d] = float2{static_cast<float>(X.re), static_cast<float>(X.im)};
       q1[d] = float2{static_cast<float>(Y.re), static_cast<float>(Y.im)};
     });
   } else {
     void* q0 = of64 ? static_cast<void*>(reinterpret_cast<double2*>(a.out0) + o0)
                     : static_cast<void*>(reinterpret_cast<float2*>(a.out0) + o0);
+    const double t6 = a.nl.tau / 6.0;
     each([&](int r, int64_t d) __attribute__((always_inline)) {
       const cd HX = {static_cast<double>(accr[0][r]), static_cast<double>(acci[0][r])};
       const cd HY = {static_cast<double>(accr[1][r]), static_cast<double>(acci[1][r])};
-      const cd z = lawson_r2(HX, HY, a.nl);
+      const cd z = lawson_r2(HX, HY, a.nl, t6);
       if (!finite2(z)) flag |= FLAG_NONFINITE;
       store_c(q0, d, of64, z);
     });

@@ -78,19 +78,34 @@ __device__ __forceinline__ bool finite2(cd u) { return isfinite(u.re) && isfinit
 //   u2 = P + tau/2 Q,  u3 = P + tau/2 g(u2),
 //   X = P + tau g(u3),  Y = P + tau/6 Q + tau/3 (g(u2) + g(u3)),
 // so that u4 = e^{tau K/2} X and u_{n+1} = e^{tau K/2} Y + tau/6 g(u4).
-__device__ __forceinline__ void lawson_r1(cd P, cd Q, const NlParams& p, cd& X, cd& Y) {
-  const double t = p.tau;
-  const cd u2 = caxpy(0.5 * t, Q, P);
+// The step fractions of tau that the combinations use, formed once per lane
+// (an FP64 division has no scalar form) and passed to the per-point code.
+struct L4Coef {
+  double h, t, t3, t6;  // tau/2, tau, tau/3, tau/6
+};
+__device__ __forceinline__ L4Coef lawson_coef(double tau) {
+  return {0.5 * tau, tau, tau / 3.0, tau / 6.0};
+}
+
+__device__ __forceinline__ void lawson_r1(cd P, cd Q, const NlParams& p, const L4Coef& c, cd& X,
+                                          cd& Y) {
+  const cd u2 = caxpy(c.h, Q, P);
   const cd g2 = g_cgl(u2, p);
-  const cd u3 = caxpy(0.5 * t, g2, P);
+  const cd u3 = caxpy(c.h, g2, P);
   const cd g3 = g_cgl(u3, p);
-  X = caxpy(t, g3, P);
-  Y = caxpy(t / 3.0, cadd(g2, g3), caxpy(t / 6.0, Q, P));
+  X = caxpy(c.t, g3, P);
+  Y = caxpy(c.t3, cadd(g2, g3), caxpy(c.t6, Q, P));
+}
+__device__ __forceinline__ void lawson_r1(cd P, cd Q, const NlParams& p, cd& X, cd& Y) {
+  lawson_r1(P, Q, p, lawson_coef(p.tau), X, Y);
 }
 
 // Lawson4 round 2 combination: u_{n+1} = HY + tau/6 g(HX)
+__device__ __forceinline__ cd lawson_r2(cd HX, cd HY, const NlParams& p, double t6) {
+  return caxpy(t6, g_cgl(HX, p), HY);
+}
 __device__ __forceinline__ cd lawson_r2(cd HX, cd HY, const NlParams& p) {
-  return caxpy(p.tau / 6.0, g_cgl(HX, p), HY);
+  return lawson_r2(HX, HY, p, p.tau / 6.0);
 }
 
 // ---- single-precision versions (prologues of the split-precision passes,
