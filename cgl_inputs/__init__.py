@@ -64,8 +64,15 @@ class Problem:
     coeffs: Coeffs
     tau: float
     steps: int
-    method: str  # "strang" or "lawson4"
+    method: str  # "strang", "lawson4", "split4", "lawson2", ...
     seed: int
+    #: condition at the right end of every direction (None: the same as ``bc``)
+    bc_hi: int | None = None
+    #: finite-difference order of the operators (2 or 4)
+    order: int = 2
+    #: initial datum: "" (the recipe of the grid's dimension) or "noise"
+    #: (standard normal / 5000, real, as in the experiments of Sections 4.1-4.2)
+    init: str = ""
 
     @property
     def d(self) -> int:
@@ -93,6 +100,18 @@ C1 = Problem("c1_cq3d_128_neumann_lawson4", (128, 128, 128), NEUMANN, -15.0, 15.
 C2 = Problem("c2_cq3d_256_dirichlet", (256, 256, 256), DIRICHLET, -15.0, 15.0,
              CQ, 2e-3, 200, "strang", 2)
 
+#: the paper's Table 1 setting: 2-D cubic CGL on (0,100)^2, 256^2 interior
+#: grid, homogeneous Dirichlet, 4th-order FD, a1=1, b1=2, a2=1, a3=-1, b3=0.2,
+#: small random initial datum, T = 6 (tau = T / steps).
+PAPER_CUBIC = Coeffs(1.0, 2.0, 1.0, -1.0, 0.2)
+T1 = Problem("t1_cubic2d_256_dirichlet_fd4", (256, 256), DIRICHLET, 0.0, 100.0,
+             PAPER_CUBIC, 6.0 / 100, 100, "split4", 10, order=4, init="noise")
+
+#: the paper's Table 3 setting: 3-D cubic CGL on (0,100)^3, 128^3 semi-internal
+#: grid per direction (Dirichlet at 0, Neumann at 100), 4th-order FD, T = 10.
+T3 = Problem("t3_cubic3d_128_dn_fd4", (128, 128, 128), DIRICHLET, 0.0, 100.0,
+             PAPER_CUBIC, 10.0 / 50, 50, "split4", 11, bc_hi=NEUMANN, order=4, init="noise")
+
 #: batched sweep: 512 2-D cubic instances (see ``batched_sweep``).
 C3_BATCH = 512
 C3_SIZES = (64, 96, 128, 160, 192)
@@ -107,8 +126,18 @@ C4_TRAIN_SEED = 4
 C4_EVAL_SEED = 5
 
 
-def nodes(n: int, a: float, b: float, bc: int) -> np.ndarray:
-    """1-D grid nodes for ``n`` unknowns on (a, b) (see module docstring)."""
+def nodes(n: int, a: float, b: float, bc: int, bc_hi: int | None = None) -> np.ndarray:
+    """1-D grid nodes for ``n`` unknowns on (a, b) (see module docstring).
+    With ``bc_hi`` the two ends may differ: a Dirichlet end is not a node, a
+    Neumann end is one (DN: x_j = a + j h, j = 1..n, h = (b-a)/n)."""
+    if bc_hi is not None and bc_hi != bc:
+        if bc == DIRICHLET and bc_hi == NEUMANN:
+            h = (b - a) / n
+            return a + h * np.arange(1, n + 1, dtype=np.float64)
+        if bc == NEUMANN and bc_hi == DIRICHLET:
+            h = (b - a) / n
+            return a + h * np.arange(0, n, dtype=np.float64)
+        raise ValueError("bc must be DIRICHLET or NEUMANN")
     if bc == DIRICHLET:
         h = (b - a) / (n + 1)
         return a + h * np.arange(1, n + 1, dtype=np.float64)
@@ -165,6 +194,9 @@ def vortex_ring_3d(n: Sequence[int], a: float, b: float, bc: int, seed: int,
 
 def initial_state(p: Problem) -> np.ndarray:
     """Seeded u0 of shape p.n (complex128)."""
+    if p.init == "noise":
+        rng = np.random.default_rng(p.seed)
+        return (rng.standard_normal(p.n) / 5000.0).astype(np.complex128)
     if p.d == 2:
         return gaussian_phase_2d(p.n, p.a, p.b, p.bc, p.seed)
     if p.d == 3:

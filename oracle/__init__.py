@@ -22,8 +22,6 @@ Contents (each function cites the passage it follows):
   written (six exponential actions per Lawson4 step), plus a time loop.
 * ``metrics``    -- relative 2-norm / infinity-norm errors and the observed
   order of convergence used in the paper's tables.
-* ``split``      -- bf16 term split and an FP32-accumulation emulator of the
-  split-precision mode product (predicts its rounding error).
 * ``surrogate``  -- FP64 residual CNN forward/backward (3x3 convolutions).
 
 All arithmetic is complex128 / float64 unless a function says otherwise.

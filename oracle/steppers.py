@@ -1,5 +1,5 @@
-"""Strang and Lawson4 steps, written exactly as in the paper (oracle; test
-infrastructure only).
+"""Strang, split4, Lawson2 and Lawson4 steps and the three-term splittings,
+written exactly as in the paper (oracle; test infrastructure only).
 
 * Strang (eq. Strang): u_{n+1} = phi_{tau/2}( e^{tau K} phi_{tau/2}(u_n) ).
   Both half flows are evaluated; consecutive half flows of two steps are not
@@ -12,8 +12,21 @@ infrastructure only).
   where e^{tau K} and e^{tau K/2} act through the Tucker operator (eq. Tucker)
   with the matrices E_mu = exp(tau A_mu) and H_mu = exp(tau A_mu / 2).
 
-The nonlinear part is an object with ``g(u)`` and ``flow(u, t)`` so that the
-same steppers run the CGL nonlinearity and the closed-form test problems.
+* split4 (eq. Richardson, the explicit form of eq. richextrap):
+      u_n2 = phi_{tau/2}(e^{tau K} phi_{tau/2}(u_n))
+      u_{n+1} = 4/3 phi_{tau/4}(e^{tau K/2} phi_{tau/2}(e^{tau K/2} phi_{tau/4}(u_n))) - 1/3 u_n2
+  (the middle sub-flow is one evaluation of phi over tau/2, as printed).
+* Lawson2b (eq. lawson2b):
+      u_n2 = e^{tau K}(u_n + tau g(u_n))
+      u_{n+1} = e^{tau K}(u_n + tau/2 g(u_n)) + tau/2 g(u_n2)
+* strang_3t (Section 4.3): S3_tau(u) = phi^q_{tau/2}(phi^c_{tau/2}(e^{tau K}
+  phi^c_{tau/2}(phi^q_{tau/2}(u)))) with the exact cubic and quintic flows;
+  split4_3t = 4/3 S3_{tau/2}(S3_{tau/2}(u)) - 1/3 S3_tau(u), composed as
+  written (S3_{tau/2} uses e^{tau K/2}).
+
+The nonlinear part is an object with ``g(u)`` and ``flow(u, t)`` (and, for
+the three-term schemes, ``phi_c`` / ``phi_q``) so that the same steppers run
+the CGL nonlinearity and the closed-form test problems.
 """
 from __future__ import annotations
 
@@ -46,10 +59,20 @@ class CGLNonlinearity:
 
     def flow(self, u: np.ndarray, t: float) -> np.ndarray:
         if self.exact:
-            v, bad = nonlinear.phi_cubic(u, t, self.coeffs[3], self.coeffs[4])
-            self.blowups += int(np.count_nonzero(bad))
-            return v
+            return self.phi_c(u, t)
         return nonlinear.rk4_flow(u, t, self.g)
+
+    def phi_c(self, u: np.ndarray, t: float) -> np.ndarray:
+        """Exact flow of the cubic part (eq. exsolcub)."""
+        v, bad = nonlinear.phi_cubic(u, t, self.coeffs[3], self.coeffs[4])
+        self.blowups += int(np.count_nonzero(bad))
+        return v
+
+    def phi_q(self, u: np.ndarray, t: float) -> np.ndarray:
+        """Exact flow of the quintic part (Section 4.3)."""
+        v, bad = nonlinear.phi_quintic(u, t, self.coeffs[5], self.coeffs[6])
+        self.blowups += int(np.count_nonzero(bad))
+        return v
 
 
 def strang_step(u: np.ndarray, E: Sequence[np.ndarray], tau: float, nl) -> np.ndarray:
@@ -71,6 +94,37 @@ def lawson4_step(u: np.ndarray, E: Sequence[np.ndarray], H: Sequence[np.ndarray]
             + (tau / 6.0) * g4)
 
 
+def split4_step(u: np.ndarray, E: Sequence[np.ndarray], H: Sequence[np.ndarray],
+                tau: float, nl) -> np.ndarray:
+    un2 = nl.flow(tucker(nl.flow(u, 0.5 * tau), E), 0.5 * tau)
+    v = nl.flow(u, 0.25 * tau)
+    v = tucker(v, H)
+    v = nl.flow(v, 0.5 * tau)
+    v = tucker(v, H)
+    v = nl.flow(v, 0.25 * tau)
+    return (4.0 / 3.0) * v - (1.0 / 3.0) * un2
+
+
+def lawson2_step(u: np.ndarray, E: Sequence[np.ndarray], tau: float, nl) -> np.ndarray:
+    g1 = nl.g(u)
+    un2 = tucker(u + tau * g1, E)
+    return tucker(u + 0.5 * tau * g1, E) + 0.5 * tau * nl.g(un2)
+
+
+def strang_3t_step(u: np.ndarray, E: Sequence[np.ndarray], tau: float, nl) -> np.ndarray:
+    t = 0.5 * tau
+    v = nl.phi_c(nl.phi_q(u, t), t)
+    w = tucker(v, E)
+    return nl.phi_q(nl.phi_c(w, t), t)
+
+
+def split4_3t_step(u: np.ndarray, E: Sequence[np.ndarray], H: Sequence[np.ndarray],
+                   tau: float, nl) -> np.ndarray:
+    full = strang_3t_step(u, E, tau, nl)
+    half = strang_3t_step(strang_3t_step(u, H, 0.5 * tau, nl), H, 0.5 * tau, nl)
+    return (4.0 / 3.0) * half - (1.0 / 3.0) * full
+
+
 def rk4_step_nonlinear(u: np.ndarray, tau: float, nl) -> np.ndarray:
     """Classical RK4 (eq. RK4) for u' = g(u), i.e. with K = 0."""
     return nonlinear.rk4_flow(u, tau, nl.g)
@@ -81,6 +135,14 @@ def make_step(method: str, E, H, tau: float, nl) -> Callable[[np.ndarray], np.nd
         return lambda u: strang_step(u, E, tau, nl)
     if method == "lawson4":
         return lambda u: lawson4_step(u, E, H, tau, nl)
+    if method == "split4":
+        return lambda u: split4_step(u, E, H, tau, nl)
+    if method == "lawson2":
+        return lambda u: lawson2_step(u, E, tau, nl)
+    if method == "strang_3t":
+        return lambda u: strang_3t_step(u, E, tau, nl)
+    if method == "split4_3t":
+        return lambda u: split4_3t_step(u, E, H, tau, nl)
     raise ValueError(method)
 
 
@@ -96,8 +158,17 @@ def run(u0: np.ndarray, step: Callable[[np.ndarray], np.ndarray], m: int,
 
 
 def operators_for(problem, t: float, route: str = "closed") -> List[np.ndarray]:
-    """exp(t A_mu) for every direction of a workload (closed form or scipy)."""
+    """exp(t A_mu) for every direction of a workload (closed form or scipy).
+    Workloads with fourth-order or mixed-boundary operators have no closed
+    form here and always take the scipy route."""
     from . import operators as ops
+    order = getattr(problem, "order", 2)
+    bc_hi = getattr(problem, "bc_hi", None)
+    if order != 2 or (bc_hi is not None and bc_hi != problem.bc):
+        hi = problem.bc if bc_hi is None else bc_hi
+        return [ops.exp_scipy(ops.operator_A_fd(n, problem.a, problem.b, problem.bc, hi, order,
+                                                problem.coeffs.as_tuple(), problem.d), t)
+                for n in problem.n]
     out = []
     for n in problem.n:
         if route == "closed":
