@@ -1,16 +1,20 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the CGL exponential stepper on one MI355X.
 
-Workload (default): 3-D cubic-quintic CGL on a 128^3 Neumann vertex grid on
-(-15,15)^3, 2nd-order FD, Lawson4 with tau = 5e-3, seeded Gaussian vortex
-ring u0.  One step = one Lawson4 step of the whole grid: four actions of
-e^{tau K/2} (three mu-mode passes each), with g and the Lawson4 stage
-combinations fused into the first-pass prologues and last-pass epilogues.
+Workload (default): 3-D cubic-quintic CGL on a 256^3 interior grid on
+(-15,15)^3 with homogeneous Dirichlet boundaries, 2nd-order FD, Lawson4 with
+tau = 2e-3, seeded Gaussian vortex ring u0 (16.8M grid points).  One step =
+one Lawson4 step of the whole grid: four actions of e^{tau K/2} (three
+mu-mode passes each), run as two rounds of three paired passes, with g and
+the Lawson4 stage combinations fused into the first-pass prologue and the
+last-pass epilogues.
 
 The timed form is the split-precision form (complex64 stage tensors,
-bf16x3 operands, FP32 accumulation); the FP64 form is timed beside it.
-Inputs are resident in HBM before the timed region; the steps are replayed
-from a captured HIP graph (cgl_run).  Prints ONE JSON line.
+bf16x3 operands, FP32 accumulation); the FP64 form and the split Strang
+step of the same grid are timed beside it.  Inputs are resident in HBM
+before the timed region; the K steps are replayed from a captured HIP graph
+(cgl_run), the state reset to u0 before each replay, and the median of the
+replays is reported.  Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -29,13 +33,29 @@ MI355X_PEAK_BF16_TFLOPS = 2500.0  # dense MFMA
 MI355X_PEAK_FP64_TFLOPS = 78.6
 MI355X_PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per split-pass launch of the 128^3 Lawson4 workload from two
-# rocprofv3 counter runs (FETCH_SIZE x 2 + WRITE_SIZE, scale factors measured
-# on a 256 MiB device copy; profiles/split_pass_c1_128_lawson4.md), valid for
-# the kernel sources whose digest is recorded with them.
-SPLIT_TRAFFIC_C1 = {"bytes_per_launch": 63295264.0, "sources_sha256_16": "4d24c1d2e3e7704d"}
+# HBM bytes per launch of the dominant kernel of a workload, from two
+# rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled
+# by the factor the same counter reads for a 256 MiB device copy in the same
+# run), valid only for the kernel sources whose digest is recorded with them
+# (profiles/split_pass_c1_128_lawson4.md, profiles/split_pass_c2_256_lawson4.md).
+SPLIT_TRAFFIC = {
+    "c1": {"bytes_per_launch": 63295264.0, "sources_sha256_16": "4d24c1d2e3e7704d"},
+    # mean over the six paired launches of a step: (FETCH_SIZE x 2 + WRITE_SIZE) KiB
+    # = (142956 x 2 + 240299) KiB
+    "c2_lawson4": {"bytes_per_launch": 538840064.0, "sources_sha256_16": "4d24c1d2e3e7704d"},
+}
 SPLIT_SOURCES = ("kernels_split.hip", "kernels.hpp", "pointwise.hpp", "split_layout.cpp",
                  "split_layout.hpp")
+
+# The paper's own throughput on the nearest workload (context, not the target:
+# another machine, another precision, 4th-order FD, 128^3 rather than 256^3).
+PAPER_TABLE3 = {
+    "source": "Table 3: 3-D cubic CGL, 128^3, Dirichlet on x1x2x3 = 0 faces and Neumann "
+              "elsewhere, if4 (Lawson4), T = 10",
+    "hardware": "Intel Core i7-10750H (6 cores), MATLAB R2022a, FP64, level-3 BLAS",
+    "if4_steps": 250, "if4_time_s": 120.6, "grid_points": 128 ** 3,
+    "gp_steps_per_s": 128 ** 3 * 250 / 120.6,
+}
 
 
 def split_sources_digest():
@@ -50,14 +70,18 @@ def split_sources_digest():
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c1",
-                    choices=["c1", "c2_strang", "c2_lawson4", "c3", "c4"])
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--replays", type=int, default=5,
+                    help="graph replays of the K timed steps (median reported)")
+    ap.add_argument("--workload", default="c2_lawson4",
+                    choices=["c2_lawson4", "c2_strang", "c1", "c3", "c4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--cpu-budget-s", type=float, default=12.0,
-                    help="host time spent on the oracle baseline (whole steps)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the second method timed beside the workload")
+    ap.add_argument("--cpu-budget-s", type=float, default=15.0,
+                    help="host time spent on the oracle baseline (whole steps, at least one)")
     ap.add_argument("--cpu-max-steps", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (a kernel of known "
@@ -89,37 +113,42 @@ def launches_per_step(method, d, paired=False):
     return 2 * d if paired else 4 * d
 
 
-def time_form(p, method, precision, steps, warmup, u0):
+def time_form(p, method, precision, steps, warmup, u0, replays):
+    """Plan, warm up, capture the graph of `steps` steps, then replay it
+    `replays` times from u0 (reset outside the timed region), each replay
+    bracketed by HIP events on the stream the plan joins (torch's current
+    stream).  Returns (plan, final state after the last replay = `steps`
+    steps from u0, list of replay times in ms)."""
     import torch
     from paper_2403_02816_amd import cgl
     plan = cgl.Plan(p.n, p.coeffs, p.tau, precision=precision)
     plan.set_fd_operators(p.a, p.b, p.bc, p.coeffs)
     u = plan.to_device(u0)
-    # warm-up: also captures the graph of `steps` steps used below
+    u_init = u.clone()
     if warmup > 0:
         st = plan.run(method, u, warmup, warmup)
         assert st == 0, st
     st = plan.run(method, u, steps, steps)  # graph capture of the timed chunk size
     assert st == 0, st
-    u.copy_(plan.to_device(u0))
-    torch.cuda.synchronize()
-    s = torch.cuda.Stream()  # events on the plan's stream: the default stream
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(torch.cuda.current_stream())
-    t0 = time.perf_counter()
-    st = plan.run(method, u, steps, steps)
-    ev1.record(torch.cuda.current_stream())
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    assert st == 0, st
-    ms = ev0.elapsed_time(ev1)
-    del s
-    return plan, u, ms, wall
+    times = []
+    stream = torch.cuda.current_stream()
+    for _ in range(max(1, replays)):
+        u.copy_(u_init)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        st = plan.run(method, u, steps, steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        assert st == 0, st
+        times.append(ev0.elapsed_time(ev1))
+    return plan, u, times
 
 
 def one_step_gate(p, method, plan):
-    """Relative 2-norm of one split step vs the FP64 oracle step (same input)."""
+    """One split step vs the FP64 oracle step from the same (complex64) input:
+    (relative 2-norm, relative max-norm = the paper's measure)."""
     import torch
     import cgl_inputs as ci
     from oracle import metrics, steppers
@@ -133,11 +162,12 @@ def one_step_gate(p, method, plan):
         E = [h @ h for h in H]
     nl = steppers.CGLNonlinearity(p.coeffs.as_tuple())
     ref = steppers.make_step(method, E, H, p.tau, nl)(u0)
-    return metrics.rel_l2(plan.to_host(u), ref)
+    got = plan.to_host(u)
+    return metrics.rel_l2(got, ref), metrics.rel_linf(got, ref)
 
 
-def _cores():
-    """Threads the host math libraries use."""
+def _blas_threads():
+    """Threads the host BLAS uses."""
     try:
         from threadpoolctl import threadpool_info
         return int(max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()]))
@@ -145,10 +175,30 @@ def _cores():
         return int(os.cpu_count())
 
 
+def _host_cpu_info():
+    """Physical cores of the host (lscpu: distinct (core, socket) pairs) and
+    the CPUs this process may run on."""
+    import subprocess
+    phys = None
+    try:
+        out = subprocess.run(["lscpu", "-p=CORE,SOCKET"], capture_output=True, text=True,
+                             timeout=10).stdout
+        phys = len({ln for ln in out.splitlines() if ln and not ln.startswith("#")})
+    except Exception:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except Exception:
+        aff = os.cpu_count()
+    return phys, aff
+
+
 def cpu_baseline(p, method, budget_s, max_steps):
-    """The FP64 oracle (as written: six exponential actions per Lawson4 step)
-    timed on the host cores on a bounded sample of full-grid steps: steps
-    until the time budget is spent (at least one, at most max_steps)."""
+    """The FP64 oracle as written (six exponential actions per Lawson4 step,
+    numpy tensordot on the host BLAS) timed on the host cores on a bounded
+    sample: whole full-grid steps until the time budget is spent (at least
+    one, at most max_steps), with all BLAS threads; then one more step with
+    one BLAS thread."""
     import cgl_inputs as ci
     from oracle import steppers
     E = steppers.operators_for(p, p.tau)
@@ -156,17 +206,30 @@ def cpu_baseline(p, method, budget_s, max_steps):
     nl = steppers.CGLNonlinearity(p.coeffs.as_tuple())
     step = steppers.make_step(method, E, H, p.tau, nl)
     u = ci.initial_state(p)
-    u = step(u)  # warm-up step
     nsteps = 0
     t0 = time.perf_counter()
     while nsteps < max_steps and (nsteps == 0 or time.perf_counter() - t0 < budget_s):
         u = step(u)
         nsteps += 1
     dt = time.perf_counter() - t0
-    return {"value": p.N * nsteps / dt, "unit": "grid-point-steps/s", "cores": _cores(),
-            "kind": "oracle",
-            "sample": f"{nsteps} {method} steps of the full {'x'.join(map(str, p.n))} grid "
-                      f"(numpy FP64, literal scheme), after 1 warm-up step; {dt:.2f} s"}
+    threads = _blas_threads()
+    phys, aff = _host_cpu_info()
+    one = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            u = step(u)
+            s1 = time.perf_counter() - t1
+        one = {"threads": 1, "value": p.N / s1, "step_s": s1,
+               "sample": f"one {method} step of the full grid with one BLAS thread"}
+    except Exception as e:  # threadpoolctl missing: report without the 1-thread figure
+        one = {"error": repr(e)}
+    return {"value": p.N * nsteps / dt, "unit": "grid-point-steps/s", "cores": threads,
+            "kind": "oracle", "physical_cores_lscpu": phys, "affinity_cpus": aff,
+            "sample": f"{nsteps} {method} step(s) of the full {'x'.join(map(str, p.n))} grid "
+                      f"(numpy FP64, literal scheme, {threads} BLAS threads); {dt:.2f} s",
+            "one_thread": one}
 
 
 def bench_batched(args):
@@ -185,39 +248,44 @@ def bench_batched(args):
     t_setup = time.perf_counter() - t_setup
     u0 = [ci.initial_state(p) for p in probs]
     u = bp.to_device_batched(u0)
+    u_init = u.clone()
     if W > 0:
         assert bp.run("lawson4", u, W, W) == 0
     assert bp.run("lawson4", u, K, K) == 0  # captures the timed chunk's graph
-    u.copy_(bp.to_device_batched(u0))
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    assert bp.run("lawson4", u, K, K) == 0
-    ev1.record()
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
+    times = []
+    for _ in range(max(1, args.replays)):
+        u.copy_(u_init)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        assert bp.run("lawson4", u, K, K) == 0
+        ev1.record()
+        torch.cuda.synchronize()
+        times.append(ev0.elapsed_time(ev1))
+    ms = float(np.median(times))
     Ntot = sum(p.N for p in probs)
     launches = launches_per_step("lawson4", 2, paired_lawson4("lawson4"))  # persistent launches
     launch_ms = ms / (K * launches)
     mfma = sum(6.0 * 8.0 * p.N * (p.n[0] + p.n[1]) for p in probs) * 4 / launches
     achieved = mfma / (launch_ms * 1e-3) / 1e12
-    # one-step gate on a sample of instances, oracle on their exponentials
+    # one-step gate of every instance, oracle on each instance's exponentials
     from oracle import steppers
-    sample = list(range(0, len(probs), 64))
     ug = bp.to_device_batched([ci.initial_state(p).astype(np.complex64) for p in probs])
     bp.step_lawson4(ug, 1)
     torch.cuda.synchronize()
     outs = bp.to_host_batched(ug)
     gate = 0.0
-    for j in sample:
-        p = probs[j]
+    gate_inf = 0.0
+    for j, p in enumerate(probs):
         H = [bp.get_instance_operator(j, mu, 1) for mu in range(2)]
         E = [h @ h for h in H]
         nl = steppers.CGLNonlinearity(p.coeffs.as_tuple())
         ref = steppers.lawson4_step(ci.initial_state(p).astype(np.complex64).astype(np.complex128),
                                     E, H, p.tau, nl)
         gate = max(gate, metrics.rel_l2(outs[j], ref))
+        gate_inf = max(gate_inf, metrics.rel_linf(outs[j], ref))
+    sample = probs
     split_state = u.clone()
     bp.destroy()
     fp64 = None
@@ -234,7 +302,7 @@ def bench_batched(args):
         s64 = time.perf_counter() - t0
         fp64 = {"value": Ntot * K / s64, "ms_per_step": 1e3 * s64 / K,
                 "note": "FP64 form, one launch per instance and pass (eager)"}
-        a = bp_split = split_state.to(torch.complex128)
+        a = split_state.to(torch.complex128)
         traj = max(float(torch.linalg.vector_norm(a[o:o + p.N] - v[o:o + p.N]).item()
                          / torch.linalg.vector_norm(v[o:o + p.N]).item())
                    for p, o in zip(probs, b64.offsets))
@@ -256,8 +324,10 @@ def bench_batched(args):
                      "unit": "TFLOP/s", "frac": achieved / MI355X_PEAK_BF16_TFLOPS,
                      "traffic": None, "kernel": ("k_pass_split_batched_pair (persistent, both actions of a Lawson4 round)" if paired_lawson4("lawson4") else "k_pass_split_batched (persistent)"),
                      "launch_ms": launch_ms},
-        "accuracy": {"one_step_rel_l2_vs_fp64_oracle_max_sampled": gate, "gate": 1e-6,
-                     "sampled_instances": len(sample),
+        "replays_ms": times,
+        "accuracy": {"one_step_rel_l2_vs_fp64_oracle_max": gate,
+                     "one_step_rel_linf_vs_fp64_oracle_max": gate_inf, "gate": 1e-6,
+                     "gated_instances": len(sample),
                      "trajectory_rel_l2_vs_fp64_form_max": traj, "trajectory_steps": K},
         "fp64_form": fp64, "cpu_baseline": cpu, "setup_s": t_setup,
     }
@@ -439,8 +509,37 @@ def cpu_baseline_surrogate(data, S):
         done += 1
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "jumps/s (forward passes of one 128^2 sample)",
-            "cores": _cores(), "kind": "oracle",
+            "cores": _blas_threads(), "kind": "oracle",
             "sample": f"{done} forward passes of the FP64 numpy network; {dt:.2f} s"}
+
+
+def split_roofline(p, method, times_ms, steps):
+    """Roofline of the dominant kernel of a split-form step, from the median
+    replay: every launch of the step is the same pass kernel (the paired pass
+    for Lawson4, the autotuned single-action pass for Strang), so its average
+    launch duration is the timed region divided by the launches."""
+    ms = float(np.median(times_ms))
+    paired = paired_lawson4(method)
+    nl = launches_per_step(method, p.d, paired)
+    launch_ms = ms / (steps * nl)
+    # algorithmic work of one launch: every grid point gets one complex
+    # mu-mode product of length n (8 n real flops) per product (two in a
+    # paired pass); the split form issues 6 bf16 term products for each, so
+    # its MFMA work is 6x that
+    prod = 2 if paired else 1
+    n_mu = p.n[0]
+    alg_flops = 8.0 * p.N * n_mu * prod
+    mfma_flops = 6.0 * alg_flops
+    alg_bytes = p.N * (8 + 8) * prod
+    achieved_tf = mfma_flops / (launch_ms * 1e-3) / 1e12
+    return {"bound": "mfma", "achieved": achieved_tf, "peak": MI355X_PEAK_BF16_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved_tf / MI355X_PEAK_BF16_TFLOPS,
+            "kernel": ("k_pass_split_pair (both actions of a Lawson4 round per launch)" if paired
+                       else "k_pass_split_dma / k_pass_split (the autotuned split pass)"),
+            "launch_ms": launch_ms, "launches_per_step": nl,
+            "mfma_flops_per_launch": mfma_flops, "alg_flops_per_launch": alg_flops,
+            "alg_bytes_per_launch": alg_bytes,
+            "hbm_gbs_algorithmic": alg_bytes / (launch_ms * 1e-3) / 1e9}
 
 
 def main():
@@ -458,7 +557,7 @@ def main():
         return bench_surrogate(args)
     p, method = workload(args.workload)
     u0 = ci.initial_state(p)
-    K, W = args.steps, args.warmup
+    K, W, R = args.steps, args.warmup, args.replays
     if args.calibrate_copy:
         a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
         b = torch.ones_like(a)
@@ -466,35 +565,45 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    plan, u, ms, wall = time_form(p, method, "split", K, W, u0)
-    ms_step = ms / K
+    plan, u, times = time_form(p, method, "split", K, W, u0, R)
+    ms = float(np.median(times))
     value = p.N * K / (ms * 1e-3)
-    paired = paired_lawson4(method)
-    nl = launches_per_step(method, p.d, paired)
-    launch_ms = ms / (K * nl)
-    # algorithmic work of one launch: every grid point gets one complex
-    # mu-mode product of length n (8 n real flops) per product (two in a
-    # paired pass); the split form issues 6 bf16 term products for each, so
-    # its MFMA work is 6x that
-    prod = 2 if paired else 1
-    n_mu = p.n[0]
-    alg_flops = 8.0 * p.N * n_mu * prod
-    mfma_flops = 6.0 * alg_flops
-    alg_bytes = p.N * (8 + 8) * prod
-    achieved_tf = mfma_flops / (launch_ms * 1e-3) / 1e12
-    gate = one_step_gate(p, method, plan)
+    roof = split_roofline(p, method, times, K)
+    gate_l2, gate_linf = one_step_gate(p, method, plan)
     split_state = u.clone()
     plan.destroy()
+
+    # the other method on the same grid and form (Strang beside Lawson4)
+    extra = None
+    if not args.no_extra and args.workload in ("c2_lawson4", "c2_strang"):
+        m2 = "strang" if method == "lawson4" else "lawson4"
+        plan2, u2, t2 = time_form(p, m2, "split", K, W, u0, R)
+        ms2 = float(np.median(t2))
+        r2 = split_roofline(p, m2, t2, K)
+        g2 = one_step_gate(p, m2, plan2)
+        plan2.destroy()
+        del u2
+        extra = {"method": m2, "value": p.N * K / (ms2 * 1e-3), "ms_per_step": ms2 / K,
+                 "replays_ms": t2, "roofline_frac": r2["frac"], "launch_ms": r2["launch_ms"],
+                 "kernel": r2["kernel"], "one_step_rel_l2_vs_fp64_oracle": g2[0],
+                 "one_step_rel_linf_vs_fp64_oracle": g2[1]}
 
     fp64 = None
     traj = None
     if not args.no_fp64:
-        plan64, u64, ms64, _ = time_form(p, method, "fp64", K, W, u0)
-        traj = float(torch.linalg.vector_norm(split_state.to(torch.complex128) - u64).item()
-                     / torch.linalg.vector_norm(u64).item())
-        fp64 = {"value": p.N * K / (ms64 * 1e-3), "ms_per_step": ms64 / K,
-                "mfma_tflops": alg_flops / ((ms64 / (K * nl)) * 1e-3) / 1e12,
-                "peak_tflops": MI355X_PEAK_FP64_TFLOPS}
+        plan64, u64, t64 = time_form(p, method, "fp64", K, W, u0, R)
+        ms64 = float(np.median(t64))
+        d = split_state.to(torch.complex128) - u64
+        traj = {"rel_l2": float(torch.linalg.vector_norm(d).item()
+                                / torch.linalg.vector_norm(u64).item()),
+                "rel_linf": float(d.abs().max().item() / u64.abs().max().item())}
+        nl64 = launches_per_step(method, p.d, False)
+        alg_flops = 8.0 * p.N * p.n[0]
+        fp64 = {"value": p.N * K / (ms64 * 1e-3), "ms_per_step": ms64 / K, "replays_ms": t64,
+                "mfma_tflops": alg_flops / ((ms64 / (K * nl64)) * 1e-3) / 1e12,
+                "peak_tflops": MI355X_PEAK_FP64_TFLOPS,
+                "note": "two actions per Lawson4 round as concurrent graph branches; "
+                        "TFLOP/s over the timed region"}
         fp64["frac"] = fp64["mfma_tflops"] / MI355X_PEAK_FP64_TFLOPS
         plan64.destroy()
 
@@ -502,9 +611,13 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(p, method, args.cpu_budget_s, args.cpu_max_steps)
 
+    tkey = {"c1": "c1", "c2_lawson4": "c2_lawson4"}.get(args.workload)
     traffic = None
-    if args.workload == "c1" and split_sources_digest() == SPLIT_TRAFFIC_C1["sources_sha256_16"]:
-        traffic = SPLIT_TRAFFIC_C1["bytes_per_launch"]
+    if tkey in SPLIT_TRAFFIC and paired_lawson4(method) and \
+            split_sources_digest() == SPLIT_TRAFFIC[tkey]["sources_sha256_16"]:
+        traffic = SPLIT_TRAFFIC[tkey]["bytes_per_launch"]
+    roof["traffic"] = traffic
+    bc = "Neumann" if p.bc else "Dirichlet"
     rec = {
         "metric": "grid-point-steps/s at rel-L2 <=1e-6 vs FP64 oracle; MFMA util % of peak",
         "value": value,
@@ -512,28 +625,25 @@ def main():
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
-        "ms_per_step": ms_step,
+        "ms_per_step": ms / K,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "bf16x3->f32 (split), state c64",
         "data": "synthetic",
         "config": {"workload": f"{p.name}: 3-D cubic-quintic CGL {'x'.join(map(str, p.n))} "
-                               f"{'Neumann' if p.bc else 'Dirichlet'}, {method}, tau={p.tau}, "
-                               f"split-precision form",
-                   "grid": list(p.n), "method": method, "tau": p.tau, "parallelism": "single-gpu"},
-        "roofline": {"bound": "mfma", "achieved": achieved_tf, "peak": MI355X_PEAK_BF16_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tf / MI355X_PEAK_BF16_TFLOPS,
-                     "traffic": traffic,
-                     "kernel": ("k_pass_split_pair (both actions of a Lawson4 round per launch)" if paired
-                                else "k_pass_split_dma / k_pass_split (the autotuned split pass)"),
-                     "launch_ms": launch_ms,
-                     "hbm_gbs": alg_bytes / (launch_ms * 1e-3) / 1e9},
-        "accuracy": {"one_step_rel_l2_vs_fp64_oracle": gate, "gate": 1e-6,
-                     "trajectory_rel_l2_vs_fp64_form": traj, "trajectory_steps": K + W},
+                               f"{bc}, 2nd-order FD, {method}, tau={p.tau}, split-precision form",
+                   "grid": list(p.n), "method": method, "tau": p.tau,
+                   "parallelism": "single-gpu"},
+        "replays_ms": times,
+        "roofline": roof,
+        "accuracy": {"one_step_rel_l2_vs_fp64_oracle": gate_l2,
+                     "one_step_rel_linf_vs_fp64_oracle": gate_linf, "gate": 1e-6,
+                     "trajectory_vs_fp64_form": traj, "trajectory_steps": K},
+        "other_method": extra,
         "fp64_form": fp64,
         "cpu_baseline": cpu,
-        "wall_s_timed_region": wall,
+        "paper_context": PAPER_TABLE3,
     }
     print(json.dumps(rec))
 
