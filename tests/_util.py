@@ -44,5 +44,23 @@ def rel_l2(a, b) -> float:
     return metrics.rel_l2(a, b)
 
 
+def errors(a, b):
+    """(relative 2-norm, relative max-norm) of a against b.  The max-norm
+    error max|a - b| / max|b| is the paper's accuracy measure (Section 4);
+    it bounds every element, so a localised error (one wrong plane of a
+    tensor) that the 2-norm would dilute fails it."""
+    return metrics.rel_l2(a, b), metrics.rel_linf(a, b)
+
+
+def assert_close(got, ref, tol, what="", linf_tol=None):
+    """Both measures within their bounds (the max-norm bound defaults to the
+    2-norm bound).  Returns (rel_l2, rel_linf)."""
+    l2, linf = errors(got, ref)
+    lt = tol if linf_tol is None else linf_tol
+    log(f"{what}: rel-L2 {l2:.3e}, rel-Linf {linf:.3e} (bounds {tol:.0e}, {lt:.0e})")
+    assert l2 < tol and linf < lt, (what, l2, linf, tol, lt)
+    return l2, linf
+
+
 def log(msg: str):
     print(msg, flush=True)

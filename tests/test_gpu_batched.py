@@ -1,18 +1,24 @@
 """GPU tests of batched plans (many independent 2-D instances with their own
 grids and coefficients, stepped together by persistent launches).
 
-* one-step gate of the split form for every instance vs the FP64 oracle
-  stepping on that instance's exponentials (relative 2-norm <= 1e-6);
+* one-step gate of the split form for every instance of the 512-instance
+  sweep (seed 3, the benchmarked workload) vs the FP64 oracle stepping on
+  that instance's exponentials (relative 2-norm and max-norm <= 1e-6), for
+  Lawson4 and for Strang;
 * the batched split plan equals one plain plan per instance bitwise (same
-  kernels and tile shape on the same data);
-* the FP64 batched form matches the oracle over 10 Lawson4 steps (<= 1e-12);
+  kernels and tile shape on the same data), for the paired Lawson4 pass
+  and for every single-action tile shape;
+* the paired and the two-action batched Lawson4 schedules give identical
+  bits;
+* the FP64 batched form matches the oracle over 10 Lawson4 / Strang steps
+  (<= 1e-12);
 * graph replay equals eager steps bitwise.
 """
 import numpy as np
 import pytest
 
 import cgl_inputs as ci
-from tests._util import log, oracle_run, rel_l2, require_gpu
+from tests._util import assert_close, errors, log, oracle_run, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -33,37 +39,49 @@ def _c64(u):
     return u.astype(np.complex64).astype(np.complex128)
 
 
-def test_batched_split_one_step_gate_every_instance():
+def _gate_every_instance(probs, method):
+    """One split step of every instance vs the FP64 oracle step on that
+    instance's exported exponentials; returns the worst (rel-L2, rel-Linf)."""
     torch = require_gpu()
-    probs = _sweep(12, 7)
+    from oracle import steppers
     bp = _batched(probs, "split")
     u0 = [_c64(ci.initial_state(p)) for p in probs]
     u = bp.to_device_batched(u0)
-    bp.step_lawson4(u, 1)
+    (bp.step_lawson4 if method == "lawson4" else bp.step_strang)(u, 1)
     torch.cuda.synchronize()
     assert bp.status() == 0
     outs = bp.to_host_batched(u)
-    worst = 0.0
+    worst = (0.0, 0.0)
     for j, p in enumerate(probs):
         H = [bp.get_instance_operator(j, mu, 1) for mu in range(2)]
-        ref = oracle_run(p, u0[j], "lawson4", 1, None, H)
-        err = rel_l2(outs[j], ref)
-        worst = max(worst, err)
-        assert err < 1e-6, (j, p.n, err)
-    log(f"batched split 12 instances: worst one-step rel-L2 {worst:.2e}")
+        E = [bp.get_instance_operator(j, mu, 0) for mu in range(2)]
+        ref = oracle_run(p, u0[j], method, 1, E if method == "strang" else None, H)
+        l2, linf = errors(outs[j], ref)
+        worst = (max(worst[0], l2), max(worst[1], linf))
+        assert l2 < 1e-6 and linf < 1e-6, (j, p.n, l2, linf)
     bp.destroy()
+    return worst
 
 
-@pytest.mark.parametrize("tile", ["0", "1", "2", "3"])
-def test_batched_equals_plain_plans_bitwise(tile, monkeypatch):
-    monkeypatch.setenv("CGL_SPLIT_TILE", tile)
+@pytest.mark.parametrize("method", ["lawson4", "strang"])
+def test_batched_split_one_step_gate_every_instance_of_the_sweep(method):
+    """All 512 instances of the benchmarked sweep (seed 3)."""
+    probs = ci.batched_sweep()
+    assert len(probs) == ci.C3_BATCH
+    worst = _gate_every_instance(probs, method)
+    log(f"batched split {method}, {len(probs)} instances: worst one-step rel-L2 {worst[0]:.2e}, "
+        f"rel-Linf {worst[1]:.2e}")
+
+
+def _batched_vs_plain(probs, method, steps):
+    """Run the batched plan and one plain plan per instance (same
+    exponentials) and require identical bits."""
     torch = require_gpu()
     from paper_2403_02816_amd import cgl
-    probs = _sweep(6, 8)
     bp = _batched(probs, "split")
     u0 = [ci.initial_state(p) for p in probs]
     u = bp.to_device_batched(u0)
-    assert bp.run("lawson4", u, 3, 3) == 0
+    assert bp.run(method, u, steps, steps) == 0
     torch.cuda.synchronize()
     outs = bp.to_host_batched(u)
     for j, p in enumerate(probs):
@@ -71,26 +89,62 @@ def test_batched_equals_plain_plans_bitwise(tile, monkeypatch):
         for mu in range(2):
             sp.set_exponentials(mu, bp.get_instance_operator(j, mu, 0), bp.get_instance_operator(j, mu, 1))
         v = sp.to_device(u0[j])
-        assert sp.run("lawson4", v, 3, 3) == 0
+        assert sp.run(method, v, steps, steps) == 0
         torch.cuda.synchronize()
-        assert np.array_equal(sp.to_host(v), outs[j]), (j, p.n)
+        assert np.array_equal(sp.to_host(v), outs[j]), (j, p.n, method)
         sp.destroy()
     bp.destroy()
 
 
-def test_batched_fp64_trajectory_matches_oracle():
+@pytest.mark.parametrize("tile", ["0", "1", "2", "3"])
+def test_batched_equals_plain_plans_bitwise_single_action(tile, monkeypatch):
+    """Every single-action tile shape (Lawson4 as two actions per round, and
+    Strang) in the persistent pass equals the plain pass bit for bit."""
+    monkeypatch.setenv("CGL_SPLIT_TILE", tile)
+    monkeypatch.setenv("CGL_LAWSON_PAIRED", "0")
+    probs = _sweep(6, 8)
+    _batched_vs_plain(probs, "lawson4", 3)
+    _batched_vs_plain(probs, "strang", 3)
+
+
+def test_batched_equals_plain_plans_bitwise_paired():
+    _batched_vs_plain(_sweep(6, 8), "lawson4", 3)
+
+
+def test_batched_paired_equals_two_action_lawson4_bitwise(monkeypatch):
+    """The batched paired pass and the batched two-action schedule compute the
+    same products and stage combinations: identical bits."""
+    torch = require_gpu()
+    probs = _sweep(10, 11)
+    u0 = [ci.initial_state(p) for p in probs]
+    out = {}
+    for paired in ("0", "1"):
+        monkeypatch.setenv("CGL_LAWSON_PAIRED", paired)
+        bp = _batched(probs, "split")
+        u = bp.to_device_batched(u0)
+        assert bp.run("lawson4", u, 3, 3) == 0
+        bp.step_lawson4(u, 1)
+        torch.cuda.synchronize()
+        out[paired] = u.cpu()
+        bp.destroy()
+    assert torch.equal(out["0"], out["1"])
+
+
+@pytest.mark.parametrize("method", ["lawson4", "strang"])
+def test_batched_fp64_trajectory_matches_oracle(method):
     torch = require_gpu()
     probs = _sweep(5, 9, sizes=(64, 96))
     bp = _batched(probs, "fp64")
     u0 = [ci.initial_state(p) for p in probs]
     u = bp.to_device_batched(u0)
-    bp.step_lawson4(u, 10)
+    (bp.step_lawson4 if method == "lawson4" else bp.step_strang)(u, 10)
     torch.cuda.synchronize()
     outs = bp.to_host_batched(u)
     for j, p in enumerate(probs):
         H = [bp.get_instance_operator(j, mu, 1) for mu in range(2)]
-        ref = oracle_run(p, u0[j], "lawson4", 10, None, H)
-        assert rel_l2(outs[j], ref) < 1e-12, j
+        E = [bp.get_instance_operator(j, mu, 0) for mu in range(2)]
+        ref = oracle_run(p, u0[j], method, 10, E if method == "strang" else None, H)
+        assert_close(outs[j], ref, 1e-12, f"batched fp64 {method} instance {j} {p.n}")
     bp.destroy()
 
 

@@ -11,7 +11,7 @@ import pytest
 
 import cgl_inputs as ci
 from oracle import tensor
-from tests._util import log, make_plan, oracle_run, plan_ops, rel_l2, require_gpu
+from tests._util import assert_close, log, make_plan, oracle_run, plan_ops, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -44,8 +44,7 @@ def test_mode_product_every_mu(shape):
             p.mode_product(mu, which, x, out)
             torch.cuda.synchronize()
             ref = tensor.mode_product(U, Ms[mu], mu)
-            err = rel_l2(p.to_host(out), ref)
-            assert err < 1e-13, (shape, mu, which, err)
+            assert_close(p.to_host(out), ref, 1e-13, f"fp64 mode {shape} mu={mu} which={which}")
     p.destroy()
 
 
@@ -58,10 +57,10 @@ def test_tucker_and_inplace(shape):
     out = torch.empty_like(x)
     p.tucker(0, x, out)
     torch.cuda.synchronize()
-    assert rel_l2(p.to_host(out), tensor.tucker(U, Es)) < 1e-13
+    assert_close(p.to_host(out), tensor.tucker(U, Es), 1e-13, f"fp64 tucker {shape}")
     p.tucker(1, x, x)  # in place
     torch.cuda.synchronize()
-    assert rel_l2(p.to_host(x), tensor.tucker(U, Hs)) < 1e-13
+    assert_close(p.to_host(x), tensor.tucker(U, Hs), 1e-13, f"fp64 tucker in place {shape}")
     p.destroy()
 
 
@@ -82,36 +81,35 @@ def _traj_case(p, method, m, rk4_flow=False, use_run=False, check_every=0):
     assert plan.status() == 0
     E, H = plan_ops(plan)
     ref = oracle_run(p, u0, method, m, E, H, rk4_flow=rk4_flow)
-    err = rel_l2(plan.to_host(u), ref)
-    log(f"  rel-L2 vs oracle {err:.3e}")
+    got = plan.to_host(u)
     plan.destroy()
-    return err
+    assert_close(got, ref, 1e-12, f"fp64 {p.name} {method} m={m}")
 
 
 def test_c0_strang_full_trajectory():
-    assert _traj_case(ci.C0, "strang", ci.C0.steps) < 1e-12
+    _traj_case(ci.C0, "strang", ci.C0.steps)
 
 
 def test_c0_lawson4_trajectory():
-    assert _traj_case(ci.C0, "lawson4", 50) < 1e-12
+    _traj_case(ci.C0, "lawson4", 50)
 
 
 @pytest.mark.parametrize("shape", [(24, 24, 24), (19, 26, 21)])
 def test_c1_shape_lawson4_trajectory(shape):
     p = ci.scaled(ci.C1, shape)
-    assert _traj_case(p, "lawson4", 40, use_run=True, check_every=10) < 1e-12
+    _traj_case(p, "lawson4", 40, use_run=True, check_every=10)
 
 
 def test_c2_shape_strang_rk4_trajectory():
     p = ci.scaled(ci.C2, (20, 22, 18))
-    assert _traj_case(p, "strang", 30, use_run=True, check_every=7) < 1e-12
+    _traj_case(p, "strang", 30, use_run=True, check_every=7)
 
 
 def test_d1_and_rk4_flow_for_cubic():
     p = ci.Problem("d1", (97,), ci.DIRICHLET, -10.0, 10.0, ci.C0.coeffs, 1e-2, 20, "strang", 9)
-    assert _traj_case(p, "strang", 20) < 1e-12
-    assert _traj_case(p, "strang", 20, rk4_flow=True) < 1e-12
-    assert _traj_case(p, "lawson4", 20) < 1e-12
+    _traj_case(p, "strang", 20)
+    _traj_case(p, "strang", 20, rk4_flow=True)
+    _traj_case(p, "lawson4", 20)
 
 
 def test_graph_replay_equals_eager_bitwise():
@@ -138,9 +136,7 @@ def test_c1_full_size_one_step():
     torch.cuda.synchronize()
     E, H = plan_ops(plan)
     ref = oracle_run(p, u0, "lawson4", 2, E, H)
-    err = rel_l2(plan.to_host(u), ref)
-    log(f"C1 128^3 FP64 Lawson4 2 steps rel-L2 {err:.3e}")
-    assert err < 1e-12
+    assert_close(plan.to_host(u), ref, 1e-12, "C1 128^3 FP64 Lawson4 2 steps")
     plan.destroy()
 
 

@@ -14,7 +14,7 @@ import pytest
 
 import cgl_inputs as ci
 from oracle import tensor
-from tests._util import log, make_plan, oracle_run, plan_ops, rel_l2, require_gpu
+from tests._util import assert_close, errors, log, make_plan, oracle_run, plan_ops, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -50,8 +50,8 @@ def test_split_mode_product_every_mu(shape):
             log(f"split mode_product shape={shape} mu={mu} which={which}")
             p.mode_product(mu, which, x, out)
             torch.cuda.synchronize()
-            err = rel_l2(p.to_host(out), tensor.mode_product(U, Ms[mu], mu))
-            assert err < 1e-6, (shape, mu, which, err)
+            assert_close(p.to_host(out), tensor.mode_product(U, Ms[mu], mu), 1e-6,
+                         f"split mode {shape} mu={mu} which={which}")
     p.destroy()
 
 
@@ -64,9 +64,7 @@ def test_split_tucker(shape):
     out = torch.empty_like(x)
     p.tucker(1, x, out)
     torch.cuda.synchronize()
-    err = rel_l2(p.to_host(out), tensor.tucker(U, Hs))
-    log(f"split tucker {shape} {err:.2e}")
-    assert err < 1e-6
+    assert_close(p.to_host(out), tensor.tucker(U, Hs), 1e-6, f"split tucker {shape}")
 
 
 def _one_step_gate(p, method, master=False, rk4_flow=False, steps=1):
@@ -84,44 +82,51 @@ def _one_step_gate(p, method, master=False, rk4_flow=False, steps=1):
     assert plan.status() == 0
     E, H = plan_ops(plan)
     ref = oracle_run(p, u0, method, steps, E, H, rk4_flow=rk4_flow)
-    err = rel_l2(plan.to_host(u), ref)
-    log(f"split {p.name} {method} master={master} steps={steps} rel-L2 {err:.3e}")
+    got = plan.to_host(u)
     plan.destroy()
-    return err
+    l2, linf = errors(got, ref)
+    log(f"split {p.name} {method} master={master} steps={steps} rel-L2 {l2:.3e} rel-Linf {linf:.3e}")
+    return l2, linf
+
+
+def _gate(p, method, **kw):
+    """The split form's accuracy target for one step: both measures <= 1e-6."""
+    l2, linf = _one_step_gate(p, method, **kw)
+    assert l2 < 1e-6 and linf < 1e-6, (p.name, method, kw, l2, linf)
 
 
 @pytest.mark.parametrize("method", ["strang", "lawson4"])
 def test_split_one_step_gate_c0(method):
-    assert _one_step_gate(ci.C0, method) < 1e-6
+    _gate(ci.C0, method)
 
 
 @pytest.mark.parametrize("method", ["strang", "lawson4"])
 @pytest.mark.parametrize("master", [False, True])
 def test_split_one_step_gate_c1_shape(method, master):
-    assert _one_step_gate(ci.scaled(ci.C1, (40, 36, 44)), method, master=master) < 1e-6
+    _gate(ci.scaled(ci.C1, (40, 36, 44)), method, master=master)
 
 
 @pytest.mark.parametrize("method", ["strang", "lawson4"])
 def test_split_one_step_gate_c2_shape(method):
-    assert _one_step_gate(ci.scaled(ci.C2, (48, 40, 52)), method) < 1e-6
+    _gate(ci.scaled(ci.C2, (48, 40, 52)), method)
 
 
 def test_split_one_step_gate_c1_full_size():
-    assert _one_step_gate(ci.C1, "lawson4") < 1e-6
+    _gate(ci.C1, "lawson4")
 
 
 @pytest.mark.parametrize("method", ["strang", "lawson4"])
 def test_split_one_step_gate_c2_full_size(method):
     """256^3 Dirichlet cubic-quintic, the full grid (the oracle takes ~10 s)."""
-    assert _one_step_gate(ci.C2, method) < 1e-6
+    _gate(ci.C2, method)
 
 
 def test_split_trajectory_error_is_reported():
     p = ci.scaled(ci.C1, (32, 32, 32))
     err = _one_step_gate(p, "lawson4", steps=40)
     errm = _one_step_gate(p, "lawson4", master=True, steps=40)
-    log(f"split 32^3 Lawson4 40 steps: c64 state {err:.3e}, FP64 master {errm:.3e}")
-    assert err < 1e-3 and errm < 1e-3
+    log(f"split 32^3 Lawson4 40 steps: c64 state {err}, FP64 master {errm}")
+    assert max(err + errm) < 1e-3
 
 
 def test_split_graph_replay_equals_eager_bitwise():
@@ -154,13 +159,17 @@ def test_split_every_tile_shape(tile, monkeypatch):
     for mu in range(3):
         p.mode_product(mu, 1, x, out)
         torch.cuda.synchronize()
-        assert rel_l2(p.to_host(out), tensor.mode_product(U, Hs[mu], mu)) < 1e-6
+        assert_close(p.to_host(out), tensor.mode_product(U, Hs[mu], mu), 1e-6,
+                     f"tile {tile} mode {mu}")
     p.tucker(0, x, out)
     torch.cuda.synchronize()
-    assert rel_l2(p.to_host(out), tensor.tucker(U, Es)) < 1e-6
+    assert_close(p.to_host(out), tensor.tucker(U, Es), 1e-6, f"tile {tile} tucker")
     p.destroy()
+    # Lawson4 of the two-action form (the paired form ignores the tile
+    # choice) and Strang run on the forced shape
+    monkeypatch.setenv("CGL_LAWSON_PAIRED", "0")
     for method in ("strang", "lawson4"):
-        assert _one_step_gate(ci.scaled(ci.C2, (64, 32, 48)), method) < 1e-6
+        _gate(ci.scaled(ci.C2, (64, 32, 48)), method)
 
 
 @pytest.mark.parametrize("shape,method", [((96, 80, 40), "lawson4"), ((130, 70, 9), "strang"),
@@ -168,9 +177,12 @@ def test_split_every_tile_shape(tile, monkeypatch):
 def test_dma_tiles_match_register_tiles_bitwise(shape, method, monkeypatch):
     """The direct-to-LDS shapes compute the same products in the same order as
     the register-staged shapes with the same rows per workgroup: 64 x 16
-    against 64 x 32 and 128 x 16 against 128 x 16, bit for bit."""
+    against 64 x 32 and 128 x 16 against 128 x 16, bit for bit.  Lawson4 runs
+    as two single-action passes per direction here (the paired pass has its
+    own tile choice)."""
     torch = require_gpu()
     from paper_2403_02816_amd import cgl
+    monkeypatch.setenv("CGL_LAWSON_PAIRED", "0")
     p = ci.scaled(ci.C1, shape) if len(shape) == 3 else ci.scaled(ci.C0, shape)
     u0 = ci.initial_state(p)
     out = {}
