@@ -31,6 +31,7 @@ import numpy as np
 
 DIRICHLET = 0
 NEUMANN = 1
+PERIODIC = 2
 
 
 @dataclasses.dataclass(frozen=True)
@@ -70,8 +71,9 @@ class Problem:
     bc_hi: int | None = None
     #: finite-difference order of the operators (2 or 4)
     order: int = 2
-    #: initial datum: "" (the recipe of the grid's dimension) or "noise"
+    #: initial datum: "" (the recipe of the grid's dimension), "noise"
     #: (standard normal / 5000, real, as in the experiments of Sections 4.1-4.2)
+    #: or "necklace" (the necklace ring of Section 4.3, no random draw)
     init: str = ""
 
     @property
@@ -112,6 +114,18 @@ T1 = Problem("t1_cubic2d_256_dirichlet_fd4", (256, 256), DIRICHLET, 0.0, 100.0,
 T3 = Problem("t3_cubic3d_128_dn_fd4", (128, 128, 128), DIRICHLET, 0.0, 100.0,
              PAPER_CUBIC, 10.0 / 50, 50, "split4", 11, bc_hi=NEUMANN, order=4, init="noise")
 
+#: the paper's Table 2 setting: the Table 1 equation with periodic
+#: boundaries, 256^2 Fourier grid on (0,100)^2, T = 6.
+T2 = Problem("t2_cubic2d_256_periodic", (256, 256), PERIODIC, 0.0, 100.0,
+             PAPER_CUBIC, 6.0 / 200, 200, "split4", 12, init="noise")
+
+#: the paper's Table 4 setting: 3-D cubic-quintic CGL on (-12,12)^3 with
+#: periodic boundaries, 128^3 Fourier grid, a1 = b1 = 1/2, a2 = -1/2,
+#: a3 = 2.52, b3 = 1, a4 = -1, b4 = -0.11, necklace-ring datum, T = 5.
+PAPER_CQ = Coeffs(0.5, 0.5, -0.5, 2.52, 1.0, -1.0, -0.11)
+T4 = Problem("t4_cq3d_128_periodic", (128, 128, 128), PERIODIC, -12.0, 12.0,
+             PAPER_CQ, 5.0 / 300, 300, "lawson4", 13, init="necklace")
+
 #: batched sweep: 512 2-D cubic instances (see ``batched_sweep``).
 C3_BATCH = 512
 C3_SIZES = (64, 96, 128, 160, 192)
@@ -138,6 +152,8 @@ def nodes(n: int, a: float, b: float, bc: int, bc_hi: int | None = None) -> np.n
             h = (b - a) / n
             return a + h * np.arange(0, n, dtype=np.float64)
         raise ValueError("bc must be DIRICHLET or NEUMANN")
+    if bc == PERIODIC:
+        return a + (b - a) * np.arange(0, n, dtype=np.float64) / n
     if bc == DIRICHLET:
         h = (b - a) / (n + 1)
         return a + h * np.arange(1, n + 1, dtype=np.float64)
@@ -192,11 +208,27 @@ def vortex_ring_3d(n: Sequence[int], a: float, b: float, bc: int, seed: int,
     return ((1.0 + noise * xi) * env * np.exp(1j * charge * np.arctan2(y, x))).astype(np.complex128)
 
 
+def necklace_ring(n: Sequence[int], a: float, b: float, bc: int, delta: float = 1.2,
+                  rho0: float = 6.0, omega: float = 2.5, eta: int = 5,
+                  kappa: int = 3) -> np.ndarray:
+    """The necklace ring of Section 4.3: delta sech(sqrt((rho - rho0)^2 + z^2) / omega)
+    cos(eta theta) exp(i kappa theta), rho = sqrt(x^2 + y^2), theta = atan2(y, x)."""
+    x, y, z = np.meshgrid(nodes(n[0], a, b, bc), nodes(n[1], a, b, bc), nodes(n[2], a, b, bc),
+                          indexing="ij")
+    rho = np.sqrt(x * x + y * y)
+    theta = np.arctan2(y, x)
+    r = np.sqrt((rho - rho0) ** 2 + z * z)
+    return (delta / np.cosh(r / omega) * np.cos(eta * theta) * np.exp(1j * kappa * theta)).astype(
+        np.complex128)
+
+
 def initial_state(p: Problem) -> np.ndarray:
     """Seeded u0 of shape p.n (complex128)."""
     if p.init == "noise":
         rng = np.random.default_rng(p.seed)
         return (rng.standard_normal(p.n) / 5000.0).astype(np.complex128)
+    if p.init == "necklace":
+        return necklace_ring(p.n, p.a, p.b, p.bc)
     if p.d == 2:
         return gaussian_phase_2d(p.n, p.a, p.b, p.bc, p.seed)
     if p.d == 3:

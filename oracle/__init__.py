@@ -18,8 +18,12 @@ Contents (each function cites the passage it follows):
 * ``nonlinear``  -- g(u) of eq. (cqCGL), the exact cubic and quintic flows
   (eq. exsolcub and its quintic analogue in Section 4.3), one classical RK4
   step of u' = g(u) (eq. RK4 with K = 0) as the cubic-quintic sub-flow.
-* ``steppers``   -- Strang (eq. Strang) and Lawson4 (eq. lawson4) exactly as
-  written (six exponential actions per Lawson4 step), plus a time loop.
+* ``steppers``   -- Strang (eq. Strang), split4 (eq. Richardson), Lawson2b
+  (eq. lawson2b), Lawson4 (eq. lawson4, six exponential actions per step)
+  and the three-term splittings of Section 4.3 exactly as written, plus a
+  time loop.
+* ``fourier``    -- periodic boundaries by the Fourier pseudospectral route of
+  Section 3.2 (exp(t K) as a pointwise product between transforms).
 * ``metrics``    -- relative 2-norm / infinity-norm errors and the observed
   order of convergence used in the paper's tables.
 * ``surrogate``  -- FP64 residual CNN forward/backward (3x3 convolutions).

@@ -35,7 +35,13 @@ from typing import Callable, List, Sequence
 import numpy as np
 
 from . import nonlinear
-from .tensor import tucker
+from .tensor import tucker as _tucker
+
+
+def tucker(u: np.ndarray, M) -> np.ndarray:
+    """The exponential action: the Tucker operator of eq. (Tucker) for a list
+    of matrices, or a callable action (the Fourier path of Section 3.2)."""
+    return M(u) if callable(M) else _tucker(u, M)
 
 
 class CGLNonlinearity:
