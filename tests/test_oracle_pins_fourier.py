@@ -94,4 +94,4 @@ def test_table4_datum_is_the_ten_bead_necklace():
     assert peaks == 10 and abs(mod.max() - 1.2) < 1e-6
     u = ci.initial_state(ci.scaled(ci.T4, (32, 32, 32)))
     assert abs(np.abs(u).max() - 1.2) < 0.2
-    assert np.abs(u[0, 0, 0]) < 1e-3  # a corner of (-12, 12)^3 is far from the ring
+    assert np.abs(u[0, 0, 0]) < 1e-2  # a corner of (-12, 12)^3 is far from the ring
