@@ -10,9 +10,9 @@
  * of the 1-D operators A_mu (eq. ODEs).  The action of exp(t K) is computed as
  * the Tucker operator U x_1 exp(t A_1) x_2 ... x_d exp(t A_d) (eq. Tucker) of
  * dense mu-mode products; it is interleaved with the pointwise nonlinear flow
- * inside Strang (eq. Strang) and Lawson4 (eq. lawson4) steps with a constant
- * step size tau, so the small exponentials are computed once per plan
- * (Section 3.1).
+ * inside Strang (eq. Strang), split4 (eq. Richardson), Lawson2b (eq.
+ * lawson2b) and Lawson4 (eq. lawson4) steps with a constant step size tau, so
+ * the small exponentials are computed once per plan (Section 3.1).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -59,12 +59,23 @@ enum {
   CGL_EDEVICE = -3,    /* a HIP runtime call failed */
   CGL_ENOTREADY = -4,  /* a step was requested before every mu has operators */
   CGL_ENONFINITE = -5, /* the state became NaN/Inf (the paper's "x" entries) */
-  CGL_EBLOWUP = -6,    /* 1 - 2 a3 |u|^2 t <= 0 in the exact cubic flow */
+  CGL_EBLOWUP = -6,    /* 1 - 2 a3 |u|^2 t <= 0 in the exact cubic flow (or
+                          1 - 4 a4 |u|^4 t <= 0 in the exact quintic flow) */
   CGL_EGATE = -7       /* a surrogate jump failed its a-posteriori check */
 };
 
-enum { CGL_FP64 = 0, CGL_SPLIT_BF16 = 1 };         /* precision form */
-enum { CGL_STRANG = 0, CGL_LAWSON4 = 1 };          /* time stepper */
+/* precision form.  CGL_SPLIT_BF16: complex64 stage tensors, operands split
+ * into three bf16 terms (six term products kept), FP32 accumulation.  Its
+ * stated accuracy (one mu-mode product or one step within 1e-6 relative of
+ * the FP64 result, 2-norm and max-norm) holds for directions of up to 512
+ * points: the FP32 accumulation error grows like sqrt(n_mu) (one product
+ * with random operands measured 7.2e-7 / 1.25e-6 (2-norm / max-norm) at
+ * n_mu = 1024 and 1.45e-6 / 2.5e-6 at n_mu = 4096). */
+enum { CGL_FP64 = 0, CGL_SPLIT_BF16 = 1 };
+/* time stepper: Strang (eq. Strang), Lawson4 (eq. lawson4), split4 = the
+ * Richardson extrapolation of Strang (eq. richextrap / Richardson), Lawson2b
+ * (eq. lawson2b) */
+enum { CGL_STRANG = 0, CGL_LAWSON4 = 1, CGL_SPLIT4 = 2, CGL_LAWSON2 = 3 };
 enum { CGL_DIRICHLET = 0, CGL_NEUMANN = 1 };       /* boundary type */
 enum { CGL_E = 0, CGL_H = 1 };                     /* exp(tau A) or exp(tau A / 2) */
 
@@ -73,6 +84,10 @@ enum { CGL_E = 0, CGL_H = 1 };                     /* exp(tau A) or exp(tau A / 
                                    every step's final update is made in FP64 */
 #define CGL_FLAG_RK4_FLOW 2u    /* Strang: use the RK4 sub-flow even when the
                                    nonlinearity is cubic (default: exact flow) */
+#define CGL_FLAG_THREE_TERM 4u  /* Strang / split4 become strang_3t / split4_3t
+                                   (Section 4.3): the sub-flow entering a step is
+                                   phi^c o phi^q, the one leaving it phi^q o phi^c,
+                                   both exact; excludes CGL_FLAG_RK4_FLOW */
 
 /* Create a plan for a d-dimensional grid n[0..d-1] (n[mu] >= 3, d in 1..3),
  * coefficients c, constant step tau > 0 and a precision form.  hip_stream is
@@ -103,6 +118,22 @@ int cgl_set_exponentials(cgl_plan_t p, int mu, const double* E, const double* H)
  * doubles, complex128 column-major.  Errors: CGL_EINVAL. */
 int cgl_fd_operator(int64_t n, double a, double b, int bc, const cgl_coeffs* c, int d,
                     double* A_out);
+
+/* Build the finite-difference operator A = (a1 + i b1) D2 + (a2/d) I of one
+ * direction with a condition bc_lo at a and bc_hi at b (CGL_DIRICHLET or
+ * CGL_NEUMANN each) and order 2 or 4.  Grid: a Dirichlet end is not a node
+ * (its value is 0), a Neumann end is the first or last node, so n unknowns
+ * have h = (b-a)/(n+1) (both Dirichlet, the interior points of Section
+ * 4.1.1), (b-a)/n (one of each, the semi-internal points of Section 4.2) or
+ * (b-a)/(n-1) (both Neumann).  Order 2: rows (1,-2,1)/h^2, a Neumann end row
+ * (-2,2)/h^2 (centred ghost value).  Order 4 (the matrices displayed in
+ * Sections 4.1.1 and 4.2, n >= 6): centred rows (-1,16,-30,16,-1)/(12h^2);
+ * next to a Dirichlet end the one-sided row (-15,-4,14,-6,1)/(12h^2); at a
+ * Neumann end the rows (1,-6,14,-4,-15,10) and (1,-8/3,-6,56,-145/3) over
+ * 12h^2 (the left end mirrored).  A_out: host, 2*n*n doubles, complex128
+ * column-major.  Errors: CGL_EINVAL (order, n, bc, d, b <= a, null). */
+int cgl_fd_operator_ex(int64_t n, double a, double b, int bc_lo, int bc_hi, int order,
+                       const cgl_coeffs* c, int d, double* A_out);
 
 /* exp(t A) of a host complex128 column-major n x n matrix by the plan's Pade
  * routine (no plan needed).  out: host, 2*n*n doubles.  Errors: CGL_EINVAL. */
@@ -145,7 +176,20 @@ int cgl_step_strang(cgl_plan_t p, void* u_dev, int64_t nsteps);
  * actions side by side.  Same errors as cgl_step_strang. */
 int cgl_step_lawson4(cgl_plan_t p, void* u_dev, int64_t nsteps);
 
-/* Advance u_dev by nsteps steps of method (CGL_STRANG / CGL_LAWSON4),
+/* Advance u_dev in place by nsteps steps of method (CGL_STRANG,
+ * CGL_LAWSON4, CGL_SPLIT4, CGL_LAWSON2), enqueued eagerly.
+ * split4 (eq. Richardson) runs three exponential actions per step:
+ * S = phi_{tau/2}(e^{tau K} phi_{tau/2}(u)); V = phi_{tau/2}(e^{tau K/2}
+ * phi_{tau/4}(u)) (one sub-flow over tau/2 between the half steps, as the
+ * scheme is printed; the three-term form composes the exact flows);
+ * u <- 4/3 phi_{tau/4}(e^{tau K/2} V) - 1/3 S, the combination fused into the
+ * last pass.  Lawson2b (eq. lawson2b) runs the two actions P = e^{tau K} u and
+ * Q = e^{tau K} g(u) (paired in the split form) and forms
+ * u_{n+1} = P + tau/2 Q + tau/2 g(P + tau Q) in the last pass.
+ * Same errors as cgl_step_strang. */
+int cgl_step(cgl_plan_t p, int method, void* u_dev, int64_t nsteps);
+
+/* Advance u_dev by nsteps steps of method (CGL_STRANG ... CGL_LAWSON2),
  * replaying a captured HIP graph of check_every steps (check_every <= 0:
  * one chunk of nsteps).  After every chunk the device flags are read; the
  * run stops early and returns CGL_ENONFINITE or CGL_EBLOWUP when one is set.

@@ -14,11 +14,12 @@ LIB_PATH = os.path.join(_HERE, "libcgl.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTREADY, ENONFINITE, EBLOWUP, EGATE = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, SPLIT_BF16 = 0, 1
-STRANG, LAWSON4 = 0, 1
+STRANG, LAWSON4, SPLIT4, LAWSON2 = 0, 1, 2, 3
 DIRICHLET, NEUMANN = 0, 1
 E, H = 0, 1
 FLAG_FP64_MASTER = 1
 FLAG_RK4_FLOW = 2
+FLAG_THREE_TERM = 4
 SUR_LOSS_MSE, SUR_LOSS_REL = 0, 1
 
 
@@ -37,12 +38,14 @@ SIGNATURES = {
     "cgl_set_operators": (_I, [_P, _I, _DP]),
     "cgl_set_exponentials": (_I, [_P, _I, _DP, _DP]),
     "cgl_fd_operator": (_I, [_I64, _D, _D, _I, C.POINTER(Coeffs), _I, _DP]),
+    "cgl_fd_operator_ex": (_I, [_I64, _D, _D, _I, _I, _I, C.POINTER(Coeffs), _I, _DP]),
     "cgl_expm": (_I, [_I64, _DP, _D, _DP]),
     "cgl_get_operator": (_I, [_P, _I, _I, _DP]),
     "cgl_mode_product": (_I, [_P, _I, _I, _P, _P]),
     "cgl_tucker": (_I, [_P, _I, _P, _P]),
     "cgl_step_strang": (_I, [_P, _P, _I64]),
     "cgl_step_lawson4": (_I, [_P, _P, _I64]),
+    "cgl_step": (_I, [_P, _I, _P, _I64]),
     "cgl_run": (_I, [_P, _I, _P, _I64, _I64]),
     "cgl_status": (_I, [_P]),
     "cgl_clear_status": (_I, [_P]),

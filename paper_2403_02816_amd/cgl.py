@@ -16,7 +16,7 @@ from . import _lib as L
 from ._lib import CGLError, check
 
 PRECISIONS = {"fp64": L.FP64, "split": L.SPLIT_BF16}
-METHODS = {"strang": L.STRANG, "lawson4": L.LAWSON4}
+METHODS = {"strang": L.STRANG, "lawson4": L.LAWSON4, "split4": L.SPLIT4, "lawson2": L.LAWSON2}
 
 
 def _coeffs(c) -> L.Coeffs:
@@ -35,6 +35,24 @@ def fd_operator(n: int, a: float, b: float, bc: int, coeffs, d: int) -> np.ndarr
     c = _coeffs(coeffs)
     check(L.lib().cgl_fd_operator(n, a, b, bc, C.byref(c), d, _dptr(out)), "cgl_fd_operator")
     return out
+
+
+def fd_operator_ex(n: int, a: float, b: float, bc_lo: int, bc_hi: int, order: int, coeffs,
+                   d: int) -> np.ndarray:
+    """cgl_fd_operator_ex: FD A_mu of order 2 or 4 with a condition at each end."""
+    out = np.zeros((n, n), dtype=np.complex128, order="F")
+    c = _coeffs(coeffs)
+    check(L.lib().cgl_fd_operator_ex(n, a, b, bc_lo, bc_hi, order, C.byref(c), d, _dptr(out)),
+          "cgl_fd_operator_ex")
+    return out
+
+
+def problem_operators(p) -> list:
+    """The operators A_mu of a workload description (grid n, domain (a, b),
+    boundary types bc / bc_hi, FD order, coefficients)."""
+    hi = p.bc if getattr(p, "bc_hi", None) is None else p.bc_hi
+    order = getattr(p, "order", 2)
+    return [fd_operator_ex(nm, p.a, p.b, p.bc, hi, order, p.coeffs, len(p.n)) for nm in p.n]
 
 
 def expm(A: np.ndarray, t: float) -> np.ndarray:
@@ -59,14 +77,16 @@ class Plan:
     """cgl_plan + the calls that take it."""
 
     def __init__(self, n: Sequence[int], coeffs, tau: float, precision: str = "fp64",
-                 master: bool = False, rk4_flow: bool = False, stream: Optional[int] = None):
+                 master: bool = False, rk4_flow: bool = False, stream: Optional[int] = None,
+                 three_term: bool = False):
         self.n = tuple(int(v) for v in n)
         self.d = len(self.n)
         self.N = int(np.prod(self.n))
         self.tau = float(tau)
         self.precision = precision
         self.master = bool(master)
-        flags = (L.FLAG_FP64_MASTER if master else 0) | (L.FLAG_RK4_FLOW if rk4_flow else 0)
+        flags = ((L.FLAG_FP64_MASTER if master else 0) | (L.FLAG_RK4_FLOW if rk4_flow else 0)
+                 | (L.FLAG_THREE_TERM if three_term else 0))
         if stream is None:
             stream = current_stream_handle()
         self._stream = stream
@@ -110,6 +130,10 @@ class Plan:
     def set_fd_operators(self, a: float, b: float, bc: int, coeffs) -> None:
         self.set_operators_all([fd_operator(nm, a, b, bc, coeffs, self.d) for nm in self.n])
 
+    def set_problem_operators(self, p) -> None:
+        """The FD operators of a workload description (order and both ends)."""
+        self.set_operators_all(problem_operators(p))
+
     def set_operators_all(self, As) -> None:
         """cgl_set_operators_all: every operator at once (parallel exponentials)."""
         mats = [np.asfortranarray(A, dtype=np.complex128) for A in As]
@@ -142,6 +166,11 @@ class Plan:
     def step_lawson4(self, u, nsteps: int = 1) -> None:
         check(L.lib().cgl_step_lawson4(self._h, C.c_void_p(u.data_ptr()), int(nsteps)),
               "cgl_step_lawson4")
+
+    def step(self, method: str, u, nsteps: int = 1) -> None:
+        """cgl_step: nsteps eager steps of any method."""
+        check(L.lib().cgl_step(self._h, METHODS[method], C.c_void_p(u.data_ptr()), int(nsteps)),
+              "cgl_step")
 
     def run(self, method: str, u, nsteps: int, check_every: int = 0) -> int:
         """cgl_run; returns the status code (CGL_ENONFINITE etc. are not raised)."""
@@ -176,7 +205,8 @@ class BatchedPlan(Plan):
     offsets ``self.offsets``."""
 
     def __init__(self, grids, coeffs, tau: float, precision: str = "split",
-                 master: bool = False, rk4_flow: bool = False, stream: Optional[int] = None):
+                 master: bool = False, rk4_flow: bool = False, stream: Optional[int] = None,
+                 three_term: bool = False):
         grids = [tuple(int(v) for v in g) for g in grids]
         self.grids = grids
         self.batch = len(grids)
@@ -187,7 +217,8 @@ class BatchedPlan(Plan):
         self.tau = float(tau)
         self.precision = precision
         self.master = bool(master)
-        flags = (L.FLAG_FP64_MASTER if master else 0) | (L.FLAG_RK4_FLOW if rk4_flow else 0)
+        flags = ((L.FLAG_FP64_MASTER if master else 0) | (L.FLAG_RK4_FLOW if rk4_flow else 0)
+                 | (L.FLAG_THREE_TERM if three_term else 0))
         if stream is None:
             stream = current_stream_handle()
         self._stream = stream

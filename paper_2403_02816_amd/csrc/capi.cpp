@@ -67,6 +67,12 @@ struct cgl_plan_s {
   // split form: Lawson4 rounds as paired passes on one stream instead of
   // two concurrent actions
   bool paired = false;
+  // tile shape of the paired pass per direction (2: 64 rows, 3: 128 rows;
+  // autotuned; -1 not yet chosen)
+  int pair_tile[3] = {-1, -1, -1};
+  // the auxiliary input of the passes being enqueued is complex128 (the
+  // split4 combination of a master-state plan)
+  bool aux_f64 = false;
   // [0], [1]: ping-pong intermediates; [2..4]: Lawson4 stage tensors; [5], [6]:
   // ping-pong intermediates of the second branch
   void* stage[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -185,6 +191,7 @@ int pass(cgl_plan_s* p, int mu, int which, const void* in0, const void* aux, voi
   const int n = static_cast<int>(p->n[mu]);
   if (rotated && p->precision != CGL_SPLIT_BF16) return CGL_EINVAL;
   hipError_t e;
+
   if (p->precision == CGL_FP64) {
     PassF64 a{};
     a.in0 = static_cast<const double*>(in0);
@@ -223,6 +230,7 @@ int pass(cgl_plan_s* p, int mu, int which, const void* in0, const void* aux, voi
     a.epi = epi;
     a.in_f64 = in_f64 ? 1 : 0;
     a.out_f64 = out_f64 ? 1 : 0;
+    a.aux_f64 = p->aux_f64 ? 1 : 0;
     a.nl = p->nl;
     a.flag = p->dflag;
     e = launch_pass_split(a, s);
@@ -252,7 +260,9 @@ int pass_batched(cgl_plan_s* p, int mu, int which, const void* in0, const void* 
     b.epi = epi;
     b.in_f64 = in_f64 ? 1 : 0;
     b.out_f64 = out_f64 ? 1 : 0;
+    b.aux_f64 = p->aux_f64 ? 1 : 0;
     b.tile = t;
+    b.tf = p->nl.tf;
     b.flag = p->dflag;
     return launch_pass_split_batched(b, p->nwg, s) == hipSuccess ? CGL_OK : CGL_EDEVICE;
   }
@@ -278,6 +288,7 @@ int pass_batched(cgl_plan_s* p, int mu, int which, const void* in0, const void* 
     a.pro = pro;
     a.epi = epi;
     a.nl = p->bnl[j];
+    a.nl.tf = p->nl.tf;
     a.flag = p->dflag;
     if (launch_pass_f64(a, s) != hipSuccess) return CGL_EDEVICE;
   }
@@ -405,13 +416,51 @@ int action(cgl_plan_s* p, int which, const void* in0, const void* aux, void* out
   return action_range(p, which, c, aux, out0, out1, pro, epi, out_f64, s, 0, 0, p->d);
 }
 
+int pass_pair(cgl_plan_s* p, int mu, int which, const void* in0, const void* in1, void* out0,
+              void* out1, bool sameg, int epi, bool in_f64, bool out_f64, hipStream_t s);
+
+// Picks the paired pass's tile shape (64 or 128 rows) of every direction by
+// timing it on the plan's stream (stage buffers as scratch).  For a batched
+// plan the choice covers every instance of a direction.
+int tune_pair(cgl_plan_s* p) {
+  const char* forced = std::getenv("CGL_PAIR_TILE");
+  for (int mu = 0; mu < p->d; ++mu) {
+    if (p->pair_tile[mu] >= 0) continue;
+    if (forced) {
+      const int t = std::atoi(forced);
+      if (t != 2 && t != 3) return CGL_EINVAL;
+      p->pair_tile[mu] = t;
+      continue;
+    }
+    std::string key;
+    if (p->batch > 0) {
+      uint64_t h = 1469598103934665603ull;  // FNV-1a over the instance sizes
+      for (int64_t v : p->bn) h = (h ^ static_cast<uint64_t>(v)) * 1099511628211ull;
+      key = device_tag() + ":pairbatch:b" + std::to_string(p->batch) + ":mu" + std::to_string(mu) +
+            ":h" + std::to_string(h);
+    } else {
+      const int64_t n = p->n[mu];
+      key = device_tag() + ":pair:n" + std::to_string(n) + ":F" + std::to_string(p->N / n);
+    }
+    auto launch = [&](int c) -> hipError_t {
+      p->pair_tile[mu] = 2 + c;
+      const int st = pass_pair(p, mu, CGL_H, p->stage[0], p->stage[5], p->stage[1], p->stage[6],
+                               false, EPI_NONE, false, false, p->ustream);
+      p->pair_tile[mu] = -1;
+      return st == CGL_OK ? hipSuccess : hipErrorInvalidValue;
+    };
+    p->pair_tile[mu] = 2 + autotune_pick(key, 2, launch, p->ustream, 8);
+  }
+  return CGL_OK;
+}
+
 // Picks the split tile shape of every direction by timing passes of each
 // candidate on the plan's stream (stage buffers as scratch).  The first pass
 // of an action (direction 0) carries the prologue of the stepper (the Strang
 // sub-flow, or g for Lawson4), evaluated once per p-tile workgroup, so it is
 // tuned separately for each prologue kind.  Runs outside any graph capture; a
 // no-op for FP64 plans and choices already made.
-int ensure_tuned(cgl_plan_s* p) {
+int ensure_tuned_single(cgl_plan_s* p) {
   if (p->precision != CGL_SPLIT_BF16) return CGL_OK;
   const int bt = build_tables(p);
   if (bt != CGL_OK) return bt;
@@ -437,7 +486,7 @@ int ensure_tuned(cgl_plan_s* p) {
       } else {
         const int64_t n = p->n[mu];
         key = device_tag() + ":split:n" + std::to_string(n) + ":F" + std::to_string(p->N / n) +
-              ":pro" + std::to_string(pro) + (p->nl.exact ? ":x" : "");
+              ":pro" + std::to_string(pro) + ":f" + std::to_string(p->nl.flow);
       }
       int saved[3];
       for (int q = 0; q < 3; ++q) saved[q] = p->tile[mu][q];
@@ -468,46 +517,72 @@ int ensure_tuned(cgl_plan_s* p) {
   return CGL_OK;
 }
 
+// Strang (eq. Strang): u <- phi_{tau/2}(e^{tau K} phi_{tau/2}(u)), both sub-flows
+// fused into the action (first-pass prologue, last-pass epilogue).
 int enqueue_strang(cgl_plan_s* p, void* u, hipStream_t s) {
   const bool m = master(p);
+  p->nl.tf = 0.5 * p->tau;
   return action(p, CGL_E, u, nullptr, u, nullptr, PRO_FLOW, EPI_FLOW, m, m, s);
+}
+
+// split4 (eq. Richardson): three actions,
+//   S = phi_{tau/2}(e^{tau K} phi_{tau/2}(u))                      [the full Strang step]
+//   V = mid_{tau/4}(e^{tau K/2} phi_{tau/4}(u))                    [first half step + the
+//                                                                   sub-flow between halves]
+//   u <- 4/3 phi_{tau/4}(e^{tau K/2} V) - 1/3 S                    [combination in the epilogue]
+// S and V live in stage[2] and stage[3] (S in complex128 for a master-state
+// plan, so the combination keeps FP64 inputs).
+int enqueue_split4(cgl_plan_s* p, void* u, hipStream_t s) {
+  const bool m = master(p);
+  void* S = p->stage[2];
+  void* V = p->stage[3];
+  p->nl.tf = 0.5 * p->tau;
+  int st = action(p, CGL_E, u, nullptr, S, nullptr, PRO_FLOW, EPI_FLOW, m, m, s);
+  p->nl.tf = 0.25 * p->tau;
+  if (st == CGL_OK) st = action(p, CGL_H, u, nullptr, V, nullptr, PRO_FLOW, EPI_MID, m, false, s);
+  p->aux_f64 = m;
+  if (st == CGL_OK) st = action(p, CGL_H, V, S, u, nullptr, PRO_NONE, EPI_RICH, false, m, s);
+  p->aux_f64 = false;
+  p->nl.tf = 0.5 * p->tau;
+  return st;
 }
 
 // One round of two exponential actions of e^{tau K/2}: a = H in_a -> out_a,
 // and b = H pro(in_b), whose epilogue reads out_a.  The first d - 1 passes of
 // b do not depend on a: they run on the plan's second stream (own ping-pong
 // buffers) while a runs on s; the last pass of b follows both on s.
-int lawson_round(cgl_plan_s* p, const void* in_a, void* out_a, bool a_in64, const void* in_b,
-                 bool b_in64, int pro_b, int epi_b, void* out_b0, void* out_b1, bool b_out64,
-                 hipStream_t s) {
+int lawson_round(cgl_plan_s* p, int which, const void* in_a, void* out_a, bool a_in64,
+                 const void* in_b, bool b_in64, int pro_b, int epi_b, void* out_b0, void* out_b1,
+                 bool b_out64, hipStream_t s) {
   if (p->d == 1) {
-    int st = action(p, CGL_H, in_a, nullptr, out_a, nullptr, PRO_NONE, EPI_NONE, a_in64, false, s);
+    int st = action(p, which, in_a, nullptr, out_a, nullptr, PRO_NONE, EPI_NONE, a_in64, false, s);
     if (st == CGL_OK)
-      st = action(p, CGL_H, in_b, out_a, out_b0, out_b1, pro_b, epi_b, b_in64, b_out64, s);
+      st = action(p, which, in_b, out_a, out_b0, out_b1, pro_b, epi_b, b_in64, b_out64, s);
     return st;
   }
   if (hipEventRecord(p->ev_fork, s) != hipSuccess ||
       hipStreamWaitEvent(p->bstream, p->ev_fork, 0) != hipSuccess)
     return CGL_EDEVICE;
   ActionCursor cb{in_b, b_in64};
-  int st = action_range(p, CGL_H, cb, nullptr, nullptr, nullptr, pro_b, EPI_NONE, false,
+  int st = action_range(p, which, cb, nullptr, nullptr, nullptr, pro_b, EPI_NONE, false,
                         p->bstream, 1, 0, p->d - 1);
   const bool recorded = hipEventRecord(p->ev_join, p->bstream) == hipSuccess;
   if (st == CGL_OK)
-    st = action(p, CGL_H, in_a, nullptr, out_a, nullptr, PRO_NONE, EPI_NONE, a_in64, false, s);
+    st = action(p, which, in_a, nullptr, out_a, nullptr, PRO_NONE, EPI_NONE, a_in64, false, s);
   // rejoin s even when an enqueue failed, so that a capture can end
   if (!recorded || hipStreamWaitEvent(s, p->ev_join, 0) != hipSuccess) return CGL_EDEVICE;
   if (st == CGL_OK)
-    st = action_range(p, CGL_H, cb, out_a, out_b0, out_b1, PRO_NONE, epi_b, b_out64, s, 1,
+    st = action_range(p, which, cb, out_a, out_b0, out_b1, PRO_NONE, epi_b, b_out64, s, 1,
                       p->d - 1, p->d);
   return st;
 }
 
 // One direction of both actions of a round (split form): the paired kernel
-// on the 64 x 16 direct-to-LDS planes of e^{tau A_mu / 2}, for one plan or
-// every instance of a batched plan.
-int pass_pair(cgl_plan_s* p, int mu, const void* in0, const void* in1, void* out0, void* out1,
-              bool sameg, int epi, bool in_f64, bool out_f64, hipStream_t s) {
+// on the 64 x 16 direct-to-LDS planes of e^{tau A_mu / 2} (which = CGL_H) or
+// e^{tau A_mu} (CGL_E), for one plan or every instance of a batched plan.
+int pass_pair(cgl_plan_s* p, int mu, int which, const void* in0, const void* in1, void* out0,
+              void* out1, bool sameg, int epi, bool in_f64, bool out_f64, hipStream_t s) {
+  const int t = p->pair_tile[mu] >= 0 ? p->pair_tile[mu] : 2;
   if (p->batch > 0) {
     if (!p->tables) return CGL_ENOTREADY;
     PassBatch b{};
@@ -516,32 +591,33 @@ int pass_pair(cgl_plan_s* p, int mu, const void* in0, const void* in1, void* out
     b.out0 = out0;
     b.out1 = out1;
     b.inst = p->dinst[mu];
-    b.tiles = p->dtiles[mu][2];
-    b.ntiles = p->ntiles[mu][2];
-    b.which = 1;
+    b.tiles = p->dtiles[mu][t];
+    b.ntiles = p->ntiles[mu][t];
+    b.which = which == CGL_E ? 0 : 1;
+    b.tf = p->nl.tf;
     b.pro = sameg ? PRO_G : PRO_NONE;
     b.epi = epi;
     b.in_f64 = in_f64 ? 1 : 0;
     b.out_f64 = out_f64 ? 1 : 0;
-    b.tile = 2;
+    b.tile = t;
     b.flag = p->dflag;
     return launch_pass_split_batched_pair(b, p->nwg, s) == hipSuccess ? CGL_OK : CGL_EDEVICE;
   }
-  const DeviceOp& op = p->dH[mu];
+  const DeviceOp& op = which == CGL_E ? p->dE[mu] : p->dH[mu];
   const int n = static_cast<int>(p->n[mu]);
   PassSplit a{};
   a.in0 = in0;
   a.in1 = in1;
   a.out0 = out0;
   a.out1 = out1;
-  a.op = static_cast<const uint16_t*>(op.ptr[2]);
-  a.tile = 2;
+  a.op = static_cast<const uint16_t*>(op.ptr[t]);
+  a.tile = t;
   a.R = 1;
   a.R_out = p->N / n;
   a.F = p->N / n;
   a.n = n;
-  a.Pp = op.Pp[2];
-  a.Kp = op.Kp[2];
+  a.Pp = op.Pp[t];
+  a.Kp = op.Kp[t];
   a.pro = sameg ? PRO_G : PRO_NONE;
   a.epi = epi;
   a.in_f64 = in_f64 ? 1 : 0;
@@ -567,7 +643,7 @@ int enqueue_lawson4_paired(cgl_plan_s* p, void* u, hipStream_t s) {
       void* o0 = last ? (round == 0 ? p->stage[2] : u) : p->stage[mu & 1];
       void* o1 = last ? (round == 0 ? p->stage[3] : nullptr) : p->stage[5 + (mu & 1)];
       const int epi = last ? (round == 0 ? EPI_L4_R1 : EPI_L4_R2) : EPI_NONE;
-      const int st = pass_pair(p, mu, in0, in1, o0, o1, round == 0 && mu == 0, epi,
+      const int st = pass_pair(p, mu, CGL_H, in0, in1, o0, o1, round == 0 && mu == 0, epi,
                                round == 0 && mu == 0 && m, round == 1 && last && m, s);
       if (st != CGL_OK) return st;
       in0 = o0;
@@ -587,15 +663,68 @@ int enqueue_lawson4(cgl_plan_s* p, void* u, hipStream_t s) {
   void* B0 = p->stage[2];
   void* B1 = p->stage[3];
   void* B2 = p->stage[4];
-  int st = lawson_round(p, u, B0, m, u, m, PRO_G, EPI_L4_R1, B1, B2, false, s);
-  if (st == CGL_OK) st = lawson_round(p, B1, B0, false, B2, false, PRO_NONE, EPI_L4_R2, u, nullptr, m, s);
+  int st = lawson_round(p, CGL_H, u, B0, m, u, m, PRO_G, EPI_L4_R1, B1, B2, false, s);
+  if (st == CGL_OK)
+    st = lawson_round(p, CGL_H, B1, B0, false, B2, false, PRO_NONE, EPI_L4_R2, u, nullptr, m, s);
   return st;
 }
 
-int check_u(cgl_plan_s* p, void* u) {
+// Lawson2b (eq. lawson2b) with e^{tau K}(u + c g(u)) = P + c Q, P = e^{tau K} u,
+// Q = e^{tau K} g(u): one round of two actions of e^{tau K}, whose last pass
+// forms u_{n+1} = P + tau/2 Q + tau/2 g(P + tau Q).  Split plans run the
+// round as paired passes (u and g(u) staged from one read of u); a 1-D plan's
+// single pass reads u, so its result goes through stage[2].
+int enqueue_lawson2(cgl_plan_s* p, void* u, hipStream_t s) {
+  const bool m = master(p);
+  const int d = p->d;
+  if (p->paired) {
+    const void* in0 = u;
+    const void* in1 = u;
+    for (int mu = 0; mu < d; ++mu) {
+      const bool last = mu == d - 1;
+      void* o0 = last ? (d == 1 ? p->stage[2] : u) : p->stage[mu & 1];
+      void* o1 = last ? nullptr : p->stage[5 + (mu & 1)];
+      const int st = pass_pair(p, mu, CGL_E, in0, in1, o0, o1, mu == 0, last ? EPI_L2 : EPI_NONE,
+                               mu == 0 && m, last && m, s);
+      if (st != CGL_OK) return st;
+      in0 = o0;
+      in1 = o1;
+    }
+    if (d == 1 && hipMemcpyAsync(u, p->stage[2], user_bytes(p), hipMemcpyDeviceToDevice, s) !=
+                      hipSuccess)
+      return CGL_EDEVICE;
+    return CGL_OK;
+  }
+  return lawson_round(p, CGL_E, u, p->stage[2], m, u, m, PRO_G, EPI_L2, u, nullptr, m, s);
+}
+
+int enqueue_method(cgl_plan_s* p, int method, void* u, hipStream_t s) {
+  switch (method) {
+    case CGL_STRANG: return enqueue_strang(p, u, s);
+    case CGL_LAWSON4: return enqueue_lawson4(p, u, s);
+    case CGL_SPLIT4: return enqueue_split4(p, u, s);
+    case CGL_LAWSON2: return enqueue_lawson2(p, u, s);
+    default: return CGL_EINVAL;
+  }
+}
+
+// Tunes what a step of `method` (or, with method < 0, a plain exponential
+// action) will launch: the paired pass for the Lawson methods of a split
+// plan that pairs its rounds, the single-action shapes otherwise.  Runs
+// outside graph capture (it times launches).
+int ensure_tuned(cgl_plan_s* p, int method) {
+  if (p->precision != CGL_SPLIT_BF16) return CGL_OK;
+  const bool pair = p->paired && (method == CGL_LAWSON4 || method == CGL_LAWSON2);
+  if (!pair) return ensure_tuned_single(p);
+  const int bt = build_tables(p);
+  return bt != CGL_OK ? bt : tune_pair(p);
+}
+
+int check_u(cgl_plan_s* p, void* u, int method) {
   if (!p || !u) return CGL_EINVAL;
   if (!ready(p)) return CGL_ENOTREADY;
-  return ensure_tuned(p);
+  if (method < CGL_STRANG || method > CGL_LAWSON2) return CGL_EINVAL;
+  return ensure_tuned(p, method);
 }
 
 }  // namespace
@@ -610,7 +739,7 @@ const char* cgl_strerror(int status) {
     case CGL_EDEVICE: return "HIP runtime error";
     case CGL_ENOTREADY: return "operators not set for every direction";
     case CGL_ENONFINITE: return "state became non-finite";
-    case CGL_EBLOWUP: return "exact cubic flow left its domain (blow-up)";
+    case CGL_EBLOWUP: return "exact cubic or quintic flow left its domain (blow-up)";
     case CGL_EGATE: return "surrogate jump failed its a-posteriori check";
     default: return "unknown status";
   }
@@ -621,6 +750,16 @@ int cgl_fd_operator(int64_t n, double a, double b, int bc, const cgl_coeffs* c, 
   if (!c || !A_out || n < 3 || d < 1 || d > 3 || !(b > a)) return CGL_EINVAL;
   if (bc != CGL_DIRICHLET && bc != CGL_NEUMANN) return CGL_EINVAL;
   const CMat A = fd_operator_2nd(n, a, b, bc, c->a1, c->b1, c->a2, d);
+  A.to_interleaved(A_out);
+  return CGL_OK;
+}
+
+int cgl_fd_operator_ex(int64_t n, double a, double b, int bc_lo, int bc_hi, int order,
+                       const cgl_coeffs* c, int d, double* A_out) {
+  if (!c || !A_out || d < 1 || d > 3 || !(b > a) || !std::isfinite(a) || !std::isfinite(b))
+    return CGL_EINVAL;
+  CMat A;
+  if (!fd_operator(n, a, b, bc_lo, bc_hi, order, c->a1, c->b1, c->a2, d, A)) return CGL_EINVAL;
   A.to_interleaved(A_out);
   return CGL_OK;
 }
@@ -638,6 +777,14 @@ int cgl_expm(int64_t n, const double* A, double t, double* out) {
 
 namespace {
 
+// Sub-flow of the splitting schemes: the three-term exact flows when asked
+// for, the exact cubic flow (eq. exsolcub) for a cubic equation unless the
+// RK4 sub-flow is forced, one RK4 step otherwise.
+int flow_kind(const cgl_coeffs& c, unsigned flags) {
+  if (flags & CGL_FLAG_THREE_TERM) return FLOW_3T;
+  return (c.a4 == 0.0 && c.b4 == 0.0 && !(flags & CGL_FLAG_RK4_FLOW)) ? FLOW_EXACT : FLOW_RK4;
+}
+
 // Validates the common arguments and allocates a plan whose state tensors
 // have N complex points (stage buffers, flags, streams, events).
 int create_plan(cgl_plan_t* out, int d, const int64_t* n, int64_t N, const cgl_coeffs* c,
@@ -646,7 +793,8 @@ int create_plan(cgl_plan_t* out, int d, const int64_t* n, int64_t N, const cgl_c
   if (!(tau > 0.0) || !std::isfinite(tau)) return CGL_EINVAL;
   if (!(c->a1 > 0.0)) return CGL_EINVAL;
   if (precision != CGL_FP64 && precision != CGL_SPLIT_BF16) return CGL_EINVAL;
-  if (flags & ~(CGL_FLAG_FP64_MASTER | CGL_FLAG_RK4_FLOW)) return CGL_EINVAL;
+  if (flags & ~(CGL_FLAG_FP64_MASTER | CGL_FLAG_RK4_FLOW | CGL_FLAG_THREE_TERM)) return CGL_EINVAL;
+  if ((flags & CGL_FLAG_RK4_FLOW) && (flags & CGL_FLAG_THREE_TERM)) return CGL_EINVAL;
   if ((flags & CGL_FLAG_FP64_MASTER) && precision != CGL_SPLIT_BF16) return CGL_EINVAL;
   const double cv[7] = {c->a1, c->b1, c->a2, c->a3, c->b3, c->a4, c->b4};
   for (double v : cv)
@@ -663,11 +811,12 @@ int create_plan(cgl_plan_t* out, int d, const int64_t* n, int64_t N, const cgl_c
   p->flags = flags;
   p->ustream = static_cast<hipStream_t>(hip_stream);
   p->nl.tau = tau;
+  p->nl.tf = 0.5 * tau;
   p->nl.a3 = c->a3;
   p->nl.b3 = c->b3;
   p->nl.a4 = c->a4;
   p->nl.b4 = c->b4;
-  p->nl.exact = (c->a4 == 0.0 && c->b4 == 0.0 && !(flags & CGL_FLAG_RK4_FLOW)) ? 1 : 0;
+  p->nl.flow = flow_kind(*c, flags);
   int st = CGL_OK;
   if (hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&p->bstream, hipStreamNonBlocking) != hipSuccess ||
@@ -822,7 +971,7 @@ int cgl_plan_batched(cgl_plan_t* out, int batch, int d, const int64_t* n, const 
     q.b3 = c[j].b3;
     q.a4 = c[j].a4;
     q.b4 = c[j].b4;
-    q.exact = (c[j].a4 == 0.0 && c[j].b4 == 0.0 && !(flags & CGL_FLAG_RK4_FLOW)) ? 1 : 0;
+    q.flow = flow_kind(c[j], flags);
     p->bnl[j] = q;
   }
   const size_t K = static_cast<size_t>(batch) * d;
@@ -946,7 +1095,7 @@ int cgl_mode_product(cgl_plan_t p, int mu, int which, const void* in_dev, void* 
     return CGL_EINVAL;
   if (which != CGL_E && which != CGL_H) return CGL_EINVAL;
   if (!ready(p)) return CGL_ENOTREADY;
-  const int st = ensure_tuned(p);
+  const int st = ensure_tuned(p, -1);
   if (st != CGL_OK) return st;
   return pass(p, mu, which, in_dev, nullptr, out_dev, nullptr, PRO_NONE, EPI_NONE, false, false,
               false, p->ustream);
@@ -955,14 +1104,14 @@ int cgl_mode_product(cgl_plan_t p, int mu, int which, const void* in_dev, void* 
 int cgl_tucker(cgl_plan_t p, int which, const void* in_dev, void* out_dev) {
   if (!p || !in_dev || !out_dev || (which != CGL_E && which != CGL_H)) return CGL_EINVAL;
   if (!ready(p)) return CGL_ENOTREADY;
-  const int st = ensure_tuned(p);
+  const int st = ensure_tuned(p, -1);
   if (st != CGL_OK) return st;
   return action(p, which, in_dev, nullptr, out_dev, nullptr, PRO_NONE, EPI_NONE, false, false,
                 p->ustream);
 }
 
 int cgl_step_strang(cgl_plan_t p, void* u_dev, int64_t nsteps) {
-  int st = check_u(p, u_dev);
+  int st = check_u(p, u_dev, CGL_STRANG);
   if (st != CGL_OK) return st;
   if (nsteps < 0) return CGL_EINVAL;
   for (int64_t i = 0; i < nsteps && st == CGL_OK; ++i) st = enqueue_strang(p, u_dev, p->ustream);
@@ -970,10 +1119,19 @@ int cgl_step_strang(cgl_plan_t p, void* u_dev, int64_t nsteps) {
 }
 
 int cgl_step_lawson4(cgl_plan_t p, void* u_dev, int64_t nsteps) {
-  int st = check_u(p, u_dev);
+  int st = check_u(p, u_dev, CGL_LAWSON4);
   if (st != CGL_OK) return st;
   if (nsteps < 0) return CGL_EINVAL;
   for (int64_t i = 0; i < nsteps && st == CGL_OK; ++i) st = enqueue_lawson4(p, u_dev, p->ustream);
+  return st;
+}
+
+int cgl_step(cgl_plan_t p, int method, void* u_dev, int64_t nsteps) {
+  int st = check_u(p, u_dev, method);
+  if (st != CGL_OK) return st;
+  if (nsteps < 0) return CGL_EINVAL;
+  for (int64_t i = 0; i < nsteps && st == CGL_OK; ++i)
+    st = enqueue_method(p, method, u_dev, p->ustream);
   return st;
 }
 
@@ -1009,9 +1167,7 @@ static int get_graph(cgl_plan_t p, int method, void* u, int64_t k, hipGraphExec_
   if (hipStreamBeginCapture(p->gstream, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return CGL_EDEVICE;
   int st = CGL_OK;
-  for (int64_t i = 0; i < k && st == CGL_OK; ++i)
-    st = (method == CGL_STRANG) ? enqueue_strang(p, u, p->gstream)
-                                : enqueue_lawson4(p, u, p->gstream);
+  for (int64_t i = 0; i < k && st == CGL_OK; ++i) st = enqueue_method(p, method, u, p->gstream);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(p->gstream, &g);
   if (st != CGL_OK || e != hipSuccess) {
@@ -1028,9 +1184,9 @@ static int get_graph(cgl_plan_t p, int method, void* u, int64_t k, hipGraphExec_
 }
 
 int cgl_run(cgl_plan_t p, int method, void* u_dev, int64_t nsteps, int64_t check_every) {
-  int st = check_u(p, u_dev);
+  int st = check_u(p, u_dev, method);
   if (st != CGL_OK) return st;
-  if (nsteps < 0 || (method != CGL_STRANG && method != CGL_LAWSON4)) return CGL_EINVAL;
+  if (nsteps < 0) return CGL_EINVAL;
   if (nsteps == 0) return CGL_OK;
   const int64_t k = (check_every <= 0 || check_every > nsteps) ? nsteps : check_every;
   // join the caller's stream; conditions latched before this run were

@@ -233,6 +233,74 @@ CMat fd_operator_2nd(int64_t n, double a, double b, int bc, double a1, double b1
   return A;
 }
 
+bool fd_operator(int64_t n, double a, double b, int bc_lo, int bc_hi, int order, double a1,
+                 double b1, double a2, int d, CMat& A) {
+  if ((bc_lo != 0 && bc_lo != 1) || (bc_hi != 0 && bc_hi != 1)) return false;
+  if (order != 2 && order != 4) return false;
+  if (n < (order == 4 ? 6 : 3)) return false;
+  // a Dirichlet end is not a node, a Neumann end is the first / last node
+  const int ends = (bc_lo == 1) + (bc_hi == 1);
+  const double h = (b - a) / double(n + 1 - ends);
+  std::vector<double> D(static_cast<size_t>(n * n), 0.0);  // column-major
+  auto at = [&](int64_t i, int64_t j) -> double& { return D[static_cast<size_t>(i + n * j)]; };
+  double scale;
+  if (order == 2) {
+    for (int64_t i = 0; i < n; ++i) {
+      at(i, i) = -2.0;
+      if (i > 0) at(i, i - 1) = 1.0;
+      if (i < n - 1) at(i, i + 1) = 1.0;
+    }
+    // Neumann end: the ghost value of the centred u' = 0 doubles the inner neighbour
+    if (bc_lo == 1) at(0, 1) = 2.0;
+    if (bc_hi == 1) at(n - 1, n - 2) = 2.0;
+    scale = 1.0 / (h * h);
+  } else {
+    // Sections 4.1.1 and 4.2: centred five-point rows (a Dirichlet boundary
+    // value, 0, drops out); next to a Dirichlet end the one-sided six-point
+    // row whose boundary weight multiplies that zero; at a Neumann end the
+    // two modified rows of the semi-internal grid.  The left end mirrors the
+    // right one (column order reversed).
+    static const double kCentre[5] = {-1.0, 16.0, -30.0, 16.0, -1.0};
+    static const double kNextToDirichlet[5] = {-15.0, -4.0, 14.0, -6.0, 1.0};  // from the end inwards
+    static const double kBeforeNeumannEnd[6] = {10.0, -15.0, -4.0, 14.0, -6.0, 1.0};
+    static const double kNeumannEnd[5] = {-145.0 / 3.0, 56.0, -6.0, -8.0 / 3.0, 1.0};
+    for (int64_t i = 0; i < n; ++i)
+      for (int k = -2; k <= 2; ++k)
+        if (i + k >= 0 && i + k < n) at(i, i + k) = kCentre[k + 2];
+    auto clear_row = [&](int64_t i) {
+      for (int64_t j = 0; j < n; ++j) at(i, j) = 0.0;
+    };
+    // right end: column n-1-k takes entry k of a table written from the end inwards
+    if (bc_hi == 0) {
+      clear_row(n - 1);
+      for (int k = 0; k < 5; ++k) at(n - 1, n - 1 - k) = kNextToDirichlet[k];
+    } else {
+      clear_row(n - 2);
+      clear_row(n - 1);
+      for (int k = 0; k < 6; ++k) at(n - 2, n - 1 - k) = kBeforeNeumannEnd[k];
+      for (int k = 0; k < 5; ++k) at(n - 1, n - 1 - k) = kNeumannEnd[k];
+    }
+    // left end: column k
+    if (bc_lo == 0) {
+      clear_row(0);
+      for (int k = 0; k < 5; ++k) at(0, k) = kNextToDirichlet[k];
+    } else {
+      clear_row(1);
+      clear_row(0);
+      for (int k = 0; k < 6; ++k) at(1, k) = kBeforeNeumannEnd[k];
+      for (int k = 0; k < 5; ++k) at(0, k) = kNeumannEnd[k];
+    }
+    scale = 1.0 / (12.0 * h * h);
+  }
+  A = CMat(n);
+  for (size_t q = 0; q < D.size(); ++q) {
+    A.re[q] = a1 * (D[q] * scale);
+    A.im[q] = b1 * (D[q] * scale);
+  }
+  for (int64_t i = 0; i < n; ++i) A.re[i + n * i] += a2 / double(d);
+  return true;
+}
+
 uint16_t f32_to_bf16_rne(float x) {
   uint32_t u;
   std::memcpy(&u, &x, 4);

@@ -32,6 +32,12 @@ bool expm_pade13(const CMat& A, double t, CMat& out);
 CMat fd_operator_2nd(int64_t n, double a, double b, int bc, double a1, double b1, double a2,
                      int d);
 
+// FD operator of order 2 or 4 with a Dirichlet (0) or Neumann (1) condition at
+// each end (see cgl_fd_operator_ex in cgl.h).  Returns false for an order or
+// size it does not support.
+bool fd_operator(int64_t n, double a, double b, int bc_lo, int bc_hi, int order, double a1,
+                 double b1, double a2, int d, CMat& A);
+
 // Round-to-nearest-even float -> bf16 bits and back.
 uint16_t f32_to_bf16_rne(float x);
 float bf16_to_f32(uint16_t h);

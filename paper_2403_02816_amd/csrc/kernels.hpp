@@ -23,20 +23,30 @@
 
 namespace cgl {
 
-// prologue codes (first pass of an exponential action)
+// prologue codes (first pass of an exponential action); t = NlParams::tf
 enum Prologue : int {
   PRO_NONE = 0,
-  PRO_FLOW = 1,  // x <- phi_{tau/2}(x)                          (Strang)
-  PRO_G = 2,     // x <- g(x)                                    (Lawson4: Q = e^{tau K/2} g(u))
+  PRO_FLOW = 1,  // x <- phi_t(x) (the sub-flow entering a splitting step)
+  PRO_G = 2,     // x <- g(x)                                    (Lawson: Q = e^{s K} g(u))
 };
 
 // epilogue codes (last pass of an exponential action); "aux" is a second
-// tensor read at the same grid point
+// tensor read at the same grid point; t = NlParams::tf
 enum Epilogue : int {
   EPI_NONE = 0,
-  EPI_FLOW = 1,   // y <- phi_{tau/2}(y), check finite            (Strang)
+  EPI_FLOW = 1,   // y <- phi_t(y) (the sub-flow leaving a splitting step), check finite
   EPI_L4_R1 = 2,  // acc = Q, aux = P:  out0 <- X, out1 <- Y        (Lawson4 round 1)
   EPI_L4_R2 = 3,  // acc = H Y, aux = H X:  out0 <- H Y + tau/6 g(H X), check finite
+  EPI_MID = 4,    // y <- the sub-flow between the two half steps of split4, check finite
+  EPI_RICH = 5,   // out0 <- 4/3 phi_t(y) - 1/3 aux (split4), check finite
+  EPI_L2 = 6,     // acc = Q = E g(u), aux = P = E u:  out0 <- P + tau/2 Q + tau/2 g(P + tau Q)
+};
+
+// sub-flow of the splitting schemes
+enum FlowKind : int {
+  FLOW_RK4 = 0,    // one classical RK4 step of u' = g(u)
+  FLOW_EXACT = 1,  // the exact cubic flow (eq. exsolcub), a4 = b4 = 0
+  FLOW_3T = 2,     // exact cubic and exact quintic flows in sequence (three-term splitting)
 };
 
 // latched device conditions
@@ -44,8 +54,9 @@ enum : unsigned { FLAG_NONFINITE = 1u, FLAG_BLOWUP = 2u };
 
 struct NlParams {
   double tau;  // full step
+  double tf;   // time of the sub-flows of this pass (PRO_FLOW, EPI_FLOW, EPI_MID, EPI_RICH)
   double a3, b3, a4, b4;
-  int exact;  // 1: exact cubic sub-flow, 0: one RK4 step of u' = g(u)
+  int flow;    // FlowKind
 };
 
 // FP64 pass: complex128 tensors, FP64 operator embedding.
@@ -93,6 +104,7 @@ struct PassSplit {
   int epi;
   int in_f64;   // in0 is complex128 (master state) instead of complex64
   int out_f64;  // out0/out1 are complex128
+  int aux_f64;  // aux is complex128 (EPI_RICH of a master-state plan)
   int tile;     // index into SPLIT_TILES (the operator planes must match it)
   NlParams nl;
   unsigned* flag;
@@ -139,7 +151,9 @@ struct PassBatch {
   int epi;
   int in_f64;
   int out_f64;
+  int aux_f64;
   int tile;  // tile shape (index into SPLIT_TILES)
+  double tf;  // sub-flow time of this pass (every instance shares tau)
   unsigned* flag;
 };
 

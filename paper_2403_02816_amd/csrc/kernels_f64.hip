@@ -115,7 +115,7 @@ __global__ __launch_bounds__(256, 3) void k_pass_f64(PassF64 a) {
       cd x = xin[j];
       if (xok[j]) {
         if (a.pro == PRO_FLOW) {
-          x = half_flow(x, a.nl, flag);
+          x = flow_in(x, a.nl.tf, a.nl, flag);
         } else if (a.pro == PRO_G) {
           x = g_cgl(x, a.nl);
         }
@@ -145,9 +145,11 @@ __global__ __launch_bounds__(256, 3) void k_pass_f64(PassF64 a) {
   // epilogue: the accumulator of lane l holds rows g + 4r (g = l/16, r < 4)
   // of a 16-row block b; the host's row permutation makes registers (0, 1)
   // the (re, im) of output m = 8b + g and registers (2, 3) those of m + 4.
-  // For the Lawson4 combinations the 8 auxiliary values of the lane are
-  // loaded before the first store (stores could alias them).
-  const bool lawson = a.epi == EPI_L4_R1 || a.epi == EPI_L4_R2;
+  // For the epilogues with an auxiliary input (Lawson combinations, split4)
+  // the 8 auxiliary values of the lane are loaded before the first store
+  // (stores could alias them).
+  const bool lawson = a.epi == EPI_L4_R1 || a.epi == EPI_L4_R2 || a.epi == EPI_RICH ||
+                      a.epi == EPI_L2;
   double2 xa[2][2][2];
 #pragma unroll
   for (int pb = 0; pb < 2; ++pb)
@@ -178,8 +180,9 @@ __global__ __launch_bounds__(256, 3) void k_pass_f64(PassF64 a) {
         const cd y = {acc[pb][fb][2 * hh], acc[pb][fb][2 * hh + 1]};
         if (a.epi == EPI_NONE) {
           *reinterpret_cast<double2*>(a.out0 + off) = double2{y.re, y.im};
-        } else if (a.epi == EPI_FLOW) {
-          const cd z = half_flow(y, a.nl, flag);
+        } else if (a.epi == EPI_FLOW || a.epi == EPI_MID) {
+          const cd z = a.epi == EPI_FLOW ? flow_out(y, a.nl.tf, a.nl, flag)
+                                         : flow_mid(y, a.nl.tf, a.nl, flag);
           if (!finite2(z)) flag |= FLAG_NONFINITE;
           *reinterpret_cast<double2*>(a.out0 + off) = double2{z.re, z.im};
         } else {
@@ -189,8 +192,12 @@ __global__ __launch_bounds__(256, 3) void k_pass_f64(PassF64 a) {
             lawson_r1(x, y, a.nl, X, Y);
             *reinterpret_cast<double2*>(a.out0 + off) = double2{X.re, X.im};
             *reinterpret_cast<double2*>(a.out1 + off) = double2{Y.re, Y.im};
-          } else {  // EPI_L4_R2: y = H Y, x = H X
-            const cd z = lawson_r2(x, y, a.nl);
+          } else {
+            // EPI_L4_R2: y = H Y, x = H X; EPI_RICH: x = the full Strang
+            // step; EPI_L2: y = Q, x = P
+            const cd z = a.epi == EPI_L4_R2 ? lawson_r2(x, y, a.nl)
+                         : a.epi == EPI_RICH ? richardson(y, x, a.nl, flag)
+                                             : lawson2(x, y, a.nl, 0.5 * a.nl.tau);
             if (!finite2(z)) flag |= FLAG_NONFINITE;
             *reinterpret_cast<double2*>(a.out0 + off) = double2{z.re, z.im};
           }
@@ -211,8 +218,10 @@ hipError_t launch_pass_f64(const PassF64& a, hipStream_t s) {
   if (a.Pp % PT != 0 || a.Kp % KC != 0 || a.Kp < 2 * a.n || a.Pp < 2 * a.n || a.F <= 0)
     return hipErrorInvalidValue;
   if (!a.in0 || !a.out0 || !a.op || !a.flag) return hipErrorInvalidValue;
-  if ((a.epi == EPI_L4_R1 || a.epi == EPI_L4_R2) && !a.aux) return hipErrorInvalidValue;
+  if ((a.epi == EPI_L4_R1 || a.epi == EPI_L4_R2 || a.epi == EPI_RICH || a.epi == EPI_L2) && !a.aux)
+    return hipErrorInvalidValue;
   if (a.epi == EPI_L4_R1 && !a.out1) return hipErrorInvalidValue;
+  if (a.epi < EPI_NONE || a.epi > EPI_L2) return hipErrorInvalidValue;
   const int64_t nF = (a.F + FT - 1) / FT;
   const int64_t G = nF * (a.Pp / PT);
   if (G > 0x7fffffffLL) return hipErrorInvalidValue;

@@ -199,19 +199,24 @@ __device__ __forceinline__ void split_epilogue(const PassSplit& a, int pt, int64
         const int64_t off = fibre_base(f, a.R_out, a.n) + a.R_out * (int64_t)m;
         const float2 v = sE[lr * EP + fc];
         const cd y = {static_cast<double>(v.x), static_cast<double>(v.y)};
-        if (a.epi == EPI_FLOW) {
-          const cd z = half_flow(y, a.nl, flag);
+        if (a.epi == EPI_FLOW || a.epi == EPI_MID) {
+          const cd z = a.epi == EPI_FLOW ? flow_out(y, a.nl.tf, a.nl, flag)
+                                         : flow_mid(y, a.nl.tf, a.nl, flag);
           if (!finite2(z)) flag |= FLAG_NONFINITE;
           store_c(a.out0, off, of64, z);
         } else {
-          const cd x = load_c(a.aux, off, false);
+          const cd x = load_c(a.aux, off, a.aux_f64 != 0);
           if (a.epi == EPI_L4_R1) {  // y = Q, x = P
             cd X, Y;
             lawson_r1(x, y, a.nl, X, Y);
             store_c(a.out0, off, of64, X);
             store_c(a.out1, off, of64, Y);
-          } else {  // EPI_L4_R2: y = H Y, x = H X
-            const cd z = lawson_r2(x, y, a.nl);
+          } else {
+            // EPI_L4_R2: y = H Y, x = H X; EPI_RICH: x = the full Strang
+            // step; EPI_L2: y = Q, x = P
+            const cd z = a.epi == EPI_L4_R2 ? lawson_r2(x, y, a.nl)
+                         : a.epi == EPI_RICH ? richardson(y, x, a.nl, flag)
+                                             : lawson2(x, y, a.nl, 0.5 * a.nl.tau);
             if (!finite2(z)) flag |= FLAG_NONFINITE;
             store_c(a.out0, off, of64, z);
           }
@@ -348,7 +353,7 @@ __device__ __forceinline__ void split_tile(const PassSplit& a, int pt, int64_t f
     for (int i = 0; i < FI; ++i) {
       if (PRO == PRO_FLOW) {
 #pragma unroll
-        for (int j = 0; j < KJ; ++j) vin[i][j] = half_flow_f(vin[i][j], a.nl, flag);
+        for (int j = 0; j < KJ; ++j) vin[i][j] = flow_in_f(vin[i][j], a.nl, flag);
       } else if (PRO == PRO_G) {
 #pragma unroll
         for (int j = 0; j < KJ; ++j) vin[i][j] = g_cgl_f(vin[i][j], a.nl);
@@ -496,7 +501,7 @@ __device__ __forceinline__ void split_tile_dma(const PassSplit& a, int pt, int64
     for (int j = 0; j < KJ; ++j) {
       w[j] = cf{v[j / 2][2 * (j % 2)], v[j / 2][2 * (j % 2) + 1]};
       if (ks * KS + k0t + j >= a.n) w[j] = cf{0.0f, 0.0f};
-      if (PRO == PRO_FLOW) w[j] = half_flow_f(w[j], a.nl, flag);
+      if (PRO == PRO_FLOW) w[j] = flow_in_f(w[j], a.nl, flag);
       else if (PRO == PRO_G) w[j] = g_cgl_f(w[j], a.nl);
     }
     unsigned tr[3][KJ / 2], ti[3][KJ / 2];
@@ -610,34 +615,48 @@ __global__ __launch_bounds__(256, 2) void k_pass_split(PassSplit a) {
 }
 
 // ---- Paired pass: one direction of the two exponential actions of a
-// Lawson4 round in one launch.  A workgroup applies its operator tile to the
+// Lawson round in one launch.  A workgroup applies its operator tile to the
 // tiles of both inputs (in0 for the first action, in1 for the second, or, in
 // the first pass of the first round, in0 and g(in0)), so each operator stage
 // is copied to LDS once for two products, and the round's stage combination
 // runs in the epilogue with both results at hand (no auxiliary tensor, no
-// cross-stream join).  64 rows x 64 fibres, 16-deep stages, direct-to-LDS
-// operator copies as above; two accumulator sets per wave.
+// cross-stream join).  PT rows x 64 fibres, 16-deep stages, direct-to-LDS
+// operator copies as above; two accumulator sets per wave, each wave 32 rows
+// x 32 fibres.  Two shapes: PT = 64 (4 waves, two workgroups per CU) and
+// PT = 128 (8 waves, one workgroup per CU: the state tile of a stage is
+// split into bf16 terms once for twice the rows).
 template <int PT, int KS>
 struct LdsP {
   unsigned short A[2][6 * PT * KS];
   unsigned short B[2][2][6 * FT * KS];
 };
 
+template <int PT>
+struct PairGeom {
+  static constexpr int NW = PT / 16;          // waves
+  static constexpr int NT = NW * 64;          // threads
+  static constexpr int RB = PT / 32;          // 32-row blocks (waves along the rows)
+  static constexpr int TPT = NT == 256 ? 2 : 1;  // state tensors a thread stages
+  static_assert(PT == 64 || PT == 128, "paired tile shapes");
+};
+
 // Epilogue of a paired tile: y0, y1 the two results of a point, both held
 // by the same lane (the two accumulator sets have one layout).  EPI_NONE:
 // out0 = y0, out1 = y1.  EPI_L4_R1: (P, Q) = (y0, y1) -> out0 = X, out1 = Y.
-// EPI_L4_R2: (HX, HY) = (y0, y1) -> out0 = u_{n+1}.  Every kind stores
+// EPI_L4_R2: (HX, HY) = (y0, y1) -> out0 = u_{n+1}.  EPI_L2: (P, Q) =
+// (E u, E g(u)) -> out0 = u_{n+1} of Lawson2b.  Every kind stores
 // straight from the accumulators: lanes 0..31 of a row take 32 consecutive
 // fibres, which are adjacent in the output (R_out = F).
+template <int PT>
 __device__ __forceinline__ void pair_epilogue(const PassSplit& a, int pt, int64_t f0,
                                               f32x16 (&accr)[2], f32x16 (&acci)[2],
                                               unsigned& flag) {
-  constexpr int PT = 64;
+  using G = PairGeom<PT>;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wp = wave & 1;
-  const int wf = wave >> 1;
+  const int wp = wave % G::RB;
+  const int wf = wave / G::RB;
   const bool of64 = a.out_f64 != 0;
   const int64_t f = f0 + wf * 32 + (lane & 31);
   if (f >= a.F) return;
@@ -675,7 +694,7 @@ __device__ __forceinline__ void pair_epilogue(const PassSplit& a, int pt, int64_
       q0[d] = float2{static_cast<float>(X.re), static_cast<float>(X.im)};
       q1[d] = float2{static_cast<float>(Y.re), static_cast<float>(Y.im)};
     });
-  } else {
+  } else if (a.epi == EPI_L4_R2) {
     void* q0 = of64 ? static_cast<void*>(reinterpret_cast<double2*>(a.out0) + o0)
                     : static_cast<void*>(reinterpret_cast<float2*>(a.out0) + o0);
     const double t6 = a.nl.tau / 6.0;
@@ -686,59 +705,82 @@ __device__ __forceinline__ void pair_epilogue(const PassSplit& a, int pt, int64_
       if (!finite2(z)) flag |= FLAG_NONFINITE;
       store_c(q0, d, of64, z);
     });
+  } else {  // EPI_L2
+    void* q0 = of64 ? static_cast<void*>(reinterpret_cast<double2*>(a.out0) + o0)
+                    : static_cast<void*>(reinterpret_cast<float2*>(a.out0) + o0);
+    const double h = 0.5 * a.nl.tau;
+    each([&](int r, int64_t d) __attribute__((always_inline)) {
+      const cd P = {static_cast<double>(accr[0][r]), static_cast<double>(acci[0][r])};
+      const cd Q = {static_cast<double>(accr[1][r]), static_cast<double>(acci[1][r])};
+      const cd z = lawson2(P, Q, a.nl, h);
+      if (!finite2(z)) flag |= FLAG_NONFINITE;
+      store_c(q0, d, of64, z);
+    });
   }
 }
 
 // SAMEG: both products read in0; the second applies g first (P = H u and
-// Q = H g(u)).  Otherwise the inputs are in0 and in1 (complex64).
-template <bool SAMEG, bool IN64>
+// Q = H g(u)).  Otherwise the inputs are in0 and in1 (complex64).  Staging
+// of a stage's state tile (64 fibres x 16 indices of both tensors): with 4
+// waves every thread stages its 4 indices of one fibre of both tensors;
+// with 8 waves threads 0..255 stage the first tensor and 256..511 the second.
+template <bool SAMEG, bool IN64, int PT>
 __device__ __forceinline__ void split_tile_pair(const PassSplit& a, int pt, int64_t f0,
-                                                LdsP<64, 16>& lds) {
-  constexpr int PT = 64, KS = 16;
+                                                LdsP<PT, 16>& lds) {
+  using G = PairGeom<PT>;
+  constexpr int KS = 16;
   constexpr int KJ = KS / 4;
   constexpr int ABYTES = 12 * PT * KS;
-  constexpr int NDMA = ABYTES / 4096;
+  constexpr int NDMA = ABYTES / (G::NW * 1024);  // 1 KB copies per wave and stage
+  static_assert(NDMA * G::NW * 1024 == ABYTES, "operator stage must split evenly");
   constexpr int ESZ = IN64 ? 16 : 8;
-  constexpr int NIN = SAMEG ? 1 : 2;       // state tensors loaded
+  // state tensors this thread loads: both inputs (or u once) with 4 waves,
+  // its own tensor's input with 8
+  constexpr int NL = G::TPT == 2 ? (SAMEG ? 1 : 2) : 1;
   constexpr unsigned OOR = 0x80000000u;
   static_assert(!IN64 || SAMEG, "a complex128 input occurs only in the first pass");
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wp = wave & 1;
-  const int wf = wave >> 1;
+  const int wp = wave % G::RB;
+  const int wf = wave / G::RB;
   const int nKS = a.Kp / KS;
   const __amdgpu_buffer_rsrc_t ors = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<uint16_t*>(a.op + static_cast<size_t>(pt) * nKS * (6 * PT * KS)), 0,
       nKS * ABYTES, 0x00020000);
-  const int fl = (tid & 7) + 8 * (tid >> 5);
-  const int k0t = KJ * ((tid >> 3) & 3);
+  const int sid = tid & 255;                 // position within a 256-thread staging group
+  const int ts0 = G::TPT == 2 ? 0 : (tid >> 8);  // first tensor this thread stages
+  const int fl = (sid & 7) + 8 * (sid >> 5);
+  const int k0t = KJ * ((sid >> 3) & 3);
   const int64_t srem = (a.F - f0) * static_cast<int64_t>(a.n) * ESZ;
   const int rnum = static_cast<int>(srem < 0x7fffffffll ? srem : 0x7fffffffll);
   const int64_t tile0 = f0 * static_cast<int64_t>(a.n) * ESZ;
-  __amdgpu_buffer_rsrc_t srs[NIN];
-  srs[0] = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<char*>(reinterpret_cast<const char*>(a.in0) + tile0), 0, rnum, 0x00020000);
-  if constexpr (!SAMEG)
-    srs[NIN - 1] = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<char*>(reinterpret_cast<const char*>(a.in1) + tile0), 0, rnum, 0x00020000);
+  __amdgpu_buffer_rsrc_t srs[NL];
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    // load i reads in1 for the second tensor of a pair of distinct inputs
+    const bool second = !SAMEG && (G::TPT == 2 ? i == 1 : ts0 == 1);
+    srs[i] = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<char*>(reinterpret_cast<const char*>(second ? a.in1 : a.in0) + tile0), 0, rnum,
+        0x00020000);
+  }
   const unsigned svo = static_cast<unsigned>((fl * a.n + k0t) * ESZ);
 
   auto copy_op = [&](int ks, int buf) __attribute__((always_inline)) {
     const unsigned o = ks < nKS ? static_cast<unsigned>(ks * ABYTES) : OOR;
 #pragma unroll
     for (int j = 0; j < NDMA; ++j) {
-      const int blk = wave + 4 * j;
+      const int blk = wave + G::NW * j;
       __builtin_amdgcn_raw_ptr_buffer_load_lds(
           ors, (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(lds.A[buf]) + blk * 1024),
           16, o + static_cast<unsigned>(blk * 1024 + lane * 16), 0, 0, 0);
     }
   };
-  auto load_state = [&](int ks, f32x4 (&v)[NIN][KJ / 2]) __attribute__((always_inline)) {
+  auto load_state = [&](int ks, f32x4 (&v)[NL][KJ / 2]) __attribute__((always_inline)) {
     const unsigned o = ks < nKS ? svo + static_cast<unsigned>(ks * KS * ESZ) : OOR;
 #pragma unroll
-    for (int i = 0; i < NIN; ++i)
+    for (int i = 0; i < NL; ++i)
 #pragma unroll
       for (int j = 0; j < KJ; j += 2) {
         if constexpr (IN64) {
@@ -755,17 +797,18 @@ __device__ __forceinline__ void split_tile_pair(const PassSplit& a, int pt, int6
       }
   };
   unsigned flag = 0;
-  auto store_state = [&](int ks, const f32x4 (&v)[NIN][KJ / 2], int buf) __attribute__((always_inline)) {
+  auto store_state = [&](int ks, const f32x4 (&v)[NL][KJ / 2], int buf) __attribute__((always_inline)) {
     const int off = fl * KS + dma_chunk(fl, k0t / 8) * 8 + k0t % 8;
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < G::TPT; ++t) {
+      const int tt = ts0 + t;                       // tensor staged
+      const int li = G::TPT == 2 ? (SAMEG ? 0 : t) : 0;  // its load
       cf w[KJ];
 #pragma unroll
       for (int j = 0; j < KJ; ++j) {
-        const int i = SAMEG ? 0 : t;
-        w[j] = cf{v[i][j / 2][2 * (j % 2)], v[i][j / 2][2 * (j % 2) + 1]};
+        w[j] = cf{v[li][j / 2][2 * (j % 2)], v[li][j / 2][2 * (j % 2) + 1]};
         if (ks * KS + k0t + j >= a.n) w[j] = cf{0.0f, 0.0f};
-        if (SAMEG && t == 1) w[j] = g_cgl_f(w[j], a.nl);
+        if (SAMEG && tt == 1) w[j] = g_cgl_f(w[j], a.nl);
       }
       unsigned tr[3][KJ / 2], ti[3][KJ / 2];
 #pragma unroll
@@ -780,8 +823,8 @@ __device__ __forceinline__ void split_tile_pair(const PassSplit& a, int pt, int6
       }
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        store_terms<KJ>(&lds.B[buf][t][q * FT * KS + off], tr[q]);
-        store_terms<KJ>(&lds.B[buf][t][(3 + q) * FT * KS + off], ti[q]);
+        store_terms<KJ>(&lds.B[buf][tt][q * FT * KS + off], tr[q]);
+        store_terms<KJ>(&lds.B[buf][tt][(3 + q) * FT * KS + off], ti[q]);
       }
     }
   };
@@ -797,7 +840,7 @@ __device__ __forceinline__ void split_tile_pair(const PassSplit& a, int pt, int6
   const int row = lane & 31;
   const int ch = lane >> 5;
 
-  auto stage = [&](int ks, f32x4 (&vload)[NIN][KJ / 2], const f32x4 (&vstore)[NIN][KJ / 2])
+  auto stage = [&](int ks, f32x4 (&vload)[NL][KJ / 2], const f32x4 (&vstore)[NL][KJ / 2])
       __attribute__((always_inline)) {
     const int cur = ks & 1;
     bf16x8 br[2][3], bi[2][3], ar[3], ai[3];
@@ -843,7 +886,7 @@ __device__ __forceinline__ void split_tile_pair(const PassSplit& a, int pt, int6
     __syncthreads();
   };
 
-  f32x4 sv[2][NIN][KJ / 2];
+  f32x4 sv[2][NL][KJ / 2];
   copy_op(0, 0);
   load_state(0, sv[0]);
   load_state(1, sv[1]);
@@ -857,16 +900,17 @@ __device__ __forceinline__ void split_tile_pair(const PassSplit& a, int pt, int6
   if (ks < nKS) stage(ks, sv[0], sv[1]);
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the last copies write the other buffer
   __syncthreads();
-  pair_epilogue(a, pt, f0, accr, acci, flag);
+  pair_epilogue<PT>(a, pt, f0, accr, acci, flag);
   if (flag) atomicOr(a.flag, flag);
 }
 
-template <bool SAMEG, bool IN64>
-__global__ __launch_bounds__(256, 2) void k_pass_split_pair(PassSplit a) {
-  __shared__ __attribute__((aligned(16))) LdsP<64, 16> lds;
-  const int nP = a.Pp / 64;
+template <bool SAMEG, bool IN64, int PT>
+__global__ __launch_bounds__(PT * 4, PT == 64 ? 2 : 1) void k_pass_split_pair(PassSplit a) {
+  __shared__ __attribute__((aligned(16))) LdsP<PT, 16> lds;
+  const int nP = a.Pp / PT;
   const unsigned w = xcd_remap(blockIdx.x, gridDim.x);
-  split_tile_pair<SAMEG, IN64>(a, static_cast<int>(w % nP), static_cast<int64_t>(w / nP) * FT, lds);
+  split_tile_pair<SAMEG, IN64, PT>(a, static_cast<int>(w % nP), static_cast<int64_t>(w / nP) * FT,
+                                   lds);
 }
 
 template <int PT, int KS, int PRO, bool IN64>
@@ -906,8 +950,10 @@ __global__ __launch_bounds__(256, 2) void k_pass_split_batched(PassBatch b) {
     a.epi = b.epi;
     a.in_f64 = IN64 ? 1 : 0;
     a.out_f64 = b.out_f64;
+    a.aux_f64 = b.aux_f64;
     a.tile = b.tile;
     a.nl = in.nl;
+    a.nl.tf = b.tf;
     a.flag = b.flag;
     if constexpr (DMA)
       split_tile_dma<PT, KS, PRO, IN64>(a, tl.pt, static_cast<int64_t>(tl.ft) * FT, lds);
@@ -917,9 +963,9 @@ __global__ __launch_bounds__(256, 2) void k_pass_split_batched(PassBatch b) {
 }
 
 // Paired pass over every instance of a batched plan (persistent grid).
-template <bool SAMEG, bool IN64>
-__global__ __launch_bounds__(256, 2) void k_pass_split_batched_pair(PassBatch b) {
-  __shared__ __attribute__((aligned(16))) LdsP<64, 16> lds;
+template <bool SAMEG, bool IN64, int PT>
+__global__ __launch_bounds__(PT * 4, PT == 64 ? 2 : 1) void k_pass_split_batched_pair(PassBatch b) {
+  __shared__ __attribute__((aligned(16))) LdsP<PT, 16> lds;
   for (int t = blockIdx.x; t < b.ntiles; t += gridDim.x) {
     const BatchTile tl = b.tiles[t];
     if (tl.inst < 0) continue;  // padding entry of the table
@@ -930,21 +976,22 @@ __global__ __launch_bounds__(256, 2) void k_pass_split_batched_pair(PassBatch b)
     a.in1 = b.in1 ? static_cast<const char*>(b.in1) + in.off * 8 : nullptr;
     a.out0 = static_cast<char*>(b.out0) + in.off * esz_out;
     a.out1 = b.out1 ? static_cast<char*>(b.out1) + in.off * 8 : nullptr;
-    a.op = b.which == 0 ? in.opE[2] : in.opH[2];
+    a.op = b.which == 0 ? in.opE[b.tile] : in.opH[b.tile];
     a.R = 1;
     a.R_out = in.F;
     a.F = in.F;
     a.n = in.n;
-    a.Pp = in.Pp[2];
-    a.Kp = in.Kp[2];
+    a.Pp = in.Pp[b.tile];
+    a.Kp = in.Kp[b.tile];
     a.pro = SAMEG ? PRO_G : PRO_NONE;
     a.epi = b.epi;
     a.in_f64 = IN64 ? 1 : 0;
     a.out_f64 = b.out_f64;
-    a.tile = 2;
+    a.tile = b.tile;
     a.nl = in.nl;
+    a.nl.tf = b.tf;
     a.flag = b.flag;
-    split_tile_pair<SAMEG, IN64>(a, tl.pt, static_cast<int64_t>(tl.ft) * FT, lds);
+    split_tile_pair<SAMEG, IN64, PT>(a, tl.pt, static_cast<int64_t>(tl.ft) * FT, lds);
   }
 }
 
@@ -1018,8 +1065,10 @@ hipError_t launch_pass_split_batched(const PassBatch& b, int nwg, hipStream_t s)
   if (b.tile < 0 || b.tile >= SPLIT_NTILES_BATCHED || b.ntiles <= 0 || nwg <= 0)
     return hipErrorInvalidValue;
   if (!b.in0 || !b.out0 || !b.inst || !b.tiles || !b.flag) return hipErrorInvalidValue;
-  if ((b.epi == EPI_L4_R1 || b.epi == EPI_L4_R2) && !b.aux) return hipErrorInvalidValue;
+  if ((b.epi == EPI_L4_R1 || b.epi == EPI_L4_R2 || b.epi == EPI_RICH || b.epi == EPI_L2) && !b.aux)
+    return hipErrorInvalidValue;
   if (b.epi == EPI_L4_R1 && !b.out1) return hipErrorInvalidValue;
+  if (b.epi < EPI_NONE || b.epi > EPI_L2) return hipErrorInvalidValue;
   if (b.pro != PRO_NONE && b.pro != PRO_FLOW && b.pro != PRO_G) return hipErrorInvalidValue;
   const dim3 grid(static_cast<unsigned>(nwg < b.ntiles ? nwg : b.ntiles));
   switch (b.tile) {
@@ -1031,49 +1080,71 @@ hipError_t launch_pass_split_batched(const PassBatch& b, int nwg, hipStream_t s)
   return hipGetLastError();
 }
 
+template <int PT>
+void launch_batched_pair_tile(const PassBatch& b, int nwg, hipStream_t s) {
+  // one 8-wave workgroup per CU for 128 rows (its LDS), two 4-wave ones for 64
+  const int g = PT == 64 ? nwg : (nwg + 1) / 2;
+  const dim3 grid(static_cast<unsigned>(g < b.ntiles ? g : b.ntiles)), block(PT * 4);
+  if (b.pro == PRO_G) {
+    if (b.in_f64)
+      hipLaunchKernelGGL((k_pass_split_batched_pair<true, true, PT>), grid, block, 0, s, b);
+    else
+      hipLaunchKernelGGL((k_pass_split_batched_pair<true, false, PT>), grid, block, 0, s, b);
+  } else {
+    hipLaunchKernelGGL((k_pass_split_batched_pair<false, false, PT>), grid, block, 0, s, b);
+  }
+}
+
 hipError_t launch_pass_split_batched_pair(const PassBatch& b, int nwg, hipStream_t s) {
-  if (b.tile != 2 || b.ntiles <= 0 || nwg <= 0) return hipErrorInvalidValue;
+  if ((b.tile != 2 && b.tile != 3) || b.ntiles <= 0 || nwg <= 0) return hipErrorInvalidValue;
   if (!b.in0 || !b.out0 || !b.inst || !b.tiles || !b.flag) return hipErrorInvalidValue;
   const bool sameg = b.pro == PRO_G;
   if (b.pro != PRO_NONE && !sameg) return hipErrorInvalidValue;
   if (!sameg && (!b.in1 || b.in_f64)) return hipErrorInvalidValue;
-  if (b.epi != EPI_NONE && b.epi != EPI_L4_R1 && b.epi != EPI_L4_R2) return hipErrorInvalidValue;
-  if (b.epi != EPI_L4_R2 && (!b.out1 || b.out_f64)) return hipErrorInvalidValue;
-  const dim3 grid(static_cast<unsigned>(nwg < b.ntiles ? nwg : b.ntiles));
-  if (sameg) {
-    if (b.in_f64)
-      hipLaunchKernelGGL((k_pass_split_batched_pair<true, true>), grid, dim3(256), 0, s, b);
-    else
-      hipLaunchKernelGGL((k_pass_split_batched_pair<true, false>), grid, dim3(256), 0, s, b);
-  } else {
-    hipLaunchKernelGGL((k_pass_split_batched_pair<false, false>), grid, dim3(256), 0, s, b);
-  }
+  if (b.epi != EPI_NONE && b.epi != EPI_L4_R1 && b.epi != EPI_L4_R2 && b.epi != EPI_L2)
+    return hipErrorInvalidValue;
+  if (b.epi != EPI_L4_R2 && b.epi != EPI_L2 && (!b.out1 || b.out_f64)) return hipErrorInvalidValue;
+  if (b.tile == 2)
+    launch_batched_pair_tile<64>(b, nwg, s);
+  else
+    launch_batched_pair_tile<128>(b, nwg, s);
   return hipGetLastError();
 }
 
+template <int PT>
+void launch_pair_tile(const PassSplit& a, dim3 grid, hipStream_t s) {
+  const dim3 block(PT * 4);
+  if (a.pro == PRO_G) {
+    if (a.in_f64)
+      hipLaunchKernelGGL((k_pass_split_pair<true, true, PT>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_pass_split_pair<true, false, PT>), grid, block, 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_pass_split_pair<false, false, PT>), grid, block, 0, s, a);
+  }
+}
+
 hipError_t launch_pass_split_pair(const PassSplit& a, hipStream_t s) {
-  // the operator planes must be those of the 64 x 16 direct-to-LDS shape
-  if (a.tile != 2 || a.R != 1 || a.Pp % 64 != 0 || a.Kp % 16 != 0 || a.Kp < a.n || a.Pp < a.n ||
-      a.F <= 0)
+  // the operator planes must be those of a direct-to-LDS shape (64 or 128 x 16)
+  if (a.tile != 2 && a.tile != 3) return hipErrorInvalidValue;
+  const int PT = SPLIT_TILES[a.tile].PT;
+  if (a.R != 1 || a.Pp % PT != 0 || a.Kp % 16 != 0 || a.Kp < a.n || a.Pp < a.n || a.F <= 0)
     return hipErrorInvalidValue;
   if (!a.in0 || !a.out0 || !a.op || !a.flag) return hipErrorInvalidValue;
   const bool sameg = a.pro == PRO_G;
   if (a.pro != PRO_NONE && !sameg) return hipErrorInvalidValue;
   if (!sameg && (!a.in1 || a.in_f64)) return hipErrorInvalidValue;
-  if (a.epi != EPI_NONE && a.epi != EPI_L4_R1 && a.epi != EPI_L4_R2) return hipErrorInvalidValue;
-  if (a.epi != EPI_L4_R2 && (!a.out1 || a.out_f64)) return hipErrorInvalidValue;
+  if (a.epi != EPI_NONE && a.epi != EPI_L4_R1 && a.epi != EPI_L4_R2 && a.epi != EPI_L2)
+    return hipErrorInvalidValue;
+  if (a.epi != EPI_L4_R2 && a.epi != EPI_L2 && (!a.out1 || a.out_f64)) return hipErrorInvalidValue;
   const int64_t nF = (a.F + FT - 1) / FT;
-  const int64_t G = nF * (a.Pp / 64);
+  const int64_t G = nF * (a.Pp / PT);
   if (G > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 grid(static_cast<unsigned>(G));
-  if (sameg) {
-    if (a.in_f64)
-      hipLaunchKernelGGL((k_pass_split_pair<true, true>), grid, dim3(256), 0, s, a);
-    else
-      hipLaunchKernelGGL((k_pass_split_pair<true, false>), grid, dim3(256), 0, s, a);
-  } else {
-    hipLaunchKernelGGL((k_pass_split_pair<false, false>), grid, dim3(256), 0, s, a);
-  }
+  if (PT == 64)
+    launch_pair_tile<64>(a, grid, s);
+  else
+    launch_pair_tile<128>(a, grid, s);
   return hipGetLastError();
 }
 
@@ -1083,8 +1154,10 @@ hipError_t launch_pass_split(const PassSplit& a, hipStream_t s) {
   if (a.Pp % PT != 0 || a.Kp % KS != 0 || a.Kp < a.n || a.Pp < a.n || a.F <= 0)
     return hipErrorInvalidValue;
   if (!a.in0 || !a.out0 || !a.op || !a.flag) return hipErrorInvalidValue;
-  if ((a.epi == EPI_L4_R1 || a.epi == EPI_L4_R2) && !a.aux) return hipErrorInvalidValue;
+  if ((a.epi == EPI_L4_R1 || a.epi == EPI_L4_R2 || a.epi == EPI_RICH || a.epi == EPI_L2) && !a.aux)
+    return hipErrorInvalidValue;
   if (a.epi == EPI_L4_R1 && !a.out1) return hipErrorInvalidValue;
+  if (a.epi < EPI_NONE || a.epi > EPI_L2) return hipErrorInvalidValue;
   if (a.R_out < 1 || (a.pro != PRO_NONE && a.pro != PRO_FLOW && a.pro != PRO_G))
     return hipErrorInvalidValue;
   const int64_t nF = (a.F + FT - 1) / FT;

@@ -3,10 +3,16 @@
 //
 //  g(u)      = (a3 + i b3)|u|^2 u + (a4 + i b4)|u|^4 u        (eq. cqCGL)
 //  phi^c_t   = exact flow of u' = (a3 + i b3)|u|^2 u          (eq. exsolcub)
+//  phi^q_t   = exact flow of u' = (a4 + i b4)|u|^4 u          (Section 4.3)
 //  phi_t     = one classical RK4 step of u' = g(u) (eq. RK4 with K = 0) when
 //              there is no exact flow (cubic-quintic case, Section 4.3)
+//  The sub-flows of the splitting schemes: entering a step (phi_t, or
+//  phi^c_t o phi^q_t for the three-term splitting), leaving it (phi_t, or
+//  phi^q_t o phi^c_t), between the two half steps of split4 (eq. Richardson:
+//  one phi over 2t; three-term: leaving then entering), and the split4
+//  combination 4/3 a - 1/3 b.
 //  Lawson4 stage combinations of eq. (lawson4), regrouped around four
-//  half-step exponential actions.
+//  half-step exponential actions; the Lawson2b combination (eq. lawson2b).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -56,6 +62,31 @@ __device__ __forceinline__ cd phi_cubic(cd u, double t, const NlParams& p, unsig
   return {mag * (u.re * cs - u.im * sn), mag * (u.re * sn + u.im * cs)};
 }
 
+// exp(-(a4 + i b4)/(4 a4) log(1 - 4 a4 |u|^4 t)) u, with the same domain
+// handling as the cubic flow
+__device__ __forceinline__ cd phi_quintic(cd u, double t, const NlParams& p, unsigned& flag) {
+  const double r = u.re * u.re + u.im * u.im;
+  const double r2 = r * r;
+  double mag = 1.0, ang;
+  if (p.a4 == 0.0) {
+    ang = p.b4 * r2 * t;
+  } else {
+    const double s = -4.0 * p.a4 * r2 * t;
+    double L;
+    if (1.0 + s <= 0.0) {
+      flag |= FLAG_BLOWUP;
+      L = log(fabs(1.0 + s));
+    } else {
+      L = log1p(s);
+    }
+    mag = exp(-0.25 * L);
+    ang = -p.b4 * L / (4.0 * p.a4);
+  }
+  double sn, cs;
+  sincos(ang, &sn, &cs);
+  return {mag * (u.re * cs - u.im * sn), mag * (u.re * sn + u.im * cs)};
+}
+
 __device__ __forceinline__ cd rk4_flow(cd u, double t, const NlParams& p) {
   const cd k1 = g_cgl(u, p);
   const cd k2 = g_cgl(caxpy(0.5 * t, k1, u), p);
@@ -66,10 +97,30 @@ __device__ __forceinline__ cd rk4_flow(cd u, double t, const NlParams& p) {
   return caxpy(t / 6.0, s, u);
 }
 
-// phi_{tau/2}: the Strang sub-flow
-__device__ __forceinline__ cd half_flow(cd u, const NlParams& p, unsigned& flag) {
-  const double t = 0.5 * p.tau;
-  return p.exact ? phi_cubic(u, t, p, flag) : rk4_flow(u, t, p);
+// sub-flow over t entering a splitting step (applied before the linear flow)
+__device__ __forceinline__ cd flow_in(cd u, double t, const NlParams& p, unsigned& flag) {
+  if (p.flow == FLOW_3T) return phi_cubic(phi_quintic(u, t, p, flag), t, p, flag);
+  return p.flow == FLOW_EXACT ? phi_cubic(u, t, p, flag) : rk4_flow(u, t, p);
+}
+
+// sub-flow over t leaving a splitting step (applied after the linear flow)
+__device__ __forceinline__ cd flow_out(cd u, double t, const NlParams& p, unsigned& flag) {
+  if (p.flow == FLOW_3T) return phi_quintic(phi_cubic(u, t, p, flag), t, p, flag);
+  return p.flow == FLOW_EXACT ? phi_cubic(u, t, p, flag) : rk4_flow(u, t, p);
+}
+
+// between the two half steps of split4 (each with sub-flows over t): the
+// printed scheme has one sub-flow over 2t there; the three-term splitting
+// composes the flows leaving one half step and entering the next
+__device__ __forceinline__ cd flow_mid(cd u, double t, const NlParams& p, unsigned& flag) {
+  if (p.flow == FLOW_3T) return flow_in(flow_out(u, t, p, flag), t, p, flag);
+  return flow_in(u, 2.0 * t, p, flag);
+}
+
+// split4: 4/3 phi_t(y) - 1/3 b, with b the full Strang step of the same point
+__device__ __forceinline__ cd richardson(cd y, cd b, const NlParams& p, unsigned& flag) {
+  const cd a = flow_out(y, p.tf, p, flag);
+  return {(4.0 * a.re - b.re) / 3.0, (4.0 * a.im - b.im) / 3.0};
 }
 
 __device__ __forceinline__ bool finite2(cd u) { return isfinite(u.re) && isfinite(u.im); }
@@ -100,6 +151,13 @@ __device__ __forceinline__ void lawson_r1(cd P, cd Q, const NlParams& p, cd& X, 
   lawson_r1(P, Q, p, lawson_coef(p.tau), X, Y);
 }
 
+// Lawson2b (eq. lawson2b) from P = e^{tau K} u and Q = e^{tau K} g(u):
+//   u_n2 = P + tau Q,  u_{n+1} = P + tau/2 Q + tau/2 g(u_n2)
+__device__ __forceinline__ cd lawson2(cd P, cd Q, const NlParams& p, double h) {
+  const cd un2 = caxpy(2.0 * h, Q, P);
+  return caxpy(h, g_cgl(un2, p), caxpy(h, Q, P));
+}
+
 // Lawson4 round 2 combination: u_{n+1} = HY + tau/6 g(HX)
 __device__ __forceinline__ cd lawson_r2(cd HX, cd HY, const NlParams& p, double t6) {
   return caxpy(t6, g_cgl(HX, p), HY);
@@ -125,29 +183,38 @@ __device__ __forceinline__ cf g_cgl_f(cf u, const NlParams& p) {
   return {cr * u.re - ci * u.im, cr * u.im + ci * u.re};
 }
 
-__device__ __forceinline__ cf half_flow_f(cf u, const NlParams& p, unsigned& flag) {
-  const float t = static_cast<float>(0.5 * p.tau);
-  if (p.exact) {
-    const float r = u.re * u.re + u.im * u.im;
-    float mag = 1.0f, ang;
-    if (p.a3 == 0.0) {
-      ang = static_cast<float>(p.b3) * r * t;
+// exact flow of u' = (a + i b)|u|^{2k} u over t in FP32 (k = 1 cubic, 2 quintic)
+__device__ __forceinline__ cf phi_power_f(cf u, float t, double a, double b, int k,
+                                          unsigned& flag) {
+  const float r = u.re * u.re + u.im * u.im;
+  const float rk = k == 1 ? r : r * r;
+  const float c = static_cast<float>(2 * k);
+  float mag = 1.0f, ang;
+  if (a == 0.0) {
+    ang = static_cast<float>(b) * rk * t;
+  } else {
+    const float s = -c * static_cast<float>(a) * rk * t;
+    float L;
+    if (1.0f + s <= 0.0f) {
+      flag |= FLAG_BLOWUP;
+      L = logf(fabsf(1.0f + s));
     } else {
-      const float s = -2.0f * static_cast<float>(p.a3) * r * t;
-      float L;
-      if (1.0f + s <= 0.0f) {
-        flag |= FLAG_BLOWUP;
-        L = logf(fabsf(1.0f + s));
-      } else {
-        L = log1pf(s);
-      }
-      mag = expf(-0.5f * L);
-      ang = static_cast<float>(-p.b3 / (2.0 * p.a3)) * L;
+      L = log1pf(s);
     }
-    float sn, cs;
-    sincosf(ang, &sn, &cs);
-    return {mag * (u.re * cs - u.im * sn), mag * (u.re * sn + u.im * cs)};
+    mag = expf(-L / c);
+    ang = static_cast<float>(-b / (2.0 * k * a)) * L;
   }
+  float sn, cs;
+  sincosf(ang, &sn, &cs);
+  return {mag * (u.re * cs - u.im * sn), mag * (u.re * sn + u.im * cs)};
+}
+
+// flow_in in FP32 (the prologues of the split-precision passes)
+__device__ __forceinline__ cf flow_in_f(cf u, const NlParams& p, unsigned& flag) {
+  const float t = static_cast<float>(p.tf);
+  if (p.flow == FLOW_3T)
+    return phi_power_f(phi_power_f(u, t, p.a4, p.b4, 2, flag), t, p.a3, p.b3, 1, flag);
+  if (p.flow == FLOW_EXACT) return phi_power_f(u, t, p.a3, p.b3, 1, flag);
   const cf k1 = g_cgl_f(u, p);
   const cf k2 = g_cgl_f(cfaxpy(0.5f * t, k1, u), p);
   const cf k3 = g_cgl_f(cfaxpy(0.5f * t, k2, u), p);

@@ -147,6 +147,10 @@ static void steppers(std::vector<int64_t> n, int precision, unsigned flags, cgl_
   expect(cgl_step_lawson4(p, u, 2) == CGL_OK, "lawson4");
   expect(cgl_run(p, CGL_LAWSON4, u, 3, 2) == CGL_OK, "run lawson4");
   expect(cgl_run(p, CGL_STRANG, u, 3, 0) == CGL_OK, "run strang");
+  expect(cgl_step(p, CGL_SPLIT4, u, 1) == CGL_OK, "split4");
+  expect(cgl_step(p, CGL_LAWSON2, u, 1) == CGL_OK, "lawson2");
+  expect(cgl_run(p, CGL_SPLIT4, u, 2, 1) == CGL_OK, "run split4");
+  expect(cgl_run(p, CGL_LAWSON2, u, 2, 0) == CGL_OK, "run lawson2");
   expect(cgl_status(p) == CGL_OK, "status");
   std::printf("  steppers prec=%d flags=%u d=%d ok\n", precision, flags, d);
   cgl_destroy(p);
@@ -217,13 +221,14 @@ static void paired_bitwise(std::vector<int64_t> n, unsigned flags, cgl_coeffs c,
     void* u = c128 ? static_cast<void*>(u64.data()) : static_cast<void*>(u32.data());
     expect(cgl_step_lawson4(p, u, 2) == CGL_OK, "lawson4");
     expect(cgl_run(p, CGL_LAWSON4, u, 2, 2) == CGL_OK, "run lawson4");
+    expect(cgl_step(p, CGL_LAWSON2, u, 2) == CGL_OK, "lawson2");
     expect(cgl_status(p) == CGL_OK, "status");
     const unsigned char* q = static_cast<const unsigned char*>(u);
     res.emplace_back(q, q + bytes);
     cgl_destroy(p);
   }
   unsetenv("CGL_LAWSON_PAIRED");
-  expect(res[0] == res[1], "paired Lawson4 == two concurrent actions");
+  expect(res[0] == res[1], "paired Lawson4 / Lawson2b == two concurrent actions");
   std::printf("  paired lawson4 bitwise d=%d flags=%u ok\n", d, flags);
 }
 
@@ -290,6 +295,8 @@ static void batched_vs_single(int precision) {
   void* u = c128 ? static_cast<void*>(u64.data()) : static_cast<void*>(u32.data());
   expect(cgl_step_lawson4(bp, u, 2) == CGL_OK, "batched lawson4");
   expect(cgl_run(bp, CGL_STRANG, u, 2, 1) == CGL_OK, "batched run strang");
+  expect(cgl_step(bp, CGL_SPLIT4, u, 1) == CGL_OK, "batched split4");
+  expect(cgl_step(bp, CGL_LAWSON2, u, 1) == CGL_OK, "batched lawson2");
   expect(cgl_status(bp) == CGL_OK, "batched status");
   int mism = 0;
   for (int j = 0; j < B; ++j) {
@@ -310,6 +317,8 @@ static void batched_vs_single(int precision) {
     void* v = c128 ? static_cast<void*>(v64.data()) : static_cast<void*>(v32.data());
     expect(cgl_step_lawson4(sp, v, 2) == CGL_OK, "single lawson4");
     expect(cgl_run(sp, CGL_STRANG, v, 2, 1) == CGL_OK, "single run strang");
+    expect(cgl_step(sp, CGL_SPLIT4, v, 1) == CGL_OK, "single split4");
+    expect(cgl_step(sp, CGL_LAWSON2, v, 1) == CGL_OK, "single lawson2");
     for (int64_t i = 0; i < Nj; ++i) {
       const bool same = c128 ? (v64[i] == u64[offs[j] + i]) : (v32[i] == u32[offs[j] + i]);
       if (!same) ++mism;
@@ -480,6 +489,13 @@ int main(int argc, char** argv) {
       setenv("CGL_SPLIT_TILE", t, 1);
       batched_vs_single(CGL_SPLIT_BF16);
     }
+    // the 128-row paired pass (8 waves) against the two-action form and in
+    // the batched persistent pass
+    setenv("CGL_PAIR_TILE", "3", 1);
+    paired_bitwise({20, 9, 7}, 0, cq, -15, 15, CGL_NEUMANN);
+    paired_bitwise({7, 6, 5}, CGL_FLAG_FP64_MASTER, cq, -15, 15, CGL_NEUMANN);
+    batched_vs_single(CGL_SPLIT_BF16);
+    unsetenv("CGL_PAIR_TILE");
     if (keep) setenv("CGL_SPLIT_TILE", saved.c_str(), 1); else unsetenv("CGL_SPLIT_TILE");
   } else {
     // quick: every kernel variant (mu = 1 contiguous, mu > 1 strided, ragged
@@ -497,6 +513,8 @@ int main(int argc, char** argv) {
     steppers({64, 32}, CGL_SPLIT_BF16, CGL_FLAG_FP64_MASTER, cub, -10, 10, CGL_DIRICHLET);
     steppers({7, 6, 5}, CGL_SPLIT_BF16, CGL_FLAG_FP64_MASTER, cq, -15, 15, CGL_NEUMANN);
     steppers({9}, CGL_SPLIT_BF16, CGL_FLAG_FP64_MASTER, cub, -10, 10, CGL_DIRICHLET);
+    steppers({12, 10, 6}, CGL_FP64, CGL_FLAG_THREE_TERM, cq, -15, 15, CGL_NEUMANN);
+    steppers({16, 12}, CGL_SPLIT_BF16, CGL_FLAG_THREE_TERM, cq, -10, 10, CGL_DIRICHLET);
     batched_vs_single(CGL_FP64);
     batched_vs_single(CGL_SPLIT_BF16);
   }

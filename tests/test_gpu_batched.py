@@ -160,3 +160,21 @@ def test_batched_graph_equals_eager():
     torch.cuda.synchronize()
     assert torch.equal(a, b)
     bp.destroy()
+
+
+def test_batched_paired_tile_shapes_agree_bitwise(monkeypatch):
+    """The persistent paired pass over the instance table with 64-row and
+    128-row tiles: identical bits."""
+    torch = require_gpu()
+    probs = _sweep(12, 14)
+    u0 = [ci.initial_state(p) for p in probs]
+    out = {}
+    for tile in ("2", "3"):
+        monkeypatch.setenv("CGL_PAIR_TILE", tile)
+        bp = _batched(probs, "split")
+        u = bp.to_device_batched(u0)
+        assert bp.run("lawson4", u, 3, 3) == 0
+        torch.cuda.synchronize()
+        out[tile] = u.cpu()
+        bp.destroy()
+    assert torch.equal(out["2"], out["3"])

@@ -12,11 +12,18 @@ from tests._util import assert_close, log, require_gpu
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("precision", ["fp64", "split"])
-def test_largest_and_smallest_direction(precision):
+@pytest.mark.parametrize("precision,nmax", [("fp64", 4096), ("split", 512), ("split", 4096)])
+def test_largest_and_smallest_direction(precision, nmax):
+    """A direction of nmax points beside one of 3.  The FP64 form meets 1e-13
+    up to the largest direction a plan accepts (4096).  The split form's FP32
+    accumulation over ~3n/4 additions per output drifts like u sqrt(3n/4):
+    it meets the 1e-6 bound in both measures up to n = 512 (the limit cgl.h
+    states; measured at n = 1024: 7.2e-7 in the 2-norm but 1.25e-6 in the
+    max-norm); at n = 4096 (1.45e-6, 2.5e-6) it is held to 3e-6, outside the
+    stated range."""
     torch = require_gpu()
     from paper_2403_02816_amd import cgl
-    shape = (4096, 3)
+    shape = (nmax, 3)
     p = cgl.Plan(shape, ci.C0.coeffs, 0.01, precision=precision)
     M = []
     for mu, n in enumerate(shape):
@@ -29,20 +36,15 @@ def test_largest_and_smallest_direction(precision):
         U = U.astype(np.complex64).astype(np.complex128)
     x = p.to_device(U, dtype=p.stage_dtype)
     out = torch.empty_like(x)
-    # split form: the 1e-6 bound holds for contraction lengths up to 256; an
-    # FP32 accumulator that takes ~3n/4 additions (the six term products of
-    # the four real products per 16-deep MFMA) drifts like u sqrt(3n/4),
-    # u = 6e-8, so for n = 4096 the bound scales by sqrt(4096 / 256) = 4
+    tol = 1e-13 if precision == "fp64" else (1e-6 if nmax <= 512 else 3e-6)
     for mu in range(2):
-        tol = 1e-13 if precision == "fp64" else 1e-6 * max(1.0, np.sqrt(shape[mu] / 256))
         p.mode_product(mu, 1, x, out)
         torch.cuda.synchronize()
         assert_close(p.to_host(out), tensor.mode_product(U, M[mu], mu), tol,
-                     f"{precision} (4096, 3) mode {mu}")
+                     f"{precision} ({nmax}, 3) mode {mu}")
     p.tucker(1, x, out)
     torch.cuda.synchronize()
-    tol = 1e-13 if precision == "fp64" else 4e-6
-    assert_close(p.to_host(out), tensor.tucker(U, M), tol, f"{precision} (4096, 3) tucker")
+    assert_close(p.to_host(out), tensor.tucker(U, M), tol, f"{precision} ({nmax}, 3) tucker")
     p.destroy()
 
 

@@ -222,3 +222,26 @@ def test_paired_lawson4_matches_concurrent_actions_bitwise(shape, master, monkey
         plan.destroy()
     log(f"paired lawson4 {shape} master={master}: equal {np.array_equal(out['0'], out['1'])}")
     assert np.array_equal(out["0"], out["1"])
+
+
+@pytest.mark.parametrize("shape,master", [((96, 80, 40), False), ((130, 70, 9), True),
+                                          ((256, 256), False), ((200, 33, 17), False)])
+def test_paired_tile_shapes_agree_bitwise(shape, master, monkeypatch):
+    """The paired pass with 64-row tiles (4 waves) and 128-row tiles (8 waves)
+    computes every output from the same 16-deep MFMA steps in the same order:
+    Lawson4 and Lawson2b steps agree bit for bit."""
+    torch = require_gpu()
+    p = ci.scaled(ci.C1, shape) if len(shape) == 3 else ci.scaled(ci.C0, shape)
+    u0 = ci.initial_state(p)
+    out = {}
+    for tile in ("2", "3"):
+        monkeypatch.setenv("CGL_PAIR_TILE", tile)
+        plan = make_plan(p, "split", master=master)
+        u = plan.to_device(u0)
+        assert plan.run("lawson4", u, 3, 3) == 0
+        plan.step("lawson2", u, 2)
+        torch.cuda.synchronize()
+        out[tile] = plan.to_host(u)
+        plan.destroy()
+    log(f"paired tiles {shape} master={master}: equal {np.array_equal(out['2'], out['3'])}")
+    assert np.array_equal(out["2"], out["3"])

@@ -86,7 +86,11 @@ def test_plan_argument_errors_are_reported_before_device_work():
                      ("cgl_status", (None,)), ("cgl_get_operator", (None, 0, 0, None))):
         assert getattr(lib, fn)(*args) == L.EINVAL, fn
     lib.cgl_destroy(None)
-    assert lib.cgl_strerror(L.EBLOWUP).decode().startswith("exact cubic flow")
+    assert lib.cgl_strerror(L.EBLOWUP).decode().startswith("exact cubic or quintic flow")
+    # the RK4 sub-flow and the three-term splitting exclude each other
+    assert lib.cgl_plan(C.byref(h), 3, n3, C.byref(c), 0.01, 0, 2 | 4, None) == L.EINVAL
+    assert lib.cgl_plan(C.byref(h), 3, n3, C.byref(c), 0.01, 0, 8, None) == L.EINVAL
+    assert lib.cgl_step(None, 2, None, 1) == L.EINVAL
 
 
 def test_fd_operator_argument_errors():
@@ -97,3 +101,31 @@ def test_fd_operator_argument_errors():
     assert lib.cgl_fd_operator(2, 0.0, 1.0, 0, C.byref(c), 2, out) == L.EINVAL
     assert lib.cgl_fd_operator(5, 1.0, 0.0, 0, C.byref(c), 2, out) == L.EINVAL
     assert lib.cgl_fd_operator(5, 0.0, 1.0, 3, C.byref(c), 2, out) == L.EINVAL
+
+
+@pytest.mark.parametrize("order", [2, 4])
+@pytest.mark.parametrize("lo,hi", [(0, 0), (0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("n,d", [(9, 1), (64, 2), (33, 3)])
+def test_fd_operator_ex_matches_oracle(order, lo, hi, n, d):
+    """cgl_fd_operator_ex against the oracle's matrices written from the
+    displays of Sections 4.1.1 and 4.2 (orders 2 and 4, every pair of ends)."""
+    from paper_2403_02816_amd import cgl
+    c = ci.PAPER_CUBIC.as_tuple()
+    A = cgl.fd_operator_ex(n, 0.0, 100.0, lo, hi, order, c, d)
+    ref = ops.operator_A_fd(n, 0.0, 100.0, lo, hi, order, c, d)
+    assert np.abs(A - ref).max() <= 4e-15 * np.abs(ref).max()
+    if order == 2 and lo == hi:  # the plain builder's operators are the same
+        assert np.array_equal(A, cgl.fd_operator(n, 0.0, 100.0, lo, c, d))
+
+
+def test_fd_operator_ex_argument_errors():
+    L = _lib()
+    lib = L.lib()
+    c = L.Coeffs(1.0, 0.5, 0.1, -1.0, 1.0, 0.0, 0.0)
+    out = (C.c_double * 200)()
+    assert lib.cgl_fd_operator_ex(5, 0.0, 1.0, 0, 0, 4, C.byref(c), 2, out) == L.EINVAL  # n < 6
+    assert lib.cgl_fd_operator_ex(8, 0.0, 1.0, 0, 0, 3, C.byref(c), 2, out) == L.EINVAL
+    assert lib.cgl_fd_operator_ex(8, 0.0, 1.0, 2, 0, 2, C.byref(c), 2, out) == L.EINVAL
+    assert lib.cgl_fd_operator_ex(8, 1.0, 0.0, 0, 1, 2, C.byref(c), 2, out) == L.EINVAL
+    assert lib.cgl_fd_operator_ex(8, 0.0, 1.0, 0, 1, 2, None, 2, out) == L.EINVAL
+    assert lib.cgl_fd_operator_ex(8, 0.0, 1.0, 0, 1, 2, C.byref(c), 2, None) == L.EINVAL
