@@ -61,7 +61,8 @@ enum {
   CGL_ENONFINITE = -5, /* the state became NaN/Inf (the paper's "x" entries) */
   CGL_EBLOWUP = -6,    /* 1 - 2 a3 |u|^2 t <= 0 in the exact cubic flow (or
                           1 - 4 a4 |u|^4 t <= 0 in the exact quintic flow) */
-  CGL_EGATE = -7       /* a surrogate jump failed its a-posteriori check */
+  CGL_EGATE = -7,      /* a surrogate jump failed its a-posteriori check */
+  CGL_ESCRATCH = -8    /* the grid does not fit cgl_tucker_noalloc's fixed scratch */
 };
 
 /* precision form.  CGL_SPLIT_BF16: complex64 stage tensors, operands split
@@ -155,6 +156,21 @@ int cgl_mode_product(cgl_plan_t p, int mu, int which, const void* in_dev, void* 
  * exp(tau K) (which = CGL_E) or exp(tau K/2) (CGL_H) applied to in.  Same
  * types and errors as cgl_mode_product; in_dev may equal out_dev. */
 int cgl_tucker(cgl_plan_t p, int which, const void* in_dev, void* out_dev);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * Tucker operator as cgl_tucker, out = in x_1 M_1 ... x_d M_d, but its
+ * intermediate tensors live in a fixed 32 MiB device array of the library
+ * (two halves of 16 MiB; one copy per GPU, held until the process ends)
+ * instead of the plan's stage buffers, and it enqueues no tile tuning (it
+ * uses the shape an earlier call of the plan chose, else the default one).
+ * It allocates nothing.  Plain plans only; the grid must fit a half:
+ * N * 8 bytes (split form) or N * 16 bytes (FP64 form) <= 16 MiB, else
+ * CGL_ESCRATCH and nothing is enqueued.  Every call on a GPU shares that GPU's
+ * array: calls that overlap in time on one GPU (other streams, other host
+ * threads) race and give wrong results.  Same argument rules and other errors
+ * as cgl_tucker. */
+int cgl_tucker_noalloc(cgl_plan_t p, int which, const void* in_dev, void* out_dev);
 
 /* Advance u_dev in place by nsteps >= 0 Strang steps (eq. Strang),
  * u <- phi_{tau/2}(exp(tau K) phi_{tau/2}(u)).  phi is the exact cubic flow

@@ -12,7 +12,8 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcgl.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, ENOTREADY, ENONFINITE, EBLOWUP, EGATE = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, ENOMEM, EDEVICE, ENOTREADY, ENONFINITE, EBLOWUP, EGATE, ESCRATCH = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
 FP64, SPLIT_BF16 = 0, 1
 STRANG, LAWSON4, SPLIT4, LAWSON2 = 0, 1, 2, 3
 DIRICHLET, NEUMANN = 0, 1
@@ -43,6 +44,7 @@ SIGNATURES = {
     "cgl_get_operator": (_I, [_P, _I, _I, _DP]),
     "cgl_mode_product": (_I, [_P, _I, _I, _P, _P]),
     "cgl_tucker": (_I, [_P, _I, _P, _P]),
+    "cgl_tucker_noalloc": (_I, [_P, _I, _P, _P]),
     "cgl_step_strang": (_I, [_P, _P, _I64]),
     "cgl_step_lawson4": (_I, [_P, _P, _I64]),
     "cgl_step": (_I, [_P, _I, _P, _I64]),

@@ -73,6 +73,9 @@ struct cgl_plan_s {
   // the auxiliary input of the passes being enqueued is complex128 (the
   // split4 combination of a master-state plan)
   bool aux_f64 = false;
+  // intermediates of the action being enqueued in caller-provided memory
+  // instead of stage[0] / stage[1] (the allocation-free Tucker variant)
+  void* tmp_override[2] = {nullptr, nullptr};
   // [0], [1]: ping-pong intermediates; [2..4]: Lawson4 stage tensors; [5], [6]:
   // ping-pong intermediates of the second branch
   void* stage[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -387,7 +390,7 @@ int action_range(cgl_plan_s* p, int which, ActionCursor& c, const void* aux, voi
   // the split form rotates the axis order by one per pass (back to the
   // original after d passes); the FP64 form contracts in place
   const bool rotated = p->precision == CGL_SPLIT_BF16;
-  void* const* tmp = br == 0 ? &p->stage[0] : &p->stage[5];
+  void* const* tmp = br == 0 ? (p->tmp_override[0] ? p->tmp_override : &p->stage[0]) : &p->stage[5];
   for (int mu = mu0; mu < mu1; ++mu) {
     const bool last = (mu == p->d - 1);
     void* dst = last ? out0 : tmp[mu & 1];
@@ -741,6 +744,7 @@ const char* cgl_strerror(int status) {
     case CGL_ENONFINITE: return "state became non-finite";
     case CGL_EBLOWUP: return "exact cubic or quintic flow left its domain (blow-up)";
     case CGL_EGATE: return "surrogate jump failed its a-posteriori check";
+    case CGL_ESCRATCH: return "grid too large for the allocation-free entry point's scratch";
     default: return "unknown status";
   }
 }
@@ -1241,6 +1245,22 @@ void cgl_destroy(cgl_plan_t p) {
 }
 
 }  // extern "C"
+
+int cgl::tucker_with_scratch(cgl_plan_t p, int which, const void* in_dev, void* out_dev,
+                             void* tmp0, void* tmp1) {
+  if (!p || !in_dev || !out_dev || !tmp0 || !tmp1 || (which != CGL_E && which != CGL_H) ||
+      p->batch > 0)
+    return CGL_EINVAL;
+  if (!ready(p)) return CGL_ENOTREADY;
+  // no tuning here (it times launches): the shape chosen by an earlier call
+  // of the plan, else the default shape
+  p->tmp_override[0] = tmp0;
+  p->tmp_override[1] = tmp1;
+  const int st = action(p, which, in_dev, nullptr, out_dev, nullptr, PRO_NONE, EPI_NONE, false,
+                        false, p->ustream);
+  p->tmp_override[0] = p->tmp_override[1] = nullptr;
+  return st;
+}
 
 int cgl::plan_info(cgl_plan_t p, PlanInfo* out) {
   if (!p || !out) return CGL_EINVAL;

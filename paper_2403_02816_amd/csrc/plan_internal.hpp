@@ -20,4 +20,10 @@ struct PlanInfo {
 
 int plan_info(cgl_plan_t p, PlanInfo* out);
 
+// The Tucker operator of cgl_tucker with its intermediates in tmp0 / tmp1
+// (device memory of at least N complex stage elements each) instead of the
+// plan's stage buffers; enqueues no tuning and allocates nothing.
+int tucker_with_scratch(cgl_plan_t p, int which, const void* in_dev, void* out_dev, void* tmp0,
+                        void* tmp1);
+
 }  // namespace cgl

@@ -122,6 +122,20 @@ static void kernel_parity(std::vector<int64_t> n, int precision, unsigned seed) 
   const double e = rel(out, ref);
   std::printf("  tucker prec=%d d=%d rel=%.2e\n", precision, d, e);
   expect(e < 4 * tol, "tucker parity");
+  // the allocation-free variant (intermediates in the library's fixed
+  // scratch) gives the same bits, out of place and in place
+  if (precision == CGL_FP64) {
+    std::vector<cd> y = U, z(U.size());
+    expect(cgl_tucker_noalloc(p, CGL_E, y.data(), z.data()) == CGL_OK, "tucker noalloc");
+    expect(std::memcmp(z.data(), out.data(), z.size() * sizeof(cd)) == 0, "noalloc == tucker");
+    expect(cgl_tucker_noalloc(p, CGL_E, y.data(), y.data()) == CGL_OK, "tucker noalloc in place");
+    expect(std::memcmp(y.data(), out.data(), y.size() * sizeof(cd)) == 0, "noalloc in place");
+  } else {
+    auto y = cast<float>(U);
+    std::vector<std::complex<float>> z(U.size());
+    expect(cgl_tucker_noalloc(p, CGL_E, y.data(), z.data()) == CGL_OK, "tucker noalloc");
+    expect(back(z) == out, "noalloc == tucker");
+  }
   cgl_destroy(p);
 }
 

@@ -25,6 +25,9 @@ using std::isfinite;
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __shared__ static
+#define __align__(n) alignas(n)
+// a device symbol's host name is its address in the emulation
+#define HIP_SYMBOL(x) (&(x))
 
 struct dim3 {
   unsigned x = 1, y = 1, z = 1;
@@ -314,6 +317,10 @@ inline hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
 inline hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) { *ms = 1.0f; return hipSuccess; }
 struct hipDeviceProp_t { char gcnArchName[256]; };
 inline hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }
+inline hipError_t hipGetSymbolAddress(void** p, const void* sym) {
+  *p = const_cast<void*>(sym);
+  return hipSuccess;
+}
 enum { hipDeviceAttributeMultiprocessorCount = 1 };
 // a small emulated device: few workgroups, so persistent grids loop over tiles
 inline hipError_t hipDeviceGetAttribute(int* v, int, int) { *v = 2; return hipSuccess; }
