@@ -39,10 +39,11 @@ MI355X_PEAK_HBM_GBS = 8000.0
 # run), valid only for the kernel sources whose digest is recorded with them
 # (profiles/split_pass_c1_128_lawson4.md, profiles/split_pass_c2_256_lawson4.md).
 SPLIT_TRAFFIC = {
-    "c1": {"bytes_per_launch": 63295264.0, "sources_sha256_16": "4d24c1d2e3e7704d"},
-    # mean over the six paired launches of a step: (FETCH_SIZE x 2 + WRITE_SIZE) KiB
-    # = (142956 x 2 + 240299) KiB
-    "c2_lawson4": {"bytes_per_launch": 538840064.0, "sources_sha256_16": "4d24c1d2e3e7704d"},
+    # mean over the six paired launches of a step (128-row tiles, the shape the
+    # autotuner picks): (FETCH_SIZE x 2 + WRITE_SIZE) KiB = (15889 x 2 + 30037) KiB
+    "c1": {"bytes_per_launch": 63299584.0, "sources_sha256_16": "4e739ce4f8d7156f"},
+    # (144820 x 2 + 240299) KiB = 1.011 x the algorithmic 536870912 bytes
+    "c2_lawson4": {"bytes_per_launch": 542657835.0, "sources_sha256_16": "4e739ce4f8d7156f"},
 }
 SPLIT_SOURCES = ("kernels_split.hip", "kernels.hpp", "pointwise.hpp", "split_layout.cpp",
                  "split_layout.hpp")
@@ -75,7 +76,7 @@ def parse():
     ap.add_argument("--replays", type=int, default=5,
                     help="graph replays of the K timed steps (median reported)")
     ap.add_argument("--workload", default="c2_lawson4",
-                    choices=["c2_lawson4", "c2_strang", "c1", "c3", "c4"])
+                    choices=["c2_lawson4", "c2_strang", "c1", "c3", "c4", "t4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
@@ -542,6 +543,121 @@ def split_roofline(p, method, times_ms, steps):
             "hbm_gbs_algorithmic": alg_bytes / (launch_ms * 1e-3) / 1e9}
 
 
+# The paper's Table 4 (3-D cubic-quintic CGL, periodic, 128^3 Fourier, if4,
+# T = 5): context for the Fourier path, not the target (MATLAB + FFTW on a
+# laptop, FP64).
+PAPER_TABLE4 = {
+    "source": "Table 4: 3-D cubic-quintic CGL, periodic, 128^3 Fourier pseudospectral, if4 "
+              "(Lawson4), 300 steps, T = 5",
+    "hardware": "Intel Core i7-10750H (6 cores), MATLAB R2022a with FFTW, FP64",
+    "if4_steps": 300, "if4_time_s": 141.7, "grid_points": 128 ** 3,
+    "gp_steps_per_s": 128 ** 3 * 300 / 141.7,
+}
+
+
+def bench_fourier(args):
+    """The Table 4 workload on the Fourier path: every direction periodic, each
+    pass a length-128 transform, the factors and the inverse transform in one
+    read and one write of the tensor (HBM-bound).  Lawson4, tau = 5/300,
+    complex64 state (FP32 transforms), the FP64 form beside it."""
+    import torch
+    import cgl_inputs as ci
+    from oracle import fourier as fo, metrics, steppers
+    p = ci.T4
+    u0 = ci.initial_state(p)
+    K, W, R = args.steps, args.warmup, args.replays
+
+    def timed(precision):
+        from paper_2403_02816_amd import cgl
+        plan = cgl.Plan(p.n, p.coeffs, p.tau, precision=precision)
+        plan.set_problem_operators(p)
+        u = plan.to_device(u0)
+        u_init = u.clone()
+        if W > 0:
+            assert plan.run("lawson4", u, W, W) == 0
+        assert plan.run("lawson4", u, K, K) == 0
+        times = []
+        for _ in range(max(1, R)):
+            u.copy_(u_init)
+            torch.cuda.synchronize()
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            assert plan.run("lawson4", u, K, K) == 0
+            ev1.record()
+            torch.cuda.synchronize()
+            times.append(ev0.elapsed_time(ev1))
+        return plan, u, times
+
+    plan, u, times = timed("split")
+    ms = float(np.median(times))
+    # algorithmic HBM bytes per Lawson4 step (complex64, per point): round 1:
+    # P = H u (3 passes x 16) + Q = H g(u) (2 x 16, last pass reads its input
+    # and P, writes X and Y: 32); round 2: H X (48) + H Y (32 + 24) = 216
+    alg_bytes = 216.0 * p.N
+    achieved = alg_bytes / (ms / K * 1e-3) / 1e9
+    # one-step gate against the oracle on the plan's exported factors
+    ug = plan.to_device(u0.astype(np.complex64).astype(np.complex128))
+    plan.step_lawson4(ug, 1)
+    torch.cuda.synchronize()
+    E = fo.FourierAction([plan.get_periodic_factor(mu, 0) for mu in range(3)])
+    H = fo.FourierAction([plan.get_periodic_factor(mu, 1) for mu in range(3)])
+    nl = steppers.CGLNonlinearity(p.coeffs.as_tuple())
+    ref = steppers.lawson4_step(u0.astype(np.complex64).astype(np.complex128), E, H, p.tau, nl)
+    got = plan.to_host(ug)
+    gate = (metrics.rel_l2(got, ref), metrics.rel_linf(got, ref))
+    split_state = u.clone()
+    plan.destroy()
+    fp64 = None
+    traj = None
+    if not args.no_fp64:
+        plan64, u64, t64 = timed("fp64")
+        ms64 = float(np.median(t64))
+        d = split_state.to(torch.complex128) - u64
+        traj = {"rel_l2": float(torch.linalg.vector_norm(d).item()
+                                / torch.linalg.vector_norm(u64).item()),
+                "rel_linf": float(d.abs().max().item() / u64.abs().max().item())}
+        fp64 = {"value": p.N * K / (ms64 * 1e-3), "ms_per_step": ms64 / K, "replays_ms": t64,
+                "hbm_gbs": 2.0 * alg_bytes / (ms64 / K * 1e-3) / 1e9,
+                "frac": 2.0 * alg_bytes / (ms64 / K * 1e-3) / 1e9 / MI355X_PEAK_HBM_GBS}
+        plan64.destroy()
+    cpu = None
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        Eo, Ho = fo.actions_for(p, p.tau), fo.actions_for(p, 0.5 * p.tau)
+        v = u0.copy()
+        nsteps = 0
+        while nsteps == 0 or (time.perf_counter() - t0 < args.cpu_budget_s and nsteps < 50):
+            v = steppers.lawson4_step(v, Eo, Ho, p.tau, nl)
+            nsteps += 1
+        dt = time.perf_counter() - t0
+        cpu = {"value": p.N * nsteps / dt, "unit": "grid-point-steps/s",
+               "cores": _blas_threads(), "kind": "oracle",
+               "sample": f"{nsteps} literal Lawson4 steps of the full 128^3 grid (numpy FFT, "
+                         f"FP64); {dt:.2f} s"}
+    rec = {
+        "metric": "grid-point-steps/s at rel-L2 <=1e-6 vs FP64 oracle; HBM % of peak",
+        "value": p.N * K / (ms * 1e-3), "unit": "grid-point-steps/s", "n_gpus": 1,
+        "steps": K, "warmup": W, "ms_per_step": ms / K, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 FFT (state c64)",
+        "data": "synthetic (the paper's deterministic necklace-ring datum)",
+        "config": {"workload": f"{p.name}: 3-D cubic-quintic CGL 128^3 periodic (Fourier), "
+                               f"Lawson4, tau={p.tau:.6g}", "grid": list(p.n),
+                   "method": "lawson4", "parallelism": "single-gpu"},
+        "replays_ms": times,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": MI355X_PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": achieved / MI355X_PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "k_pass_fft<float, 128> (12 Fourier passes per step, two actions "
+                               "per round as concurrent branches)",
+                     "alg_bytes_per_step": alg_bytes},
+        "accuracy": {"one_step_rel_l2_vs_fp64_oracle": gate[0],
+                     "one_step_rel_linf_vs_fp64_oracle": gate[1], "gate": 1e-6,
+                     "trajectory_vs_fp64_form": traj, "trajectory_steps": K},
+        "fp64_form": fp64, "cpu_baseline": cpu, "paper_context": PAPER_TABLE4,
+    }
+    print(json.dumps(rec))
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -555,6 +671,8 @@ def main():
         return bench_batched(args)
     if args.workload == "c4":
         return bench_surrogate(args)
+    if args.workload == "t4":
+        return bench_fourier(args)
     p, method = workload(args.workload)
     u0 = ci.initial_state(p)
     K, W, R = args.steps, args.warmup, args.replays

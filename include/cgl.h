@@ -136,6 +136,28 @@ int cgl_fd_operator(int64_t n, double a, double b, int bc, const cgl_coeffs* c, 
 int cgl_fd_operator_ex(int64_t n, double a, double b, int bc_lo, int bc_hi, int order,
                        const cgl_coeffs* c, int d, double* A_out);
 
+/* Make direction mu periodic on (a, b) with the Fourier pseudospectral
+ * discretisation of Section 3.2: n_mu equispaced nodes x_j = a + j (b-a)/n_mu,
+ * A_mu diagonal in the transform's coefficients with entries
+ * (a1 + i b1)(-k^2) + a2/d over the wave numbers k = 2 pi q / (b - a),
+ * q = 0, 1, .., n/2, -n/2 + 1, .., -1.  The plan keeps the diagonals of
+ * exp(tau A_mu) and exp(tau A_mu / 2) (FP64, computed on the host).  When n_mu
+ * is a power of two from 8 to 1024 every pass of direction mu is a Fourier
+ * pass: each fibre is transformed, multiplied by the diagonal and transformed
+ * back in one read and one write of the tensor (FP64 arithmetic in the
+ * CGL_FP64 form, FP32 in the CGL_SPLIT_BF16 form), and the plan's Lawson
+ * rounds run as two actions; otherwise the dense n x n exponential
+ * F^{-1} diag F is applied by the mu-mode product kernels.  cgl_get_operator
+ * returns that dense exponential.  Plain plans only.
+ * Errors: CGL_EINVAL (mu, b <= a, batched plan), CGL_ENOMEM, CGL_EDEVICE. */
+int cgl_set_periodic(cgl_plan_t p, int mu, double a, double b);
+
+/* The diagonal of exp(tau A_mu) (which = CGL_E) or exp(tau A_mu / 2) (CGL_H)
+ * of a periodic direction, n_mu complex128 values in the transform's
+ * coefficient order (out_host: 2 n_mu doubles).  Errors: CGL_EINVAL,
+ * CGL_ENOTREADY (mu is not periodic). */
+int cgl_get_periodic_factor(cgl_plan_t p, int mu, int which, double* out_host);
+
 /* exp(t A) of a host complex128 column-major n x n matrix by the plan's Pade
  * routine (no plan needed).  out: host, 2*n*n doubles.  Errors: CGL_EINVAL. */
 int cgl_expm(int64_t n, const double* A, double t, double* out);

@@ -16,7 +16,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ENOTREADY, ENONFINITE, EBLOWUP, EGATE, ESCRATCH = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)
 FP64, SPLIT_BF16 = 0, 1
 STRANG, LAWSON4, SPLIT4, LAWSON2 = 0, 1, 2, 3
-DIRICHLET, NEUMANN = 0, 1
+DIRICHLET, NEUMANN, PERIODIC = 0, 1, 2
 E, H = 0, 1
 FLAG_FP64_MASTER = 1
 FLAG_RK4_FLOW = 2
@@ -42,6 +42,8 @@ SIGNATURES = {
     "cgl_fd_operator_ex": (_I, [_I64, _D, _D, _I, _I, _I, C.POINTER(Coeffs), _I, _DP]),
     "cgl_expm": (_I, [_I64, _DP, _D, _DP]),
     "cgl_get_operator": (_I, [_P, _I, _I, _DP]),
+    "cgl_set_periodic": (_I, [_P, _I, _D, _D]),
+    "cgl_get_periodic_factor": (_I, [_P, _I, _I, _DP]),
     "cgl_mode_product": (_I, [_P, _I, _I, _P, _P]),
     "cgl_tucker": (_I, [_P, _I, _P, _P]),
     "cgl_tucker_noalloc": (_I, [_P, _I, _P, _P]),

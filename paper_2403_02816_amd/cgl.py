@@ -131,8 +131,23 @@ class Plan:
         self.set_operators_all([fd_operator(nm, a, b, bc, coeffs, self.d) for nm in self.n])
 
     def set_problem_operators(self, p) -> None:
-        """The FD operators of a workload description (order and both ends)."""
+        """The operators of a workload description: FD (order and both ends)
+        or, for periodic boundaries, the Fourier discretisation."""
+        if p.bc == L.PERIODIC:
+            for mu in range(self.d):
+                self.set_periodic(mu, p.a, p.b)
+            return
         self.set_operators_all(problem_operators(p))
+
+    def set_periodic(self, mu: int, a: float, b: float) -> None:
+        """cgl_set_periodic: direction mu periodic on (a, b), Fourier route."""
+        check(L.lib().cgl_set_periodic(self._h, mu, float(a), float(b)), "cgl_set_periodic")
+
+    def get_periodic_factor(self, mu: int, which: int) -> np.ndarray:
+        out = np.zeros(self.n[mu], dtype=np.complex128)
+        check(L.lib().cgl_get_periodic_factor(self._h, mu, which, _dptr(out)),
+              "cgl_get_periodic_factor")
+        return out
 
     def set_operators_all(self, As) -> None:
         """cgl_set_operators_all: every operator at once (parallel exponentials)."""

@@ -76,6 +76,13 @@ struct cgl_plan_s {
   // intermediates of the action being enqueued in caller-provided memory
   // instead of stage[0] / stage[1] (the allocation-free Tucker variant)
   void* tmp_override[2] = {nullptr, nullptr};
+  // periodic directions (Section 3.2): fft[mu] runs the Fourier pass with the
+  // diagonal of exp(tau A_mu) / exp(tau A_mu / 2) (host FP64 copies fac[mu][0/1],
+  // device copies in the pass precision dfac, twiddles dtw)
+  bool fft[3] = {false, false, false};
+  std::vector<double> fac[3][2];
+  void* dfac[3][2] = {};
+  void* dtw[3] = {};
   // [0], [1]: ping-pong intermediates; [2..4]: Lawson4 stage tensors; [5], [6]:
   // ping-pong intermediates of the second branch
   void* stage[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -194,7 +201,31 @@ int pass(cgl_plan_s* p, int mu, int which, const void* in0, const void* aux, voi
   const int n = static_cast<int>(p->n[mu]);
   if (rotated && p->precision != CGL_SPLIT_BF16) return CGL_EINVAL;
   hipError_t e;
-
+  if (p->fft[mu]) {
+    PassFFT f{};
+    f.in0 = in0;
+    f.aux = aux;
+    f.out0 = out0;
+    f.out1 = out1;
+    f.fac = p->dfac[mu][which == CGL_E ? 0 : 1];
+    f.tw = static_cast<const double*>(p->dtw[mu]);
+    f.R = rotated ? 1 : R;
+    f.R_out = rotated ? p->N / n : R;
+    f.F = p->N / n;
+    f.n = n;
+    f.pro = pro;
+    f.epi = epi;
+    // complex128 tensors: every tensor of an FP64 plan, the master state's
+    // ends of a complex64 plan
+    f.fp64 = p->precision == CGL_FP64 ? 1 : 0;
+    f.in_f64 = (f.fp64 || in_f64) ? 1 : 0;
+    f.out_f64 = (f.fp64 || out_f64) ? 1 : 0;
+    f.aux_f64 = (f.fp64 || p->aux_f64) ? 1 : 0;
+    f.nl = p->nl;
+    f.flag = p->dflag;
+    e = launch_pass_fft(f, s);
+    return e == hipSuccess ? CGL_OK : CGL_EDEVICE;
+  }
   if (p->precision == CGL_FP64) {
     PassF64 a{};
     a.in0 = static_cast<const double*>(in0);
@@ -471,6 +502,7 @@ int ensure_tuned_single(cgl_plan_s* p) {
   const char* forced = std::getenv("CGL_SPLIT_TILE");
   const int ncand = p->batch > 0 ? SPLIT_NTILES_BATCHED : SPLIT_NTILES;
   for (int mu = 0; mu < p->d; ++mu) {
+    if (p->fft[mu]) continue;  // the Fourier pass has no tile shape
     for (int pro : {PRO_NONE, PRO_FLOW, PRO_G}) {
       if (pro != PRO_NONE && (mu != 0 || p->batch > 0)) continue;
       if (p->tile[mu][pro] >= 0) continue;
@@ -1031,6 +1063,7 @@ int cgl_set_operators_all(cgl_plan_t p, const double* const* A) {
     } else {
       p->E[k] = E[k];
       p->H[k] = H[k];
+      p->fft[k] = false;
       st = upload_op(p, p->E[k], p->dE[k]);
       if (st == CGL_OK) st = upload_op(p, p->H[k], p->dH[k]);
       p->have_ops[k] = (st == CGL_OK);
@@ -1057,6 +1090,7 @@ int cgl_set_exponentials(cgl_plan_t p, int mu, const double* E, const double* H)
     if (!std::isfinite(E[k]) || !std::isfinite(H[k])) return CGL_EINVAL;
   p->E[mu] = CMat::from_interleaved(n, E);
   p->H[mu] = CMat::from_interleaved(n, H);
+  p->fft[mu] = false;
   int st = upload_op(p, p->E[mu], p->dE[mu]);
   if (st == CGL_OK) st = upload_op(p, p->H[mu], p->dH[mu]);
   p->have_ops[mu] = (st == CGL_OK);
@@ -1076,6 +1110,62 @@ int cgl_set_operators(cgl_plan_t p, int mu, const double* A) {
   E[0].to_interleaved(e.data());
   H[0].to_interleaved(h.data());
   return cgl_set_exponentials(p, mu, e.data(), h.data());
+}
+
+int cgl_set_periodic(cgl_plan_t p, int mu, double a, double b) {
+  if (!p || mu < 0 || mu >= p->d || p->batch > 0 || !(b > a) || !std::isfinite(a) ||
+      !std::isfinite(b))
+    return CGL_EINVAL;
+  const int64_t n = p->n[mu];
+  const cgl_coeffs& c = p->c;
+  fourier_factors(n, a, b, c.a1, c.b1, c.a2, p->d, p->tau, p->fac[mu][0]);
+  fourier_factors(n, a, b, c.a1, c.b1, c.a2, p->d, 0.5 * p->tau, p->fac[mu][1]);
+  // the dense exponentials: returned by cgl_get_operator, and applied by the
+  // mu-mode product kernels when n has no Fourier pass
+  p->E[mu] = circulant_from_factors(n, p->fac[mu][0]);
+  p->H[mu] = circulant_from_factors(n, p->fac[mu][1]);
+  for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.second);
+  p->graphs.clear();
+  if (!fft_length_supported(n)) {
+    p->fft[mu] = false;
+    int st = upload_op(p, p->E[mu], p->dE[mu]);
+    if (st == CGL_OK) st = upload_op(p, p->H[mu], p->dH[mu]);
+    p->have_ops[mu] = (st == CGL_OK);
+    return st;
+  }
+  for (int w = 0; w < 2; ++w) {
+    if (p->dfac[mu][w]) (void)hipFree(p->dfac[mu][w]);
+    p->dfac[mu][w] = nullptr;
+    int st;
+    if (p->precision == CGL_FP64) {
+      st = upload_bytes(p, p->fac[mu][w].data(), p->fac[mu][w].size() * sizeof(double),
+                        &p->dfac[mu][w]);
+    } else {
+      std::vector<float> f(p->fac[mu][w].begin(), p->fac[mu][w].end());
+      st = upload_bytes(p, f.data(), f.size() * sizeof(float), &p->dfac[mu][w]);
+    }
+    if (st != CGL_OK) return st;
+  }
+  std::vector<double> tw;
+  fft_twiddles(n, tw);
+  if (p->dtw[mu]) (void)hipFree(p->dtw[mu]);
+  p->dtw[mu] = nullptr;
+  const int st = upload_bytes(p, tw.data(), tw.size() * sizeof(double), &p->dtw[mu]);
+  if (st != CGL_OK) return st;
+  p->fft[mu] = true;
+  p->paired = false;  // the paired pass is a mu-mode product kernel: Lawson rounds as two actions
+  p->have_ops[mu] = true;
+  return CGL_OK;
+}
+
+int cgl_get_periodic_factor(cgl_plan_t p, int mu, int which, double* out_host) {
+  if (!p || !out_host || mu < 0 || mu >= p->d || (which != CGL_E && which != CGL_H) ||
+      p->batch > 0)
+    return CGL_EINVAL;
+  const std::vector<double>& f = p->fac[mu][which == CGL_E ? 0 : 1];
+  if (f.empty()) return CGL_ENOTREADY;
+  std::memcpy(out_host, f.data(), f.size() * sizeof(double));
+  return CGL_OK;
 }
 
 int cgl_get_operator(cgl_plan_t p, int mu, int which, double* out_host) {
@@ -1227,6 +1317,8 @@ void cgl_destroy(cgl_plan_t p) {
   for (int mu = 0; mu < 3; ++mu) {
     free_op(p->dE[mu]);
     free_op(p->dH[mu]);
+    for (void* q : {p->dfac[mu][0], p->dfac[mu][1], p->dtw[mu]})
+      if (q) (void)hipFree(q);
   }
   invalidate(p);
   for (auto& o : p->bdE) free_op(o);

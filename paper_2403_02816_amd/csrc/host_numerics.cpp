@@ -301,6 +301,64 @@ bool fd_operator(int64_t n, double a, double b, int bc_lo, int bc_hi, int order,
   return true;
 }
 
+void fourier_factors(int64_t n, double a, double b, double a1, double b1, double a2, int d,
+                     double t, std::vector<double>& fac) {
+  const double two_pi = 6.283185307179586476925286766559;
+  fac.assign(static_cast<size_t>(2 * n), 0.0);
+  for (int64_t q = 0; q < n; ++q) {
+    const double wave = two_pi * static_cast<double>(q <= n / 2 ? q : q - n) / (b - a);
+    const double k2 = wave * wave;
+    // t ((a1 + i b1)(-k^2) + a2/d)
+    const double re = t * (-a1 * k2 + a2 / d), im = t * (-b1 * k2);
+    const double m = std::exp(re);
+    fac[2 * q] = m * std::cos(im);
+    fac[2 * q + 1] = m * std::sin(im);
+  }
+}
+
+// angle 2 pi r / n for an integer r reduced modulo n
+static void unit_root(int64_t r, int64_t n, double& c, double& s) {
+  const double two_pi = 6.283185307179586476925286766559;
+  const int64_t q = ((r % n) + n) % n;
+  const double th = two_pi * static_cast<double>(q) / static_cast<double>(n);
+  c = std::cos(th);
+  s = std::sin(th);
+}
+
+CMat circulant_from_factors(int64_t n, const std::vector<double>& fac) {
+  // C[j, l] = c[(j - l) mod n], c[r] = (1/n) sum_q fac_q exp(2 pi i q r / n)
+  std::vector<double> cr(static_cast<size_t>(n)), ci(static_cast<size_t>(n));
+  for (int64_t r = 0; r < n; ++r) {
+    double sr = 0.0, si = 0.0;
+    for (int64_t q = 0; q < n; ++q) {
+      double co, so;
+      unit_root(q * r, n, co, so);
+      sr += fac[2 * q] * co - fac[2 * q + 1] * so;
+      si += fac[2 * q] * so + fac[2 * q + 1] * co;
+    }
+    cr[r] = sr / static_cast<double>(n);
+    ci[r] = si / static_cast<double>(n);
+  }
+  CMat C(n);
+  for (int64_t l = 0; l < n; ++l)
+    for (int64_t j = 0; j < n; ++j) {
+      const int64_t r = ((j - l) % n + n) % n;
+      C.re[j + n * l] = cr[r];
+      C.im[j + n * l] = ci[r];
+    }
+  return C;
+}
+
+void fft_twiddles(int64_t n, std::vector<double>& tw) {
+  tw.assign(static_cast<size_t>(2 * n), 0.0);
+  for (int64_t q = 0; q < n; ++q) {
+    double c, s;
+    unit_root(q, n, c, s);
+    tw[2 * q] = c;
+    tw[2 * q + 1] = -s;
+  }
+}
+
 uint16_t f32_to_bf16_rne(float x) {
   uint32_t u;
   std::memcpy(&u, &x, 4);

@@ -38,6 +38,18 @@ CMat fd_operator_2nd(int64_t n, double a, double b, int bc, double a1, double b1
 bool fd_operator(int64_t n, double a, double b, int bc_lo, int bc_hi, int order, double a1,
                  double b1, double a2, int d, CMat& A);
 
+// Periodic direction on (a, b) with n equispaced nodes (Section 3.2): the
+// diagonal of exp(t A_mu), A_mu = (a1 + i b1)(-k^2) + a2/d over the wave
+// numbers k = 2 pi q / (b - a), q = 0, 1, .., n/2, -n/2 + 1, .., -1 in the
+// transform's coefficient order; interleaved complex128 (2n doubles).
+void fourier_factors(int64_t n, double a, double b, double a1, double b1, double a2, int d,
+                     double t, std::vector<double>& fac);
+// The same exponential as a dense circulant matrix on grid values,
+// F^{-1} diag(fac) F.
+CMat circulant_from_factors(int64_t n, const std::vector<double>& fac);
+// exp(-2 pi i q / n), q < n, interleaved complex128.
+void fft_twiddles(int64_t n, std::vector<double>& tw);
+
 // Round-to-nearest-even float -> bf16 bits and back.
 uint16_t f32_to_bf16_rne(float x);
 float bf16_to_f32(uint16_t h);

@@ -157,6 +157,32 @@ struct PassBatch {
   unsigned* flag;
 };
 
+// ---- Fourier pass of a periodic direction (kernels_fft.hip): every fibre
+// goes through F^{-1} diag(fac) F (lengths n = 2^k, 8 <= n <= 1024), with the
+// same prologue / epilogue codes and layouts as the mu-mode products.
+struct PassFFT {
+  const void* in0;
+  const void* aux;
+  void* out0;
+  void* out1;
+  const void* fac;   // n complex factors: double2 (fp64 passes) or float2
+  const double* tw;  // n complex128 twiddles exp(-2 pi i q / n)
+  int64_t R;         // input: fibre stride
+  int64_t R_out;     // output: fibre stride
+  int64_t F;
+  int n;
+  int pro;
+  int epi;
+  int in_f64;
+  int out_f64;
+  int aux_f64;
+  int fp64;          // arithmetic and stage tensors in FP64 (else FP32 / complex64)
+  NlParams nl;
+  unsigned* flag;
+};
+bool fft_length_supported(int64_t n);
+hipError_t launch_pass_fft(const PassFFT& a, hipStream_t s);
+
 // launches a persistent grid of at most nwg workgroups over b.tiles
 hipError_t launch_pass_split_batched(const PassBatch& b, int nwg, hipStream_t s);
 // the paired pass (see launch_pass_split_pair) over every instance: b.tile

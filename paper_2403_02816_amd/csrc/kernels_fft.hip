@@ -1,0 +1,273 @@
+// Fourier pass: the exponential of one periodic direction (Section 3.2),
+// applied along every fibre as F^{-1} diag(e) F with a length-n discrete
+// Fourier transform (n a power of two, 8 <= n <= 1024), the pointwise product
+// with the direction's factors e_k = exp(t A_mu)_kk and the inverse
+// transform.  One read and one write of the tensor per pass (HBM-bound), the
+// same pass interface as the mu-mode product kernels: the stepper's prologue
+// on the staged input, its epilogue before the store, contiguous or strided
+// fibres, rotated or in-place output.
+//
+// A workgroup stages FPW whole fibres in LDS (each as an N1 x N2 array with
+// padded rows, element j = N2 j1 + j2 at row j1, column j2, N = N1 N2,
+// N1 >= N2) and runs the four-step transform on them:
+//   forward:  for each column j2, a length-N1 DFT over j1, times w_N^{j2 k1};
+//             for each row k1, a length-N2 DFT over j2 -> X[k1 + N1 k2];
+//   product:  X[k] *= e_k;
+//   inverse:  for each row k1, the inverse length-N2 DFT over k2, times
+//             w_N^{-j2 k1}; for each column j2, the inverse length-N1 DFT
+//             over k1, times 1/N -> x[N2 j1 + j2],
+// w_N = exp(-2 pi i / N).  The row step's thread keeps the row from the end
+// of the forward transform to the start of the inverse one, so a fibre goes
+// through LDS three times.  The short DFTs run in registers (iterative
+// radix-2, twiddles from an LDS copy of the table exp(-2 pi i k / N)).
+// Arithmetic in T: double for complex128 passes, float for complex64 ones.
+#include "kernels.hpp"
+#include "pointwise.hpp"
+
+namespace cgl {
+
+namespace {
+
+template <typename T>
+struct cx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// a times the conjugate of b
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+  return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+constexpr int bitrev(int v, int bits) {
+  int r = 0;
+  for (int b = 0; b < bits; ++b) r |= ((v >> b) & 1) << (bits - 1 - b);
+  return r;
+}
+
+// Length-M DFT of x in natural order (M a power of two <= 32), forward
+// (sum_j x_j w_M^{jk}) or inverse (sum_k x_k w_M^{-jk}, unscaled).  tw holds
+// w_N^q, q < N, and w_M = w_N^S with S = N / M.
+template <int M, int S, bool INV, typename T>
+__device__ __forceinline__ void dft(cx<T> (&x)[M], const cx<T>* tw) {
+  constexpr int B = ilog2(M);
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    const int j = bitrev(i, B);
+    if (j > i) {
+      const cx<T> t = x[i];
+      x[i] = x[j];
+      x[j] = t;
+    }
+  }
+#pragma unroll
+  for (int len = 2; len <= M; len <<= 1) {
+#pragma unroll
+    for (int i = 0; i < M; i += len)
+#pragma unroll
+      for (int j = 0; j < len / 2; ++j) {
+        const cx<T> w = tw[j * (M / len) * S];
+        const cx<T> v = INV ? cmulc(x[i + j + len / 2], w) : cmul(x[i + j + len / 2], w);
+        const cx<T> u = x[i + j];
+        x[i + j] = {u.re + v.re, u.im + v.im};
+        x[i + j + len / 2] = {u.re - v.re, u.im - v.im};
+      }
+  }
+}
+
+template <int N>
+struct FftGeom {
+  static constexpr int B = ilog2(N);
+  static constexpr int N1 = 1 << ((B + 1) / 2);  // rows
+  static constexpr int N2 = N / N1;              // columns (N2 <= N1)
+  static constexpr int P = N2 + 1;               // padded row pitch (complex)
+  static_assert((1 << B) == N && N >= 8 && N <= 1024, "power-of-two lengths 8 .. 1024");
+};
+
+template <typename T, int N>
+struct FftTile {
+  static constexpr int FPW_MAX = 256 / FftGeom<N>::N1;
+  static constexpr int FPW_LDS = (sizeof(T) == 8 ? 2048 : 4096) / N;
+  static constexpr int FPW = FPW_MAX < FPW_LDS ? FPW_MAX : (FPW_LDS > 0 ? FPW_LDS : 1);
+};
+
+__device__ __forceinline__ int64_t fibre_base(int64_t f, int64_t R, int n) {
+  return (R == 1) ? f * (int64_t)n : (f % R) + (f / R) * R * (int64_t)n;
+}
+
+template <typename T>
+__device__ __forceinline__ cd load_in(const void* p, int64_t off, bool f64) {
+  if (f64) {
+    const double2 v = reinterpret_cast<const double2*>(p)[off];
+    return {v.x, v.y};
+  }
+  const float2 v = reinterpret_cast<const float2*>(p)[off];
+  return {static_cast<double>(v.x), static_cast<double>(v.y)};
+}
+
+__device__ __forceinline__ void store_out(void* p, int64_t off, bool f64, cd v) {
+  if (f64)
+    reinterpret_cast<double2*>(p)[off] = double2{v.re, v.im};
+  else
+    reinterpret_cast<float2*>(p)[off] = float2{static_cast<float>(v.re), static_cast<float>(v.im)};
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_pass_fft(PassFFT a) {
+  using G = FftGeom<N>;
+  constexpr int N1 = G::N1, N2 = G::N2, P = G::P;
+  constexpr int FPW = FftTile<T, N>::FPW;
+  constexpr int FS = N1 * P;  // LDS stride between fibres (complex)
+  __shared__ cx<T> tile[FPW * FS];
+  __shared__ cx<T> tw[N];
+  const int tid = threadIdx.x;
+  const int64_t f0 = static_cast<int64_t>(blockIdx.x) * FPW;
+  const bool in64 = a.in_f64 != 0, out64 = a.out_f64 != 0;
+  unsigned flag = 0;
+
+  for (int q = tid; q < N; q += 256) {
+    const double2 w = reinterpret_cast<const double2*>(a.tw)[q];
+    tw[q] = {static_cast<T>(w.x), static_cast<T>(w.y)};
+  }
+  // stage the fibres (consecutive threads take consecutive elements of a
+  // contiguous fibre, or consecutive fibres of one index when strided), with
+  // the prologue applied
+  for (int e = tid; e < FPW * N; e += 256) {
+    const int fl = a.R == 1 ? e / N : e % FPW;
+    const int k = a.R == 1 ? e % N : e / FPW;
+    const int64_t f = f0 + fl;
+    cd v = {0.0, 0.0};
+    if (f < a.F) {
+      v = load_in<T>(a.in0, fibre_base(f, a.R, N) + a.R * static_cast<int64_t>(k), in64);
+      if (a.pro == PRO_FLOW)
+        v = flow_in(v, a.nl.tf, a.nl, flag);
+      else if (a.pro == PRO_G)
+        v = g_cgl(v, a.nl);
+    }
+    tile[fl * FS + (k / N2) * P + (k % N2)] = {static_cast<T>(v.re), static_cast<T>(v.im)};
+  }
+  __syncthreads();
+  // forward, columns: length-N1 DFTs over j1, twiddle w_N^{j2 k1}
+  if (tid < FPW * N2) {
+    const int fl = tid / N2, j2 = tid % N2;
+    cx<T>* t = tile + fl * FS + j2;
+    cx<T> x[N1];
+#pragma unroll
+    for (int j1 = 0; j1 < N1; ++j1) x[j1] = t[j1 * P];
+    dft<N1, N2, false>(x, tw);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) t[k1 * P] = cmul(x[k1], tw[(j2 * k1) & (N - 1)]);
+  }
+  __syncthreads();
+  // rows: length-N2 DFT over j2 (X[k1 + N1 k2]), the factors, the inverse
+  // length-N2 DFT over k2 and the twiddle w_N^{-j2 k1}
+  if (tid < FPW * N1) {
+    const int fl = tid / N1, k1 = tid % N1;
+    cx<T>* t = tile + fl * FS + k1 * P;
+    const cx<T>* fac = reinterpret_cast<const cx<T>*>(a.fac);
+    cx<T> y[N2];
+#pragma unroll
+    for (int j2 = 0; j2 < N2; ++j2) y[j2] = t[j2];
+    dft<N2, N1, false>(y, tw);
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) y[k2] = cmul(y[k2], fac[k1 + N1 * k2]);
+    dft<N2, N1, true>(y, tw);
+#pragma unroll
+    for (int j2 = 0; j2 < N2; ++j2) t[j2] = cmulc(y[j2], tw[(j2 * k1) & (N - 1)]);
+  }
+  __syncthreads();
+  // inverse, columns: length-N1 inverse DFTs over k1, scaled by 1/N
+  if (tid < FPW * N2) {
+    const int fl = tid / N2, j2 = tid % N2;
+    cx<T>* t = tile + fl * FS + j2;
+    cx<T> x[N1];
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) x[k1] = t[k1 * P];
+    dft<N1, N2, true>(x, tw);
+    const T s = static_cast<T>(1.0 / N);
+#pragma unroll
+    for (int j1 = 0; j1 < N1; ++j1) t[j1 * P] = {x[j1].re * s, x[j1].im * s};
+  }
+  __syncthreads();
+  // store with the epilogue (consecutive threads take consecutive output
+  // elements: along the fibre when the output stride is 1, across fibres
+  // otherwise)
+  for (int e = tid; e < FPW * N; e += 256) {
+    const int fl = a.R_out == 1 ? e / N : e % FPW;
+    const int m = a.R_out == 1 ? e % N : e / FPW;
+    const int64_t f = f0 + fl;
+    if (f >= a.F) continue;
+    const int64_t off = fibre_base(f, a.R_out, N) + a.R_out * static_cast<int64_t>(m);
+    const cx<T> c = tile[fl * FS + (m / N2) * P + (m % N2)];
+    const cd y = {static_cast<double>(c.re), static_cast<double>(c.im)};
+    if (a.epi == EPI_NONE) {
+      store_out(a.out0, off, out64, y);
+    } else if (a.epi == EPI_FLOW || a.epi == EPI_MID) {
+      const cd z = a.epi == EPI_FLOW ? flow_out(y, a.nl.tf, a.nl, flag)
+                                     : flow_mid(y, a.nl.tf, a.nl, flag);
+      if (!finite2(z)) flag |= FLAG_NONFINITE;
+      store_out(a.out0, off, out64, z);
+    } else {
+      const cd x = load_in<T>(a.aux, off, a.aux_f64 != 0);
+      if (a.epi == EPI_L4_R1) {  // y = Q, x = P
+        cd X, Y;
+        lawson_r1(x, y, a.nl, X, Y);
+        store_out(a.out0, off, out64, X);
+        store_out(a.out1, off, out64, Y);
+      } else {
+        const cd z = a.epi == EPI_L4_R2 ? lawson_r2(x, y, a.nl)
+                     : a.epi == EPI_RICH ? richardson(y, x, a.nl, flag)
+                                         : lawson2(x, y, a.nl, 0.5 * a.nl.tau);
+        if (!finite2(z)) flag |= FLAG_NONFINITE;
+        store_out(a.out0, off, out64, z);
+      }
+    }
+  }
+  if (flag) atomicOr(a.flag, flag);
+}
+
+template <typename T, int N>
+hipError_t launch_n(const PassFFT& a, hipStream_t s) {
+  constexpr int FPW = FftTile<T, N>::FPW;
+  const int64_t G = (a.F + FPW - 1) / FPW;
+  if (G > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_pass_fft<T, N>), dim3(static_cast<unsigned>(G)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_t(const PassFFT& a, hipStream_t s) {
+  switch (a.n) {
+    case 8: return launch_n<T, 8>(a, s);
+    case 16: return launch_n<T, 16>(a, s);
+    case 32: return launch_n<T, 32>(a, s);
+    case 64: return launch_n<T, 64>(a, s);
+    case 128: return launch_n<T, 128>(a, s);
+    case 256: return launch_n<T, 256>(a, s);
+    case 512: return launch_n<T, 512>(a, s);
+    case 1024: return launch_n<T, 1024>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+bool fft_length_supported(int64_t n) { return n >= 8 && n <= 1024 && (n & (n - 1)) == 0; }
+
+hipError_t launch_pass_fft(const PassFFT& a, hipStream_t s) {
+  if (!fft_length_supported(a.n) || a.F <= 0 || a.R < 1 || a.R_out < 1) return hipErrorInvalidValue;
+  if (!a.in0 || !a.out0 || !a.fac || !a.tw || !a.flag) return hipErrorInvalidValue;
+  if ((a.epi == EPI_L4_R1 || a.epi == EPI_L4_R2 || a.epi == EPI_RICH || a.epi == EPI_L2) && !a.aux)
+    return hipErrorInvalidValue;
+  if (a.epi == EPI_L4_R1 && !a.out1) return hipErrorInvalidValue;
+  if (a.epi < EPI_NONE || a.epi > EPI_L2) return hipErrorInvalidValue;
+  if (a.pro != PRO_NONE && a.pro != PRO_FLOW && a.pro != PRO_G) return hipErrorInvalidValue;
+  return a.fp64 ? launch_t<double>(a, s) : launch_t<float>(a, s);
+}
+
+}  // namespace cgl

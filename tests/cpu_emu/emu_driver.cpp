@@ -139,6 +139,50 @@ static void kernel_parity(std::vector<int64_t> n, int precision, unsigned seed) 
   cgl_destroy(p);
 }
 
+// Periodic directions (Fourier pass for power-of-two n, the dense circulant
+// exponential otherwise): the Tucker operator against naive mode products
+// with the plan's dense exponentials, then every stepper.
+static void fourier_parity(std::vector<int64_t> n, int precision, unsigned seed) {
+  const int d = static_cast<int>(n.size());
+  int64_t N = 1;
+  for (auto v : n) N *= v;
+  cgl_coeffs c{1.0, 0.6, -0.2, -1.0, 0.8, -0.1, -0.3};
+  cgl_plan_t p = nullptr;
+  expect(cgl_plan(&p, d, n.data(), &c, 0.01, precision, 0, nullptr) == CGL_OK, "plan");
+  std::vector<std::vector<cd>> Es(d);
+  for (int mu = 0; mu < d; ++mu) {
+    expect(cgl_set_periodic(p, mu, -3.0, 4.0) == CGL_OK, "set_periodic");
+    Es[mu].resize(n[mu] * n[mu]);
+    expect(cgl_get_operator(p, mu, CGL_E, reinterpret_cast<double*>(Es[mu].data())) == CGL_OK, "get");
+  }
+  auto U = rnd(N, seed);
+  std::vector<cd> ref = U;
+  for (int mu = 0; mu < d; ++mu) ref = mode_ref(ref, n, mu, Es[mu]);
+  std::vector<cd> out;
+  if (precision == CGL_FP64) {
+    std::vector<cd> y(U.size());
+    expect(cgl_tucker(p, CGL_E, U.data(), y.data()) == CGL_OK, "tucker");
+    out = y;
+  } else {
+    auto x = cast<float>(U);
+    std::vector<std::complex<float>> y(U.size());
+    expect(cgl_tucker(p, CGL_E, x.data(), y.data()) == CGL_OK, "tucker");
+    out = back(y);
+  }
+  const double e = rel(out, ref), tol = precision == CGL_FP64 ? 1e-12 : 2e-6;
+  std::printf("  fourier tucker prec=%d d=%d rel=%.2e\n", precision, d, e);
+  expect(e < tol, "fourier tucker parity");
+  auto V = rnd(N, seed + 1, 0.3);
+  std::vector<cd> v64 = V;
+  std::vector<std::complex<float>> v32 = cast<float>(V);
+  void* u = precision == CGL_FP64 ? static_cast<void*>(v64.data()) : static_cast<void*>(v32.data());
+  for (int m : {CGL_STRANG, CGL_LAWSON4, CGL_SPLIT4, CGL_LAWSON2})
+    expect(cgl_step(p, m, u, 1) == CGL_OK, "fourier step");
+  expect(cgl_run(p, CGL_LAWSON4, u, 2, 1) == CGL_OK, "fourier run");
+  expect(cgl_status(p) == CGL_OK, "fourier status");
+  cgl_destroy(p);
+}
+
 static void steppers(std::vector<int64_t> n, int precision, unsigned flags, cgl_coeffs c,
                      double a, double b, int bc) {
   const int d = static_cast<int>(n.size());
@@ -528,6 +572,11 @@ int main(int argc, char** argv) {
     steppers({7, 6, 5}, CGL_SPLIT_BF16, CGL_FLAG_FP64_MASTER, cq, -15, 15, CGL_NEUMANN);
     steppers({9}, CGL_SPLIT_BF16, CGL_FLAG_FP64_MASTER, cub, -10, 10, CGL_DIRICHLET);
     steppers({12, 10, 6}, CGL_FP64, CGL_FLAG_THREE_TERM, cq, -15, 15, CGL_NEUMANN);
+    for (int prec : {CGL_FP64, CGL_SPLIT_BF16}) {
+      fourier_parity({16, 8, 32}, prec, 21);   // every direction a Fourier pass (strided in FP64)
+      fourier_parity({64, 12}, prec, 22);      // n = 12: the dense circulant on MFMA
+      fourier_parity({8}, prec, 23);
+    }
     steppers({16, 12}, CGL_SPLIT_BF16, CGL_FLAG_THREE_TERM, cq, -10, 10, CGL_DIRICHLET);
     batched_vs_single(CGL_FP64);
     batched_vs_single(CGL_SPLIT_BF16);
