@@ -287,8 +287,12 @@ int cgl_get_instance_operator(cgl_plan_t p, int j, int mu, int which, double* ou
  *         (a1, b1, a2, a3, b3) of eq. cqCGL standardised by the caller)
  *   h0  = silu(conv_in x)                      7 -> 48 channels
  *   h_k = h_{k-1} + silu(conv_k h_{k-1})        48 -> 48, k = 1..4
- *   y   = (Re u, Im u) + conv_out h_4           48 -> 2
- * with 3x3 kernels, zero padding, silu(a) = a / (1 + e^{-a}).  Parameters are
+ *   y   = (Re b, Im b) + s conv_out h_4         48 -> 2
+ * where the base b is u itself or a base state the caller gives (a cheap
+ * propagation of u over the jump: the network then learns the correction to
+ * it) and s is the output scale (1 unless set: the typical size of the
+ * correction, so that the layers work on unit-size values), with 3x3
+ * kernels, zero padding, silu(a) = a / (1 + e^{-a}).  Parameters are
  * FP32 on the device, packed as W_in, b_in, W_1, b_1, ..., W_out, b_out with
  * W[co][ci][ky][kx] (ky along index 2, kx along index 1); the convolutions
  * run on bf16 MFMA with the weights and activations rounded to bf16 and FP32
@@ -318,38 +322,57 @@ int cgl_sur_set_params(cgl_sur_t s, const float* params_host);
 enum { CGL_SUR_LOSS_MSE = 0, CGL_SUR_LOSS_REL = 1 };
 int cgl_sur_set_loss(cgl_sur_t s, int kind);
 
+/* Output scale s of the network (finite, > 0; 1 after cgl_sur_create).
+ * CGL_EINVAL otherwise. */
+int cgl_sur_set_output_scale(cgl_sur_t s, float scale);
+
 /* Copy the current parameters to the host (synchronous). */
 int cgl_sur_get_params(cgl_sur_t s, float* params_host);
 
 /* out = network(u) for batch samples (1 <= batch <= max_batch); cstd_dev is a
- * device float array [batch][5].  out may equal u.  CGL_ENOTREADY before
+ * device float array [batch][5]; base_dev (complex64 [batch][P]) gives the
+ * base states, NULL takes u.  out may equal u or base.  CGL_ENOTREADY before
  * cgl_sur_set_params. */
 int cgl_sur_forward(cgl_sur_t s, int batch, const void* u_dev, const float* cstd_dev,
-                    void* out_dev);
+                    const void* base_dev, void* out_dev);
 
 /* Training batch: sample s is input src[i_s] with coefficients cstd[i_s]
  * (device [*][5]) and target src[i_s + target_offset], where i_s = idx[s]
- * (device int32 array) or s when idx_dev is NULL.  cgl_sur_grad writes the
+ * (device int32 array) or s when idx_dev is NULL, and base state
+ * base[i_s] (complex64, indexed like src) or src[i_s] when base_dev is NULL.
+ * cgl_sur_grad writes the
  * loss gradient to grad_host[count] and the loss to *loss_host (if not NULL)
  * without changing the parameters (synchronous).  cgl_sur_train_step takes
  * one Adam step with learning rate lr (asynchronous); the mean loss of the
  * steps since the last call is returned by cgl_sur_take_loss (synchronous). */
 int cgl_sur_grad(cgl_sur_t s, int batch, const void* src_dev, const float* cstd_dev,
-                 const int32_t* idx_dev, int64_t target_offset, float* grad_host,
-                 double* loss_host);
+                 const int32_t* idx_dev, int64_t target_offset, const void* base_dev,
+                 float* grad_host, double* loss_host);
 int cgl_sur_train_step(cgl_sur_t s, int batch, const void* src_dev, const float* cstd_dev,
-                       const int32_t* idx_dev, int64_t target_offset, float lr);
+                       const int32_t* idx_dev, int64_t target_offset, const void* base_dev,
+                       float lr);
 int cgl_sur_take_loss(cgl_sur_t s, double* mean_loss);
 
 /* Synchronise and free the network.  NULL is accepted. */
 void cgl_sur_destroy(cgl_sur_t s);
 
+/* Bases of a gated run's jumps: the state itself; the exact linear flow
+ * e^{M tau K} u (the change of variables behind the Lawson schemes,
+ * Section 2.2), as the E exponential of a coarse plan whose step is M tau;
+ * one Strang step (eq. Strang) of the coarse plan. */
+enum { CGL_SUR_BASE_INPUT = 0, CGL_SUR_BASE_LINEAR = 1, CGL_SUR_BASE_STRANG = 2 };
+
 /* Gated run of njumps jumps of steps_per_jump Lawson4 steps each on the
  * complex64 state u_dev of plan p (a 2-D CGL_SPLIT_BF16 plan without
  * CGL_FLAG_FP64_MASTER on the network's grid), with standardised
- * coefficients cstd[5].  Jumps j = check_every, 2 check_every, ... and the
- * last one are checked: the plain stepper advances the state the jump
- * started from by steps_per_jump steps; if the relative L2 distance of the
+ * coefficients cstd[5].  A jump is network(u) with the base given by base
+ * (CGL_SUR_BASE_*): for LINEAR and STRANG, coarse is a plan of the same
+ * shape, precision and stream as p holding the same problem with step
+ * steps_per_jump * tau (the caller builds it; the run only applies it);
+ * coarse may be NULL for CGL_SUR_BASE_INPUT.  Jumps j = check_every,
+ * 2 check_every, ... and the last one are checked: the plain stepper
+ * advances the state the jump started from by steps_per_jump steps; if the
+ * relative L2 distance of the
  * jump's result from it is <= tol, the jumps since the previous check are
  * accepted and the run continues from the plain result; otherwise they are
  * rejected, the state is rolled back to the last verified state and the
@@ -359,7 +382,7 @@ void cgl_sur_destroy(cgl_sur_t s);
  * synchronises at every check. */
 int cgl_run_surrogate(cgl_plan_t p, cgl_sur_t s, void* u_dev, const double* cstd,
                       int64_t njumps, int64_t steps_per_jump, int64_t check_every, double tol,
-                      int64_t* stats);
+                      cgl_plan_t coarse, int base, int64_t* stats);
 
 #ifdef __cplusplus
 }

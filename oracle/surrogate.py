@@ -9,7 +9,12 @@ Network (C = 48 channels, 3x3 kernels, zero padding, pixel p = i1 + n1 i2):
     h0  = silu(conv_in(x))                                        (7 -> C)
     h_k = h_{k-1} + silu(conv_k(h_{k-1})),  k = 1..4               (C -> C)
     d   = conv_out(h_4)                                           (C -> 2)
-    y   = (Re u, Im u) + d
+    y   = (Re b, Im b) + s d,  b = u, or a base state the caller gives; s the
+          output scale (1 unless given)
+The base b is where the network's correction starts from: the input itself,
+or a cheap propagation of it (the exact linear flow e^{M tau K} u of the
+Lawson change of variables, Section 2.2, or one Strang step of size M tau);
+it does not depend on the parameters, so the gradients do not involve it.
 silu(a) = a sigmoid(a).  Loss "mse": mean over samples, channels and pixels
 of (y - target)^2; loss "rel": mean over samples of the squared relative L2
 error sum (y - target)^2 / sum target^2 (sums over channels and pixels).  Parameters are packed in the order W_in, b_in, W_1, b_1,
@@ -103,8 +108,10 @@ def silu_grad(a):
     return s * (1.0 + a * (1.0 - s))
 
 
-def forward(params: np.ndarray, x: np.ndarray, C: int = 48, blocks: int = 4):
-    """x: (S, 7, n2, n1).  Returns y (S, 2, n2, n1) and the cache for backward."""
+def forward(params: np.ndarray, x: np.ndarray, C: int = 48, blocks: int = 4, base=None,
+            oscale: float = 1.0):
+    """x: (S, 7, n2, n1); base: None (the input's planes 0, 1) or (S, 2, n2, n1).
+    Returns y (S, 2, n2, n1) and the cache for backward."""
     layers = unpack(params, C, blocks)
     cache: Dict[str, list] = {"a": [], "h": [x]}
     W, b = layers[0]
@@ -120,7 +127,7 @@ def forward(params: np.ndarray, x: np.ndarray, C: int = 48, blocks: int = 4):
         cache["h"].append(h)
     W, b = layers[-1]
     d = conv3x3(h, W, b)
-    y = x[:, 0:2] + d
+    y = (x[:, 0:2] if base is None else base) + oscale * d
     return y, cache
 
 
@@ -141,11 +148,12 @@ def loss_grad(y: np.ndarray, target: np.ndarray, kind: str = "mse") -> np.ndarra
 
 
 def backward(params: np.ndarray, cache, y: np.ndarray, target: np.ndarray, C: int = 48,
-             blocks: int = 4, kind: str = "mse") -> np.ndarray:
-    """Gradient of loss(y, target, kind) with respect to the packed parameters."""
+             blocks: int = 4, kind: str = "mse", oscale: float = 1.0) -> np.ndarray:
+    """Gradient of loss(y, target, kind) with respect to the packed parameters
+    (y = base + oscale d: the output conv receives oscale dloss/dy)."""
     layers = unpack(params, C, blocks)
     grads = [None] * len(layers)
-    dy = loss_grad(y, target, kind)
+    dy = oscale * loss_grad(y, target, kind)
     hs, As = cache["h"], cache["a"]
     # output conv: d = conv_out(h_last)
     dh, dW, db = conv3x3_grads(hs[-1], layers[-1][0], dy)

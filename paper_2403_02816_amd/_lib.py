@@ -22,6 +22,7 @@ FLAG_FP64_MASTER = 1
 FLAG_RK4_FLOW = 2
 FLAG_THREE_TERM = 4
 SUR_LOSS_MSE, SUR_LOSS_REL = 0, 1
+SUR_BASE_INPUT, SUR_BASE_LINEAR, SUR_BASE_STRANG = 0, 1, 2
 
 
 class Coeffs(C.Structure):
@@ -68,12 +69,13 @@ SIGNATURES = {
     "cgl_sur_set_params": (_I, [_P, C.POINTER(C.c_float)]),
     "cgl_sur_get_params": (_I, [_P, C.POINTER(C.c_float)]),
     "cgl_sur_set_loss": (_I, [_P, _I]),
-    "cgl_sur_forward": (_I, [_P, _I, _P, _P, _P]),
-    "cgl_sur_grad": (_I, [_P, _I, _P, _P, _P, _I64, C.POINTER(C.c_float), _DP]),
-    "cgl_sur_train_step": (_I, [_P, _I, _P, _P, _P, _I64, C.c_float]),
+    "cgl_sur_forward": (_I, [_P, _I, _P, _P, _P, _P]),
+    "cgl_sur_set_output_scale": (_I, [_P, C.c_float]),
+    "cgl_sur_grad": (_I, [_P, _I, _P, _P, _P, _I64, _P, C.POINTER(C.c_float), _DP]),
+    "cgl_sur_train_step": (_I, [_P, _I, _P, _P, _P, _I64, _P, C.c_float]),
     "cgl_sur_take_loss": (_I, [_P, _DP]),
     "cgl_sur_destroy": (None, [_P]),
-    "cgl_run_surrogate": (_I, [_P, _P, _P, _DP, _I64, _I64, _I64, _D, C.POINTER(_I64)]),
+    "cgl_run_surrogate": (_I, [_P, _P, _P, _DP, _I64, _I64, _I64, _D, _P, _I, C.POINTER(_I64)]),
 }
 
 _lib = None

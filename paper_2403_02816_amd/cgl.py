@@ -322,25 +322,33 @@ class Surrogate:
         check(L.lib().cgl_sur_set_loss(self._h, {"mse": L.SUR_LOSS_MSE, "rel": L.SUR_LOSS_REL}[kind]),
               "cgl_sur_set_loss")
 
+    def set_output_scale(self, scale: float) -> None:
+        """y = base + scale * (network correction)."""
+        check(L.lib().cgl_sur_set_output_scale(self._h, float(scale)), "cgl_sur_set_output_scale")
+
     def get_params(self) -> np.ndarray:
         out = np.zeros(self.count, dtype=np.float32)
         check(L.lib().cgl_sur_get_params(self._h, _fptr(out)), "cgl_sur_get_params")
         return out
 
-    def forward(self, batch: int, u, cstd, out) -> None:
-        check(L.lib().cgl_sur_forward(self._h, int(batch), _ptr(u), _ptr(cstd), _ptr(out)),
-              "cgl_sur_forward")
+    def forward(self, batch: int, u, cstd, out, base=None) -> None:
+        """out = network(u) about base (None: about u)."""
+        check(L.lib().cgl_sur_forward(self._h, int(batch), _ptr(u), _ptr(cstd), _ptr(base),
+                                      _ptr(out)), "cgl_sur_forward")
 
-    def grad(self, batch: int, src, cstd, idx, target_offset: int):
+    def grad(self, batch: int, src, cstd, idx, target_offset: int, base=None):
         g = np.zeros(self.count, dtype=np.float32)
         loss = C.c_double()
         check(L.lib().cgl_sur_grad(self._h, int(batch), _ptr(src), _ptr(cstd), _ptr(idx),
-                                   int(target_offset), _fptr(g), C.byref(loss)), "cgl_sur_grad")
+                                   int(target_offset), _ptr(base), _fptr(g), C.byref(loss)),
+              "cgl_sur_grad")
         return g, loss.value
 
-    def train_step(self, batch: int, src, cstd, idx, target_offset: int, lr: float) -> None:
+    def train_step(self, batch: int, src, cstd, idx, target_offset: int, lr: float,
+                   base=None) -> None:
         check(L.lib().cgl_sur_train_step(self._h, int(batch), _ptr(src), _ptr(cstd), _ptr(idx),
-                                         int(target_offset), float(lr)), "cgl_sur_train_step")
+                                         int(target_offset), _ptr(base), float(lr)),
+              "cgl_sur_train_step")
 
     def take_loss(self) -> float:
         v = C.c_double()
@@ -359,13 +367,21 @@ class Surrogate:
             pass
 
 
+SUR_BASES = {"input": L.SUR_BASE_INPUT, "linear": L.SUR_BASE_LINEAR, "strang": L.SUR_BASE_STRANG}
+
+
 def run_surrogate(plan: Plan, sur: Surrogate, u, cstd, njumps: int, steps_per_jump: int,
-                  check_every: int, tol: float):
-    """cgl_run_surrogate; returns (status, dict of counters)."""
+                  check_every: int, tol: float, coarse: Optional[Plan] = None,
+                  base: str = "input"):
+    """cgl_run_surrogate; returns (status, dict of counters).  base "linear" or
+    "strang" takes the jump's base from ``coarse`` (a plan of the same problem
+    with step steps_per_jump * tau)."""
     c = np.ascontiguousarray(cstd, dtype=np.float64)
     stats = (C.c_int64 * 4)()
     st = L.lib().cgl_run_surrogate(plan._h, sur._h, _ptr(u), _dptr(c), int(njumps),
-                                   int(steps_per_jump), int(check_every), float(tol), stats)
+                                   int(steps_per_jump), int(check_every), float(tol),
+                                   coarse._h if coarse is not None else None, SUR_BASES[base],
+                                   stats)
     if st not in (L.OK, L.ENONFINITE, L.EBLOWUP):
         raise CGLError(st, "cgl_run_surrogate")
     return st, {"accepted": stats[0], "rejected": stats[1], "checks": stats[2],

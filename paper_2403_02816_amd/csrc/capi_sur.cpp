@@ -39,6 +39,7 @@ struct cgl_sur_s {
   uint16_t* wf[NL] = {};
   uint16_t* wt[NL] = {};
   float* x = nullptr;  // [maxS][7][P]
+  float* xb = nullptr; // [maxS][2][P] base planes when a base state is given
   float* a[SUR_BLOCKS + 1] = {};
   float* h[SUR_BLOCKS + 1] = {};
   float *y = nullptr, *dy = nullptr, *dh = nullptr, *da[2] = {};
@@ -47,10 +48,12 @@ struct cgl_sur_s {
   double* hacc = nullptr;   // pinned copy
   float* cstd1 = nullptr;   // [5] coefficients of a gated run
   void *ver = nullptr, *prev = nullptr;  // complex64 [P]
+  void* base1 = nullptr;                 // complex64 [P]: the base of a gated jump
   bool have_params = false;
   int64_t t = 0;            // Adam steps taken
   int64_t loss_steps = 0;   // train steps since the last cgl_sur_take_loss
   int loss_kind = CGL_SUR_LOSS_MSE;
+  float oscale = 1.0f;      // scale of the network's correction (cgl_sur_set_output_scale)
   double* wsamp = nullptr;  // [maxS] per-sample weights of the relative loss
 };
 
@@ -121,6 +124,7 @@ ConvArgs conv_args(const cgl_sur_s* s, int S, const float* x, const uint16_t* w,
   c.S = S;
   c.epi = epi;
   c.aux_ch = aux_ch;
+  c.oscale = s->oscale;
   return c;
 }
 
@@ -129,8 +133,9 @@ int conv(const ConvArgs& c, int cin_pad, int cout_pad, hipStream_t st) {
 }
 
 // x -> y.  keep: store every pre-activation a_k and h_k for backward;
-// otherwise the hidden state ping-pongs between h[0] and h[1].
-int forward(cgl_sur_s* s, int S, bool keep, hipStream_t st) {
+// otherwise the hidden state ping-pongs between h[0] and h[1].  based: the
+// output adds the correction to the planes in xb instead of the input's.
+int forward(cgl_sur_s* s, int S, bool keep, bool based, hipStream_t st) {
   const Layer* L = s->L;
   int r = conv(conv_args(s, S, s->x, s->wf[0], B(s, 0), keep ? s->a[0] : nullptr, s->h[0],
                          nullptr, nullptr, L[0].cin, L[0].cout, CEPI_SILU, 0),
@@ -145,8 +150,8 @@ int forward(cgl_sur_s* s, int S, bool keep, hipStream_t st) {
   }
   if (r != CGL_OK) return r;
   const int k = NL - 1;
-  return conv(conv_args(s, S, hin, s->wf[k], B(s, k), s->y, nullptr, s->x, nullptr, L[k].cin,
-                        L[k].cout, CEPI_OUT, SUR_CIN),
+  return conv(conv_args(s, S, hin, s->wf[k], B(s, k), s->y, nullptr, based ? s->xb : s->x,
+                        nullptr, L[k].cin, L[k].cout, CEPI_OUT, based ? 2 : SUR_CIN),
               L[k].cin_pad, L[k].cout_pad, st);
 }
 
@@ -181,21 +186,24 @@ int backward(cgl_sur_s* s, int S, hipStream_t st) {
 int check_batch(const cgl_sur_s* s, int S) { return (S >= 1 && S <= s->maxS) ? CGL_OK : CGL_EINVAL; }
 
 int loss_and_grad(cgl_sur_s* s, int S, const void* src, const float* cstd, const int32_t* idx,
-                  int64_t toff, hipStream_t st) {
+                  int64_t toff, const void* base, hipStream_t st) {
   if (!s->have_params) return CGL_ENOTREADY;
   int r = dev(launch_sur_pack(src, idx, cstd, s->x, S, s->P, st));
-  if (r == CGL_OK) r = forward(s, S, true, st);
+  if (r == CGL_OK && base) r = dev(launch_sur_pack_base(base, idx, s->xb, S, s->P, st));
+  if (r == CGL_OK) r = forward(s, S, true, base != nullptr, st);
   if (r == CGL_OK)
     r = dev(launch_mse(s->y, src, idx, toff, s->loss_kind == CGL_SUR_LOSS_REL ? s->wsamp : nullptr,
-                       s->dy, s->dacc, S, s->P, st));
+                       s->oscale, s->dy, s->dacc, S, s->P, st));
   if (r == CGL_OK) r = backward(s, S, st);
   return r;
 }
 
-int infer(cgl_sur_s* s, int S, const void* u, const float* cstd, void* out, hipStream_t st) {
+int infer(cgl_sur_s* s, int S, const void* u, const float* cstd, const void* base, void* out,
+          hipStream_t st) {
   if (!s->have_params) return CGL_ENOTREADY;
   int r = dev(launch_sur_pack(u, nullptr, cstd, s->x, S, s->P, st));
-  if (r == CGL_OK) r = forward(s, S, false, st);
+  if (r == CGL_OK && base) r = dev(launch_sur_pack_base(base, nullptr, s->xb, S, s->P, st));
+  if (r == CGL_OK) r = forward(s, S, false, base != nullptr, st);
   if (r == CGL_OK) r = dev(launch_sur_unpack(s->y, out, S, s->P, st));
   return r;
 }
@@ -207,7 +215,7 @@ void release(cgl_sur_s* s) {
   };
   f(s->params); f(s->grad); f(s->m); f(s->v);
   for (int k = 0; k < NL; ++k) { f(s->wf[k]); f(s->wt[k]); }
-  f(s->x);
+  f(s->x); f(s->xb); f(s->base1);
   for (int k = 0; k <= SUR_BLOCKS; ++k) { f(s->a[k]); f(s->h[k]); }
   f(s->y); f(s->dy); f(s->dh); f(s->da[0]); f(s->da[1]); f(s->part);
   f(s->dacc); f(s->cstd1); f(s->ver); f(s->prev); f(s->wsamp);
@@ -254,6 +262,7 @@ int cgl_sur_create(cgl_sur_t* out, int64_t n1, int64_t n2, int max_batch, void* 
     if (l.coutT_pad) need(alloc(&s->wt[k], static_cast<int64_t>(l.coutT_pad) * conv_kpad(l.cinT_pad)));
   }
   need(alloc(&s->x, S * SUR_CIN * P));
+  need(alloc(&s->xb, S * 2 * P));
   for (int k = 0; k <= SUR_BLOCKS; ++k) {
     need(alloc(&s->a[k], S * SUR_C * P));
     need(alloc(&s->h[k], S * SUR_C * P));
@@ -270,6 +279,7 @@ int cgl_sur_create(cgl_sur_t* out, int64_t n1, int64_t n2, int max_batch, void* 
   need(alloc(&s->cstd1, 8));
   need(alloc(reinterpret_cast<float**>(&s->ver), 2 * P));
   need(alloc(reinterpret_cast<float**>(&s->prev), 2 * P));
+  need(alloc(reinterpret_cast<float**>(&s->base1), 2 * P));
   if (r == CGL_OK && hipHostMalloc(reinterpret_cast<void**>(&s->hacc), 4 * sizeof(double)) != hipSuccess)
     r = CGL_ENOMEM;
   if (r == CGL_OK) r = dev(launch_zero(reinterpret_cast<float*>(s->dacc), 8, s->stream));
@@ -305,6 +315,12 @@ int cgl_sur_set_loss(cgl_sur_t s, int kind) {
   return CGL_OK;
 }
 
+int cgl_sur_set_output_scale(cgl_sur_t s, float scale) {
+  if (!s || !std::isfinite(scale) || !(scale > 0.0f)) return CGL_EINVAL;
+  s->oscale = scale;
+  return CGL_OK;
+}
+
 int cgl_sur_get_params(cgl_sur_t s, float* params_host) {
   if (!s || !params_host) return CGL_EINVAL;
   if (!s->have_params) return CGL_ENOTREADY;
@@ -315,21 +331,22 @@ int cgl_sur_get_params(cgl_sur_t s, float* params_host) {
 }
 
 int cgl_sur_forward(cgl_sur_t s, int batch, const void* u_dev, const float* cstd_dev,
-                    void* out_dev) {
+                    const void* base_dev, void* out_dev) {
   if (!s || !u_dev || !cstd_dev || !out_dev) return CGL_EINVAL;
   int r = check_batch(s, batch);
   if (r != CGL_OK) return r;
-  return infer(s, batch, u_dev, cstd_dev, out_dev, s->stream);
+  return infer(s, batch, u_dev, cstd_dev, base_dev, out_dev, s->stream);
 }
 
 int cgl_sur_grad(cgl_sur_t s, int batch, const void* src_dev, const float* cstd_dev,
-                 const int32_t* idx_dev, int64_t target_offset, float* grad_host,
-                 double* loss_host) {
+                 const int32_t* idx_dev, int64_t target_offset, const void* base_dev,
+                 float* grad_host, double* loss_host) {
   if (!s || !src_dev || !cstd_dev || !grad_host) return CGL_EINVAL;
   int r = check_batch(s, batch);
   if (r != CGL_OK) return r;
   r = dev(launch_zero(reinterpret_cast<float*>(s->dacc), 2, s->stream));
-  if (r == CGL_OK) r = loss_and_grad(s, batch, src_dev, cstd_dev, idx_dev, target_offset, s->stream);
+  if (r == CGL_OK)
+    r = loss_and_grad(s, batch, src_dev, cstd_dev, idx_dev, target_offset, base_dev, s->stream);
   if (r == CGL_OK)
     r = dev(hipMemcpyAsync(grad_host, s->grad, static_cast<size_t>(s->count) * sizeof(float),
                            hipMemcpyDeviceToHost, s->stream));
@@ -343,11 +360,12 @@ int cgl_sur_grad(cgl_sur_t s, int batch, const void* src_dev, const float* cstd_
 }
 
 int cgl_sur_train_step(cgl_sur_t s, int batch, const void* src_dev, const float* cstd_dev,
-                       const int32_t* idx_dev, int64_t target_offset, float lr) {
+                       const int32_t* idx_dev, int64_t target_offset, const void* base_dev,
+                       float lr) {
   if (!s || !src_dev || !cstd_dev || !(lr >= 0.0f)) return CGL_EINVAL;
   int r = check_batch(s, batch);
   if (r != CGL_OK) return r;
-  r = loss_and_grad(s, batch, src_dev, cstd_dev, idx_dev, target_offset, s->stream);
+  r = loss_and_grad(s, batch, src_dev, cstd_dev, idx_dev, target_offset, base_dev, s->stream);
   if (r != CGL_OK) return r;
   s->t += 1;
   const double c1 = 1.0 / (1.0 - std::pow(ADAM_B1, static_cast<double>(s->t)));
@@ -380,16 +398,26 @@ void cgl_sur_destroy(cgl_sur_t s) {
 
 int cgl_run_surrogate(cgl_plan_t p, cgl_sur_t s, void* u_dev, const double* cstd,
                       int64_t njumps, int64_t steps_per_jump, int64_t check_every, double tol,
-                      int64_t* stats) {
+                      cgl_plan_t coarse, int base, int64_t* stats) {
   if (!p || !s || !u_dev || !cstd || njumps < 0 || steps_per_jump < 1 || check_every < 1 ||
-      !(tol > 0.0))
+      !(tol > 0.0) || base < CGL_SUR_BASE_INPUT || base > CGL_SUR_BASE_STRANG ||
+      (base != CGL_SUR_BASE_INPUT && !coarse))
     return CGL_EINVAL;
   PlanInfo pi;
   int r = plan_info(p, &pi);
   if (r != CGL_OK) return r;
-  if (pi.batch != 0 || pi.d != 2 || pi.n[0] != s->n1 || pi.n[1] != s->n2 ||
-      pi.precision != CGL_SPLIT_BF16 || (pi.flags & CGL_FLAG_FP64_MASTER))
-    return CGL_EINVAL;  // complex64 state of one 2-D instance of the network's grid
+  // complex64 state of one 2-D instance of the network's grid
+  auto fits = [&](const PlanInfo& q) {
+    return q.batch == 0 && q.d == 2 && q.n[0] == s->n1 && q.n[1] == s->n2 &&
+           q.precision == CGL_SPLIT_BF16 && !(q.flags & CGL_FLAG_FP64_MASTER);
+  };
+  if (!fits(pi)) return CGL_EINVAL;
+  if (base != CGL_SUR_BASE_INPUT) {
+    PlanInfo ci;
+    r = plan_info(coarse, &ci);
+    if (r != CGL_OK) return r;
+    if (!fits(ci) || ci.stream != pi.stream) return CGL_EINVAL;
+  }
   if (!s->have_params) return CGL_ENOTREADY;
   int64_t st[4] = {0, 0, 0, 0};  // accepted jumps, rejected jumps, checks, plain steps
   const hipStream_t q = pi.stream;
@@ -403,7 +431,15 @@ int cgl_run_surrogate(cgl_plan_t p, cgl_sur_t s, void* u_dev, const double* cstd
   for (int64_t j = 1; j <= njumps && r == CGL_OK; ++j) {
     const bool check = (j % check_every == 0) || j == njumps;
     if (check) r = dev(hipMemcpyAsync(s->prev, u_dev, bytes, hipMemcpyDeviceToDevice, q));
-    if (r == CGL_OK) r = infer(s, 1, u_dev, s->cstd1, u_dev, q);
+    // the base of the jump: the input itself, the coarse plan's exponential
+    // (e^{M tau K} u when its step is M tau) or one Strang step of the coarse plan
+    if (r == CGL_OK && base == CGL_SUR_BASE_LINEAR) r = cgl_tucker(coarse, CGL_E, u_dev, s->base1);
+    if (r == CGL_OK && base == CGL_SUR_BASE_STRANG) {
+      r = dev(hipMemcpyAsync(s->base1, u_dev, bytes, hipMemcpyDeviceToDevice, q));
+      if (r == CGL_OK) r = cgl_step(coarse, CGL_STRANG, s->base1, 1);
+    }
+    if (r == CGL_OK)
+      r = infer(s, 1, u_dev, s->cstd1, base == CGL_SUR_BASE_INPUT ? nullptr : s->base1, u_dev, q);
     if (r != CGL_OK) break;
     since += 1;
     if (!check) continue;

@@ -188,7 +188,7 @@ __global__ __launch_bounds__(NT) void k_conv(ConvArgs a, int ntiles) {
             if (a.out0) a.out0[o] = av;
             a.out1[o] = xa[m][j][r] + av * sigmoid_f(av);
           } else if constexpr (EPI == CEPI_OUT) {
-            a.out0[o] = xa[m][j][r] + v + a.bias[co];
+            a.out0[o] = fmaf(a.oscale, v + a.bias[co], xa[m][j][r]);
           } else {
             const float tot = v + xa[m][j][r];
             if (a.out0) a.out0[o] = tot;
@@ -408,6 +408,21 @@ __global__ void k_pack_input(const float2* u, const int* idx, const float* cstd,
   }
 }
 
+// base states (complex64 [*][P], sample idx[s] or s) -> planes xb[s][2][P]
+__global__ void k_pack_base(const float2* b, const int* idx, float* xb, int S, int64_t P) {
+  const int64_t total = static_cast<int64_t>(S) * P;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x; i < total;
+       i += static_cast<int64_t>(gridDim.x) * NT) {
+    const int s = static_cast<int>(i / P);
+    const int64_t p = i - s * P;
+    const int64_t src = idx ? idx[s] : s;
+    const float2 v = b[src * P + p];
+    float* xs = xb + 2 * static_cast<int64_t>(s) * P + p;
+    xs[0] = v.x;
+    xs[P] = v.y;
+  }
+}
+
 __global__ void k_unpack(const float* y, float2* out, int S, int64_t P) {
   const int64_t total = static_cast<int64_t>(S) * P;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x; i < total;
@@ -441,7 +456,7 @@ __global__ void k_rel_weights(const float2* tgt, const int* idx, int64_t toff, d
 // loss = (1/S) sum_s w_s sum_{c,p} (y - t)^2 with w_s = w[s], or 1 / (2P)
 // when w is null (the mean square); dy = d loss / dy; *loss += loss
 __global__ void k_mse(const float* y, const float2* tgt, const int* idx, int64_t toff,
-                      const double* w, float* dy, double* loss, int S, int64_t P) {
+                      const double* w, float dscale, float* dy, double* loss, int S, int64_t P) {
   __shared__ double red[NT];
   const int64_t total = static_cast<int64_t>(S) * P;
   const double mse_w = 1.0 / (2.0 * static_cast<double>(P));
@@ -454,7 +469,7 @@ __global__ void k_mse(const float* y, const float2* tgt, const int* idx, int64_t
     const float2 t = tgt[src * P + p];
     const int64_t o = 2 * static_cast<int64_t>(s) * P + p;
     const double ws = (w ? w[s] : mse_w) / S;
-    const float scale = static_cast<float>(2.0 * ws);
+    const float scale = static_cast<float>(2.0 * ws * dscale);
     const float d0 = y[o] - t.x, d1 = y[o + P] - t.y;
     dy[o] = scale * d0;
     dy[o + P] = scale * d1;
@@ -615,6 +630,13 @@ hipError_t launch_sur_pack(const void* u, const int* idx, const float* cstd, flo
   return hipGetLastError();
 }
 
+hipError_t launch_sur_pack_base(const void* b, const int* idx, float* xb, int S, int64_t P,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_base, dim3(grid_for(S * P, 8)), dim3(NT), 0, s,
+                     static_cast<const float2*>(b), idx, xb, S, P);
+  return hipGetLastError();
+}
+
 hipError_t launch_sur_unpack(const float* y, void* out, int S, int64_t P, hipStream_t s) {
   hipLaunchKernelGGL(k_unpack, dim3(grid_for(S * P, 8)), dim3(NT), 0, s, y,
                      static_cast<float2*>(out), S, P);
@@ -622,7 +644,8 @@ hipError_t launch_sur_unpack(const float* y, void* out, int S, int64_t P, hipStr
 }
 
 hipError_t launch_mse(const float* y, const void* target, const int* idx, int64_t toff,
-                      double* wbuf, float* dy, double* loss, int S, int64_t P, hipStream_t s) {
+                      double* wbuf, float dscale, float* dy, double* loss, int S, int64_t P,
+                      hipStream_t s) {
   if (wbuf) {
     hipLaunchKernelGGL(k_rel_weights, dim3(S), dim3(NT), 0, s, static_cast<const float2*>(target),
                        idx, toff, wbuf, P);
@@ -630,7 +653,7 @@ hipError_t launch_mse(const float* y, const void* target, const int* idx, int64_
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_mse, dim3(grid_for(S * P, 4)), dim3(NT), 0, s, y,
-                     static_cast<const float2*>(target), idx, toff, wbuf, dy, loss, S, P);
+                     static_cast<const float2*>(target), idx, toff, wbuf, dscale, dy, loss, S, P);
   return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ constexpr int SUR_LAYERS = SUR_BLOCKS + 2;
 enum ConvEpi : int {
   CEPI_SILU = 1,  // out0 = a = conv + b, out1 = silu(a)
   CEPI_RES = 2,   // out0 = a = conv + b, out1 = aux + silu(a)      (aux = h_prev)
-  CEPI_OUT = 3,   // out0 = aux[channels 0,1] + conv + b             (aux = network input)
+  CEPI_OUT = 3,   // out0 = aux[channels 0,1] + oscale (conv + b)    (aux = base planes)
   CEPI_BWD = 4,   // out0 = conv (+ aux), out1 = out0 * silu'(aux2)  (transposed conv)
 };
 
@@ -39,6 +39,7 @@ struct ConvArgs {
   int cin, cout, n1, n2, S;
   int epi;
   int aux_ch;  // channel count of aux's samples (CEPI_OUT: network input channels)
+  float oscale;  // CEPI_OUT: scale of the network's correction
 };
 
 // cin_pad in {8, 48}, cout_pad in {16, 48}; requires n1 % 64 == 0
@@ -60,13 +61,19 @@ hipError_t launch_wgrad(const WgradArgs& a, float* part, float* grad, hipStream_
 // u complex64 [*][P], cstd [*][5]
 hipError_t launch_sur_pack(const void* u, const int* idx, const float* cstd, float* x, int S,
                            int64_t P, hipStream_t s);
+// xb[s] = [Re b, Im b] of base sample idx[s] (idx null: s); b complex64 [*][P]
+hipError_t launch_sur_pack_base(const void* b, const int* idx, float* xb, int S, int64_t P,
+                                hipStream_t s);
 // out complex64 [S][P] from y [S][2][P]
 hipError_t launch_sur_unpack(const float* y, void* out, int S, int64_t P, hipStream_t s);
 // target of sample s: complex64 sample (idx[s] or s) + toff.  wbuf null: the
 // mean square error; otherwise ([S] doubles of scratch) the mean over samples
-// of the squared relative L2 error.  dy = d loss / dy, *loss += loss (FP64).
+// of the squared relative L2 error.  dy = dscale * d loss / dy (the gradient
+// with respect to the unscaled correction when y = base + dscale * d),
+// *loss += loss (FP64).
 hipError_t launch_mse(const float* y, const void* target, const int* idx, int64_t toff,
-                      double* wbuf, float* dy, double* loss, int S, int64_t P, hipStream_t s);
+                      double* wbuf, float dscale, float* dy, double* loss, int S, int64_t P,
+                      hipStream_t s);
 // Adam on FP32 parameters; c1 = 1/(1 - b1^t), c2 = 1/(1 - b2^t)
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int count, float lr,
                        float b1, float b2, float eps, float c1, float c2, hipStream_t s);

@@ -18,7 +18,7 @@ def bf16(a: np.ndarray) -> np.ndarray:
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def forward(params, x):
+def forward(params, x, base=None, oscale=1.0):
     layers = [(bf16(W), b) for W, b in osur.unpack(params)]
     cache = {"a": [], "h": [x]}
     W, b = layers[0]
@@ -33,15 +33,15 @@ def forward(params, x):
         cache["a"].append(a)
         cache["h"].append(h)
     W, b = layers[-1]
-    y = x[:, 0:2] + osur.conv3x3(bf16(h), W, b)
+    y = (x[:, 0:2] if base is None else base) + oscale * osur.conv3x3(bf16(h), W, b)
     return y, cache, layers
 
 
-def grad(params, x, target, kind="mse"):
-    y, cache, layers = forward(params, x)
+def grad(params, x, target, kind="mse", base=None, oscale=1.0):
+    y, cache, layers = forward(params, x, base, oscale)
     nb = len(layers) - 2
     grads = [None] * len(layers)
-    dy = osur.loss_grad(y, target, kind)
+    dy = oscale * osur.loss_grad(y, target, kind)
     hs, As = cache["h"], cache["a"]
     _, dW, db = osur.conv3x3_grads(bf16(hs[-1]), layers[-1][0], bf16(dy))
     grads[-1] = (dW, db)

@@ -142,13 +142,14 @@ static void kernel_parity(std::vector<int64_t> n, int precision, unsigned seed) 
 // Periodic directions (Fourier pass for power-of-two n, the dense circulant
 // exponential otherwise): the Tucker operator against naive mode products
 // with the plan's dense exponentials, then every stepper.
-static void fourier_parity(std::vector<int64_t> n, int precision, unsigned seed) {
+static void fourier_parity(std::vector<int64_t> n, int precision, unsigned seed,
+                           unsigned flags = 0) {
   const int d = static_cast<int>(n.size());
   int64_t N = 1;
   for (auto v : n) N *= v;
   cgl_coeffs c{1.0, 0.6, -0.2, -1.0, 0.8, -0.1, -0.3};
   cgl_plan_t p = nullptr;
-  expect(cgl_plan(&p, d, n.data(), &c, 0.01, precision, 0, nullptr) == CGL_OK, "plan");
+  expect(cgl_plan(&p, d, n.data(), &c, 0.01, precision, flags, nullptr) == CGL_OK, "plan");
   std::vector<std::vector<cd>> Es(d);
   for (int mu = 0; mu < d; ++mu) {
     expect(cgl_set_periodic(p, mu, -3.0, 4.0) == CGL_OK, "set_periodic");
@@ -175,7 +176,8 @@ static void fourier_parity(std::vector<int64_t> n, int precision, unsigned seed)
   auto V = rnd(N, seed + 1, 0.3);
   std::vector<cd> v64 = V;
   std::vector<std::complex<float>> v32 = cast<float>(V);
-  void* u = precision == CGL_FP64 ? static_cast<void*>(v64.data()) : static_cast<void*>(v32.data());
+  const bool wide = precision == CGL_FP64 || (flags & CGL_FLAG_FP64_MASTER);
+  void* u = wide ? static_cast<void*>(v64.data()) : static_cast<void*>(v32.data());
   for (int m : {CGL_STRANG, CGL_LAWSON4, CGL_SPLIT4, CGL_LAWSON2})
     expect(cgl_step(p, m, u, 1) == CGL_OK, "fourier step");
   expect(cgl_run(p, CGL_LAWSON4, u, 2, 1) == CGL_OK, "fourier run");
@@ -425,17 +427,47 @@ static void surrogate(const std::string& dir, int64_t n1, int64_t n2, int S, flo
   cgl_sur_t s = nullptr;
   expect(cgl_sur_create(&s, n1, n2, S, nullptr) == CGL_OK, "sur create");
   std::vector<std::complex<float>> out(S * P);
-  expect(cgl_sur_forward(s, S, src.data(), cstd.data(), out.data()) == CGL_ENOTREADY, "not ready");
+  expect(cgl_sur_forward(s, S, src.data(), cstd.data(), nullptr, out.data()) == CGL_ENOTREADY,
+         "not ready");
   expect(cgl_sur_set_params(s, params.data()) == CGL_OK, "set params");
-  expect(cgl_sur_forward(s, S, src.data(), cstd.data(), out.data()) == CGL_OK, "forward");
+  expect(cgl_sur_forward(s, S, src.data(), cstd.data(), nullptr, out.data()) == CGL_OK, "forward");
   write_file(dir + "/fwd.c64", out);
+  // an explicit base equal to the input gives the same bits; a base shifted
+  // by a constant shifts the output by it (up to FP32 rounding)
+  std::vector<std::complex<float>> outb(S * P), based(src.begin(), src.begin() + S * P);
+  expect(cgl_sur_forward(s, S, src.data(), cstd.data(), based.data(), outb.data()) == CGL_OK,
+         "forward base");
+  expect(std::memcmp(out.data(), outb.data(), out.size() * sizeof(out[0])) == 0, "base = input");
+  const std::complex<float> shift(0.25f, -0.5f);
+  for (auto& v : based) v += shift;
+  expect(cgl_sur_forward(s, S, src.data(), cstd.data(), based.data(), outb.data()) == CGL_OK,
+         "forward shifted base");
+  double worst = 0.0;
+  for (int64_t i = 0; i < S * P; ++i)
+    worst = std::max(worst, static_cast<double>(std::abs(outb[i] - out[i] - shift)));
+  expect(worst < 1e-5, "shifted base");
+  // the output scale multiplies the correction
+  expect(cgl_sur_set_output_scale(s, 0.0f) == CGL_EINVAL && cgl_sur_set_output_scale(s, NAN) ==
+                                                                  CGL_EINVAL,
+         "bad output scale");
+  expect(cgl_sur_set_output_scale(s, 0.5f) == CGL_OK, "output scale");
+  expect(cgl_sur_forward(s, S, src.data(), cstd.data(), nullptr, outb.data()) == CGL_OK,
+         "forward scaled");
+  worst = 0.0;
+  for (int64_t i = 0; i < S * P; ++i)
+    worst = std::max(worst, static_cast<double>(std::abs((outb[i] - src[i]) -
+                                                         0.5f * (out[i] - src[i]))));
+  expect(worst < 1e-5, "scaled correction");
+  expect(cgl_sur_set_output_scale(s, 1.0f) == CGL_OK, "unit output scale");
   std::vector<float> grad(count);
   double loss = 0.0;
-  expect(cgl_sur_grad(s, S, src.data(), cstd.data(), nullptr, S, grad.data(), &loss) == CGL_OK,
+  expect(cgl_sur_grad(s, S, src.data(), cstd.data(), nullptr, S, nullptr, grad.data(), &loss) ==
+             CGL_OK,
          "grad");
   write_file(dir + "/grad.f32", grad);
   write_file(dir + "/loss.f64", std::vector<double>{loss});
-  expect(cgl_sur_train_step(s, S, src.data(), cstd.data(), nullptr, S, lr) == CGL_OK, "train");
+  expect(cgl_sur_train_step(s, S, src.data(), cstd.data(), nullptr, S, nullptr, lr) == CGL_OK,
+         "train");
   double mean = 0.0;
   expect(cgl_sur_take_loss(s, &mean) == CGL_OK && std::fabs(mean - loss) <= 1e-6 * loss,
          "take loss");
@@ -448,7 +480,8 @@ static void surrogate(const std::string& dir, int64_t n1, int64_t n2, int S, flo
     std::vector<float> g2(count);
     double l2 = 0.0;
     expect(cgl_sur_set_params(s, params.data()) == CGL_OK, "reset params");
-    expect(cgl_sur_grad(s, 2, src.data(), cstd.data(), idx.data(), S, g2.data(), &l2) == CGL_OK,
+    expect(cgl_sur_grad(s, 2, src.data(), cstd.data(), idx.data(), S, nullptr, g2.data(), &l2) ==
+               CGL_OK,
            "grad idx");
     double num = 0, den = 0;
     for (int64_t i = 0; i < count; ++i) {
@@ -457,6 +490,14 @@ static void surrogate(const std::string& dir, int64_t n1, int64_t n2, int S, flo
     }
     // the same two pairs in the other order: equal up to summation order
     expect(std::sqrt(num / den) < 1e-5 && std::fabs(l2 - loss) < 1e-9 * loss, "idx permutation");
+    // the base indexed like the source: the input itself as an explicit base
+    std::vector<float> g3(count);
+    double l3 = 0.0;
+    expect(cgl_sur_grad(s, 2, src.data(), cstd.data(), idx.data(), S, src.data(), g3.data(), &l3) ==
+               CGL_OK,
+           "grad base");
+    expect(std::memcmp(g2.data(), g3.data(), count * sizeof(float)) == 0 && l2 == l3,
+           "grad base = input");
   }
 
   // gated run with checks that fail: equals the plain stepper bit for bit
@@ -477,7 +518,8 @@ static void surrogate(const std::string& dir, int64_t n1, int64_t n2, int S, flo
   bad[count - 1] = 50.0f;
   expect(cgl_sur_set_params(s, bad.data()) == CGL_OK, "bad params");
   // 3 jumps of 1 step, checks at jumps 2 and 3: check 1, redo 2, check 1, redo 1
-  const int gst = cgl_run_surrogate(p, s, ua.data(), cs, 3, 1, 2, 1e-3, stats);
+  const int gst = cgl_run_surrogate(p, s, ua.data(), cs, 3, 1, 2, 1e-3, nullptr,
+                                    CGL_SUR_BASE_INPUT, stats);
   if (gst != CGL_OK) std::printf("gated run status %d\n", gst);
   expect(gst == CGL_OK, "gated run");
   expect(stats[0] == 0 && stats[1] == 3 && stats[2] == 2 && stats[3] == 1 + 2 + 1 + 1,
@@ -485,7 +527,50 @@ static void surrogate(const std::string& dir, int64_t n1, int64_t n2, int S, flo
   expect(cgl_run(p, CGL_LAWSON4, ub.data(), 3, 0) == CGL_OK, "plain run");
   expect(std::memcmp(ua.data(), ub.data(), ua.size() * sizeof(ua[0])) == 0, "rollback exact");
   double rs[5] = {0, 0, 0, 0, 0};
-  expect(cgl_run_surrogate(p, s, ua.data(), rs, 1, 0, 1, 1e-3, stats) == CGL_EINVAL, "bad M");
+  expect(cgl_run_surrogate(p, s, ua.data(), rs, 1, 0, 1, 1e-3, nullptr, CGL_SUR_BASE_INPUT,
+                           stats) == CGL_EINVAL,
+         "bad M");
+  expect(cgl_run_surrogate(p, s, ua.data(), rs, 1, 1, 1, 1e-3, nullptr, CGL_SUR_BASE_LINEAR,
+                           stats) == CGL_EINVAL,
+         "base without a coarse plan");
+  // a zero network about the linear base, with a loose tolerance: every jump
+  // is the coarse plan's exponential, and the checked spans continue from
+  // the plain result
+  cgl_plan_t q = nullptr;
+  expect(cgl_plan(&q, 2, n, &c, 0.02, CGL_SPLIT_BF16, 0, nullptr) == CGL_OK, "coarse plan");
+  for (int mu = 0; mu < 2; ++mu) {
+    std::vector<double> A(2 * n[mu] * n[mu]);
+    expect(cgl_fd_operator(n[mu], -10, 10, CGL_DIRICHLET, &c, 2, A.data()) == CGL_OK, "fd");
+    expect(cgl_set_operators(q, mu, A.data()) == CGL_OK, "coarse ops");
+  }
+  expect(cgl_sur_set_params(s, std::vector<float>(count, 0.0f).data()) == CGL_OK, "zero params");
+  std::vector<std::complex<float>> uc(src.begin(), src.begin() + P), ud = uc, ue(P);
+  expect(cgl_run_surrogate(p, s, uc.data(), cs, 1, 2, 2, 1e3, q, CGL_SUR_BASE_LINEAR, stats) ==
+             CGL_OK,
+         "gated linear");
+  expect(stats[0] == 1 && stats[2] == 1, "linear accepted");
+  expect(cgl_run(p, CGL_LAWSON4, ud.data(), 2, 0) == CGL_OK, "plain 2");
+  expect(std::memcmp(uc.data(), ud.data(), uc.size() * sizeof(uc[0])) == 0, "continues plain");
+  // two jumps, only the last checked (and accepted): the first jump's result
+  // is the coarse exponential of u (a zero network adds nothing), the
+  // second continues from the plain stepper's span after it
+  for (int base : {CGL_SUR_BASE_LINEAR, CGL_SUR_BASE_STRANG}) {
+    uc.assign(src.begin(), src.begin() + P);
+    ue = uc;
+    if (base == CGL_SUR_BASE_LINEAR) {
+      expect(cgl_tucker(q, CGL_E, uc.data(), ue.data()) == CGL_OK, "coarse tucker");
+    } else {
+      expect(cgl_step(q, CGL_STRANG, ue.data(), 1) == CGL_OK, "coarse strang");
+    }
+    expect(cgl_run(p, CGL_LAWSON4, ue.data(), 2, 0) == CGL_OK, "plain after base");
+    expect(cgl_run_surrogate(p, s, uc.data(), cs, 2, 2, 5, 1e3, q, base, stats) == CGL_OK,
+           "gated two jumps");
+    expect(stats[0] == 2 && stats[2] == 1, "two accepted");
+    expect(std::memcmp(uc.data(), ue.data(), uc.size() * sizeof(uc[0])) == 0, "base jump exact");
+  }
+  expect(cgl_run_surrogate(p, s, uc.data(), cs, 1, 2, 1, 1e3, q, 3, stats) == CGL_EINVAL,
+         "bad base");
+  cgl_destroy(q);
   cgl_destroy(p);
   cgl_sur_destroy(s);
 }
@@ -500,6 +585,19 @@ int main(int argc, char** argv) {
     cgl_coeffs c0{1.0, 1.5, 0.5, -1.0, 1.0, 0.0, 0.0};
     run_steps({64, 64}, CGL_FP64, 0, c0, -10, 10, CGL_DIRICHLET, 0.01, CGL_STRANG, 100);
     run_steps({64, 64}, CGL_FP64, 0, c0, -10, 10, CGL_DIRICHLET, 0.01, CGL_LAWSON4, 50);
+    std::printf("%s (%d failures)\n", failures ? "FAILED" : "PASSED", failures);
+    return failures ? 1 : 0;
+  }
+  if (argc > 1 && std::string(argv[1]) == "fft") {
+    // the Fourier pass alone: every transform length's staging shape, both
+    // precisions, a complex128 state entering a complex64 plan
+    for (int prec : {CGL_FP64, CGL_SPLIT_BF16}) {
+      fourier_parity({16, 8, 32}, prec, 21);
+      fourier_parity({128, 4}, prec, 24);
+      fourier_parity({256, 4}, prec, 25);
+    }
+    fourier_parity({32, 16}, CGL_SPLIT_BF16, 26, CGL_FLAG_FP64_MASTER);
+    fourier_parity({64, 12}, CGL_SPLIT_BF16, 27, CGL_FLAG_FP64_MASTER);
     std::printf("%s (%d failures)\n", failures ? "FAILED" : "PASSED", failures);
     return failures ? 1 : 0;
   }

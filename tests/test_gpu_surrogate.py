@@ -93,6 +93,58 @@ def test_forward_and_gradient_parity(n1, n2, S):
     sur.destroy()
 
 
+def test_base_state_parity():
+    """The network about an explicit base state, y = base + conv_out(h):
+    forward and gradient against the oracle network with the same base; the
+    base of a gathered training sample is indexed like its source; an
+    explicit base equal to the input gives the bits of no base."""
+    torch = require_gpu()
+    from paper_2403_02816_amd import cgl
+    n1, n2, S = 128, 24, 3
+    params, src, cstd = _case(n1, n2, S, seed=77)
+    P = n1 * n2
+    rng = np.random.default_rng(78)
+    base = (rng.normal(size=(S, P)) + 1j * rng.normal(size=(S, P))).astype(np.complex64)
+    sur = cgl.Surrogate(n1, n2, S)
+    sur.set_params(params.astype(np.float32))
+    u = _dev(torch, src.reshape(-1))
+    cs = _dev(torch, cstd)
+    b = _dev(torch, base.reshape(-1))
+    out0 = torch.empty((S * P,), dtype=torch.complex64, device="cuda")
+    out = torch.empty_like(out0)
+    sur.forward(S, u, cs, out0)
+    sur.forward(S, u, cs, out, base=u[:S * P].clone())
+    torch.cuda.synchronize()
+    assert torch.equal(out, out0)
+    sur.forward(S, u, cs, out, base=b)
+    g, loss = sur.grad(S, u, cs, None, S, base=b)
+    c64 = cstd.astype(np.float64)
+    x = ref.inputs_from_states(src[:S].astype(np.complex128), c64[:S], n1, n2)
+    t = ref.inputs_from_states(src[S:].astype(np.complex128), c64[S:], n1, n2)[:, 0:2]
+    bp = ref.inputs_from_states(base.astype(np.complex128), c64[:S], n1, n2)[:, 0:2]
+    y_ref, g_ref, loss_ref = ref.grad(params, x, t, base=bp)
+    e = {"fwd": rel(out.cpu().numpy().reshape(S, P), ref.planes_to_states(y_ref)),
+         "grad": rel(g, g_ref), "loss": abs(loss - loss_ref) / loss_ref}
+    log("  base: " + " ".join(f"{k} {v:.2e}" for k, v in e.items()))
+    assert e["fwd"] < 5e-4 and e["grad"] < 5e-4 and e["loss"] < 1e-5
+    # samples 2 and 0 through an index array: bases 2 and 0
+    idx = _dev(torch, np.array([2, 0], dtype=np.int32))
+    g2, loss2 = sur.grad(2, u, cs, idx, S, base=b)
+    sel = [2, 0]
+    _, g2_ref, loss2_ref = ref.grad(params, x[sel], t[sel], base=bp[sel])
+    assert rel(g2, g2_ref) < 5e-4 and abs(loss2 - loss2_ref) < 1e-5 * loss2_ref
+    # an output scale: y = base + 0.25 d, the gradient scaled with it
+    sur.set_output_scale(0.25)
+    sur.forward(S, u, cs, out, base=b)
+    g3, loss3 = sur.grad(S, u, cs, None, S, base=b)
+    y3_ref, g3_ref, loss3_ref = ref.grad(params, x, t, base=bp, oscale=0.25)
+    e3 = (rel(out.cpu().numpy().reshape(S, P), ref.planes_to_states(y3_ref)), rel(g3, g3_ref),
+          abs(loss3 - loss3_ref) / loss3_ref)
+    log(f"  scaled: fwd {e3[0]:.2e} grad {e3[1]:.2e} loss {e3[2]:.2e}")
+    assert e3[0] < 5e-4 and e3[1] < 5e-4 and e3[2] < 1e-5
+    sur.destroy()
+
+
 def test_adam_step_and_index_gather():
     torch = require_gpu()
     from paper_2403_02816_amd import cgl
@@ -192,6 +244,36 @@ def test_gated_run_rollback_and_accept():
     torch.cuda.synchronize()
     assert torch.equal(uc, ud)
     sur.destroy()
+    plan.destroy()
+
+
+def test_gated_run_about_a_coarse_base():
+    """A zero network about the linear or the Strang base: an unchecked jump
+    is the coarse plan's propagation of the state, bit for bit, and an
+    accepted check continues from the plain stepper's span."""
+    torch = require_gpu()
+    from paper_2403_02816_amd import cgl
+    from paper_2403_02816_amd import surrogate as S
+    p = ci.batched_sweep(2, ci.C4_EVAL_SEED, fixed_n=128)[0]
+    M = 10
+    plan = _plan_128(p)
+    coarse = S.coarse_plan([p], p.tau, M, batched=False)
+    cs = S.standardise(p.coeffs)
+    sur = cgl.Surrogate(128, 128, 1)
+    sur.set_params(np.zeros(sur.count, dtype=np.float32))
+    u0 = plan.to_device(ci.initial_state(p))
+    for base in ("linear", "strang"):
+        ua, ue = u0.clone(), torch.empty_like(u0)
+        S.apply_base(coarse, base, u0, ue)
+        assert plan.run("lawson4", ue, M) == 0
+        st, stats = cgl.run_surrogate(plan, sur, ua, cs, 2, M, 5, 1e3, coarse=coarse, base=base)
+        torch.cuda.synchronize()
+        assert st == 0 and stats == {"accepted": 2, "rejected": 0, "checks": 1, "plain_steps": M}
+        assert torch.equal(ua, ue), base
+    with pytest.raises(cgl.CGLError):  # a base without a coarse plan
+        cgl.run_surrogate(plan, sur, u0.clone(), cs, 1, M, 1, 1e-3, base="linear")
+    sur.destroy()
+    coarse.destroy()
     plan.destroy()
 
 

@@ -51,6 +51,30 @@ def test_backward_matches_central_finite_differences(kind):
     assert np.abs(g - fd).max() < 1e-7 * max(1.0, np.abs(fd).max())
 
 
+def test_backward_with_a_base_and_an_output_scale_matches_finite_differences():
+    """y = base + s d: the gradient carries the factor s and no dependence on
+    the base (checked against central differences of the loss itself)."""
+    C, blocks, s = 3, 1, 0.03
+    rng = np.random.default_rng(5)
+    params = S.init_params(6, C, blocks) + 0.05 * rng.standard_normal(S.param_count(C, blocks))
+    x = rng.standard_normal((2, 7, 4, 5))
+    base = rng.standard_normal((2, 2, 4, 5))
+    target = base + 0.02 * rng.standard_normal((2, 2, 4, 5))
+    y, cache = S.forward(params, x, C, blocks, base=base, oscale=s)
+    g = S.backward(params, cache, y, target, C, blocks, oscale=s)
+    h = 1e-6
+    fd = np.zeros_like(params)
+    for i in range(params.size):
+        e = np.zeros_like(params)
+        e[i] = h
+        fd[i] = (S.loss(S.forward(params + e, x, C, blocks, base=base, oscale=s)[0], target)
+                 - S.loss(S.forward(params - e, x, C, blocks, base=base, oscale=s)[0], target)) / (2 * h)
+    assert np.abs(g - fd).max() < 1e-7 * max(1.0, np.abs(fd).max())
+    # the base enters additively: a shifted base shifts y and nothing else
+    y2, _ = S.forward(params, x, C, blocks, base=base + 1.5, oscale=s)
+    assert np.allclose(y2 - y, 1.5, atol=1e-12)
+
+
 def test_adam_first_step_is_lr_times_sign():
     p = np.array([1.0, -2.0, 0.5])
     g = np.array([0.3, -4.0, 1e-3])
