@@ -21,6 +21,8 @@
 // through LDS three times.  The short DFTs run in registers (iterative
 // radix-2, twiddles from an LDS copy of the table exp(-2 pi i k / N)).
 // Arithmetic in T: double for complex128 passes, float for complex64 ones.
+#include <type_traits>
+
 #include "kernels.hpp"
 #include "pointwise.hpp"
 
@@ -94,10 +96,26 @@ struct FftTile {
   static constexpr int FPW_MAX = 256 / FftGeom<N>::N1;
   static constexpr int FPW_LDS = (sizeof(T) == 8 ? 2048 : 4096) / N;
   static constexpr int FPW = FPW_MAX < FPW_LDS ? FPW_MAX : (FPW_LDS > 0 ? FPW_LDS : 1);
+  static constexpr int EPT = FPW * N / 256;  // tensor elements per thread
+  static_assert(EPT * 256 == FPW * N, "a workgroup's fibres fill its threads evenly");
 };
 
 __device__ __forceinline__ int64_t fibre_base(int64_t f, int64_t R, int n) {
   return (R == 1) ? f * (int64_t)n : (f % R) + (f / R) * R * (int64_t)n;
+}
+
+// raw element of a complex64 (float2) or complex128 (double2) tensor
+template <bool F64>
+using Raw = std::conditional_t<F64, double2, float2>;
+
+template <bool F64>
+__device__ __forceinline__ Raw<F64> load_raw(const void* p, int64_t off) {
+  return reinterpret_cast<const Raw<F64>*>(p)[off];
+}
+
+template <typename R>
+__device__ __forceinline__ cd to_cd(R v) {
+  return {static_cast<double>(v.x), static_cast<double>(v.y)};
 }
 
 template <typename T>
@@ -117,33 +135,52 @@ __device__ __forceinline__ void store_out(void* p, int64_t off, bool f64, cd v) 
     reinterpret_cast<float2*>(p)[off] = float2{static_cast<float>(v.re), static_cast<float>(v.im)};
 }
 
-template <typename T, int N>
-__global__ __launch_bounds__(256) void k_pass_fft(PassFFT a) {
+// IN64: the input tensor is complex128 (always for T = double; for T = float
+// the first pass of a plan whose state is complex128)
+// Lengths up to 128 keep four workgroups (16 waves) per CU resident (at most
+// 128 VGPRs): a 128^3 pass is then one round of workgroups.
+template <typename T, int N, bool IN64>
+__global__ __launch_bounds__(256, N <= 128 ? 4 : 1) void k_pass_fft(PassFFT a) {
   using G = FftGeom<N>;
   constexpr int N1 = G::N1, N2 = G::N2, P = G::P;
   constexpr int FPW = FftTile<T, N>::FPW;
+  constexpr int EPT = FftTile<T, N>::EPT;
   constexpr int FS = N1 * P;  // LDS stride between fibres (complex)
   __shared__ cx<T> tile[FPW * FS];
   __shared__ cx<T> tw[N];
+  __shared__ cx<T> efac[N];  // the direction's factors e_k
   const int tid = threadIdx.x;
   const int64_t f0 = static_cast<int64_t>(blockIdx.x) * FPW;
-  const bool in64 = a.in_f64 != 0, out64 = a.out_f64 != 0;
+  const bool out64 = a.out_f64 != 0;
   unsigned flag = 0;
 
-  for (int q = tid; q < N; q += 256) {
-    const double2 w = reinterpret_cast<const double2*>(a.tw)[q];
-    tw[q] = {static_cast<T>(w.x), static_cast<T>(w.y)};
-  }
   // stage the fibres (consecutive threads take consecutive elements of a
-  // contiguous fibre, or consecutive fibres of one index when strided), with
-  // the prologue applied
-  for (int e = tid; e < FPW * N; e += 256) {
+  // contiguous fibre, or consecutive fibres of one index when strided): every
+  // load of the thread is issued before the first is used, then the
+  // prologue and the LDS stores
+  Raw<IN64> raw[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + 256 * i;
     const int fl = a.R == 1 ? e / N : e % FPW;
     const int k = a.R == 1 ? e % N : e / FPW;
     const int64_t f = f0 + fl;
-    cd v = {0.0, 0.0};
-    if (f < a.F) {
-      v = load_in<T>(a.in0, fibre_base(f, a.R, N) + a.R * static_cast<int64_t>(k), in64);
+    raw[i] = Raw<IN64>{0, 0};
+    if (f < a.F) raw[i] = load_raw<IN64>(a.in0, fibre_base(f, a.R, N) + a.R * static_cast<int64_t>(k));
+  }
+  // the twiddle table and the factors, loaded behind the tensor's elements
+  for (int q = tid; q < N; q += 256) {
+    const double2 w = reinterpret_cast<const double2*>(a.tw)[q];
+    tw[q] = {static_cast<T>(w.x), static_cast<T>(w.y)};
+    efac[q] = reinterpret_cast<const cx<T>*>(a.fac)[q];
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + 256 * i;
+    const int fl = a.R == 1 ? e / N : e % FPW;
+    const int k = a.R == 1 ? e % N : e / FPW;
+    cd v = to_cd(raw[i]);
+    if (f0 + fl < a.F) {
       if (a.pro == PRO_FLOW)
         v = flow_in(v, a.nl.tf, a.nl, flag);
       else if (a.pro == PRO_G)
@@ -169,13 +206,12 @@ __global__ __launch_bounds__(256) void k_pass_fft(PassFFT a) {
   if (tid < FPW * N1) {
     const int fl = tid / N1, k1 = tid % N1;
     cx<T>* t = tile + fl * FS + k1 * P;
-    const cx<T>* fac = reinterpret_cast<const cx<T>*>(a.fac);
     cx<T> y[N2];
 #pragma unroll
     for (int j2 = 0; j2 < N2; ++j2) y[j2] = t[j2];
     dft<N2, N1, false>(y, tw);
 #pragma unroll
-    for (int k2 = 0; k2 < N2; ++k2) y[k2] = cmul(y[k2], fac[k1 + N1 * k2]);
+    for (int k2 = 0; k2 < N2; ++k2) y[k2] = cmul(y[k2], efac[k1 + N1 * k2]);
     dft<N2, N1, true>(y, tw);
 #pragma unroll
     for (int j2 = 0; j2 < N2; ++j2) t[j2] = cmulc(y[j2], tw[(j2 * k1) & (N - 1)]);
@@ -196,8 +232,27 @@ __global__ __launch_bounds__(256) void k_pass_fft(PassFFT a) {
   __syncthreads();
   // store with the epilogue (consecutive threads take consecutive output
   // elements: along the fibre when the output stride is 1, across fibres
-  // otherwise)
-  for (int e = tid; e < FPW * N; e += 256) {
+  // otherwise); an epilogue with an auxiliary tensor issues all of the
+  // thread's auxiliary loads first
+  const bool has_aux = a.epi == EPI_L4_R1 || a.epi == EPI_L4_R2 || a.epi == EPI_RICH ||
+                       a.epi == EPI_L2;
+  cd xa[EPT];
+  if (has_aux) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = tid + 256 * i;
+      const int fl = a.R_out == 1 ? e / N : e % FPW;
+      const int m = a.R_out == 1 ? e % N : e / FPW;
+      const int64_t f = f0 + fl;
+      xa[i] = cd{0.0, 0.0};
+      if (f < a.F)
+        xa[i] = load_in<T>(a.aux, fibre_base(f, a.R_out, N) + a.R_out * static_cast<int64_t>(m),
+                           a.aux_f64 != 0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + 256 * i;
     const int fl = a.R_out == 1 ? e / N : e % FPW;
     const int m = a.R_out == 1 ? e % N : e / FPW;
     const int64_t f = f0 + fl;
@@ -213,7 +268,7 @@ __global__ __launch_bounds__(256) void k_pass_fft(PassFFT a) {
       if (!finite2(z)) flag |= FLAG_NONFINITE;
       store_out(a.out0, off, out64, z);
     } else {
-      const cd x = load_in<T>(a.aux, off, a.aux_f64 != 0);
+      const cd x = xa[i];
       if (a.epi == EPI_L4_R1) {  // y = Q, x = P
         cd X, Y;
         lawson_r1(x, y, a.nl, X, Y);
@@ -236,7 +291,14 @@ hipError_t launch_n(const PassFFT& a, hipStream_t s) {
   constexpr int FPW = FftTile<T, N>::FPW;
   const int64_t G = (a.F + FPW - 1) / FPW;
   if (G > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_pass_fft<T, N>), dim3(static_cast<unsigned>(G)), dim3(256), 0, s, a);
+  if constexpr (sizeof(T) == 8) {
+    if (!a.in_f64) return hipErrorInvalidValue;  // FP64 passes read complex128
+    hipLaunchKernelGGL((k_pass_fft<T, N, true>), dim3(static_cast<unsigned>(G)), dim3(256), 0, s, a);
+  } else if (a.in_f64) {
+    hipLaunchKernelGGL((k_pass_fft<T, N, true>), dim3(static_cast<unsigned>(G)), dim3(256), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_pass_fft<T, N, false>), dim3(static_cast<unsigned>(G)), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 

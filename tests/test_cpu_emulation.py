@@ -20,7 +20,7 @@ def test_library_under_cpu_emulation_with_sanitizers():
     # every split tile shape (the autotuner's timing is not emulated); the two
     # runs are independent processes, started together
     procs = []
-    for tile, mode in (("0", "quick"), ("1", "split")):
+    for tile, mode in (("0", "quick"), ("1", "split"), ("0", "fft")):
         env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
                    UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1", CGL_SPLIT_TILE=tile)
         procs.append((tile, mode, subprocess.Popen([exe, mode], stdout=subprocess.PIPE,
