@@ -76,7 +76,7 @@ def parse():
     ap.add_argument("--replays", type=int, default=5,
                     help="graph replays of the K timed steps (median reported)")
     ap.add_argument("--workload", default="c2_lawson4",
-                    choices=["c2_lawson4", "c2_strang", "c1", "c3", "c4", "t4"])
+                    choices=["c2_lawson4", "c2_strang", "c1", "c3", "c4", "t4", "t5"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
@@ -658,6 +658,116 @@ def bench_fourier(args):
     print(json.dumps(rec))
 
 
+PAPER_TABLE5 = {
+    "source": "Table 5: 2-D coupled cubic-quintic CGL, periodic, 700 x 350 Fourier modes, "
+              "if4 (Lawson4), 2500 steps, T = 3",
+    "hardware": "Intel Core i7-10750H (6 cores), MATLAB R2022a with FFTW, FP64",
+    "if4_steps": 2500, "if4_time_s": 167.7, "grid_points": 2 * 700 * 350,
+    "gp_steps_per_s": 2 * 700 * 350 * 2500 / 167.7,
+}
+
+
+def bench_coupled(args):
+    """The Table 5 workload: the coupled two-field system (Section 4.4) on
+    700 x 350 periodic modes (no Fourier pass at these lengths: each
+    direction's exponential is a dense circulant on the mu-mode product
+    kernels, the four independent field actions of a Lawson round run on
+    four streams), the soliton datum, Lawson4 with the paper's 2500-step tau,
+    both precisions.  A grid point is counted per field."""
+    import torch
+    import cgl_inputs as ci
+    from oracle import coupled as co, fourier as fo, steppers
+    from paper_2403_02816_amd import cgl
+    n, lo, hi, T, m = (700, 350), (0.0, 0.0), (70.0, 35.0), 3.0, 2500
+    tau = T / m
+    # the datum as Section 4.4 builds it, by the library: the 1-D cubic-quintic
+    # equation from the Gaussian 2.25 exp(-(x - 17.5)^2 / 12.5), if4 with
+    # 10000 steps to T = 25, then u0(x1, x2) = w(x1), v0 = w(70 - x1)
+    c = co.PAPER
+    p1 = cgl.Plan((n[0],), ci.Coeffs(c.a1, c.b1, c.a2, c.a3, c.b3, c.a4, c.b4), 25.0 / 10000,
+                  precision="fp64")
+    p1.set_periodic(0, lo[0], hi[0])
+    x = lo[0] + (hi[0] - lo[0]) * np.arange(n[0]) / n[0]
+    w1 = p1.to_device(2.25 * np.exp(-(x - 17.5) ** 2 / (2 * 2.5 ** 2)) + 0j)
+    assert p1.run("lawson4", w1, 10000, 2500) == 0
+    u1 = np.repeat(p1.to_host(w1)[:, None], n[1], axis=1)
+    p1.destroy()
+    W0 = np.stack([u1, np.roll(u1[::-1], 1, axis=0)])
+    K, W, R = args.steps, args.warmup, args.replays
+    pts = 2 * n[0] * n[1]
+
+    def timed(precision):
+        p = cgl.CoupledPlan(n, co.PAPER, tau, precision=precision)
+        for mu in range(2):
+            p.set_periodic(mu, lo[mu], hi[mu])
+        w = p.to_device(W0)
+        w0 = w.clone()
+        p.step("lawson4", w, max(W, 1))
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(max(1, R)):
+            w.copy_(w0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p.step("lawson4", w, K)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+        assert p.status() == 0
+        return p, w, times
+
+    p, w, times = timed("split")
+    ms = float(np.median(times))
+    # one-step gate of the split form against the oracle on the plan's factors
+    wg = p.to_device(W0.astype(np.complex64).astype(np.complex128))
+    p.step("lawson4", wg, 1)
+    torch.cuda.synchronize()
+    acts = [[fo.FourierAction([p.get_factor(f, mu, which) for mu in range(2)]) for f in range(2)]
+            for which in (0, 1)]
+    E = lambda X: np.stack([acts[0][0](X[0]), acts[0][1](X[1])])  # noqa: E731
+    H = lambda X: np.stack([acts[1][0](X[0]), acts[1][1](X[1])])  # noqa: E731
+    ref = steppers.lawson4_step(W0.astype(np.complex64).astype(np.complex128), E, H, tau,
+                                co.CoupledNonlinearity(co.PAPER))
+    from oracle import metrics
+    got = p.to_host(wg)
+    gate = (metrics.rel_l2(got, ref), metrics.rel_linf(got, ref))
+    split_state = p.to_host(w)
+    p.destroy()
+    # MFMA work of a step: 4 actions x 2 fields x (n1 + n2) x 8 N flops (FP64
+    # embedding), six bf16 term products each in the split form
+    alg = 4 * 2 * 8 * (n[0] * n[1]) * (n[0] + n[1])
+    fp64 = None
+    if not args.no_fp64:
+        p64, w64, t64 = timed("fp64")
+        ms64 = float(np.median(t64))
+        traj = metrics.rel_linf(split_state, p64.to_host(w64))
+        fp64 = {"value": pts * K / (ms64 * 1e-3), "ms_per_step": ms64 / K, "replays_ms": t64,
+                "mfma_tflops": alg / (ms64 / K * 1e-3) / 1e12,
+                "frac": alg / (ms64 / K * 1e-3) / 1e12 / MI355X_PEAK_FP64_TFLOPS,
+                "split_vs_fp64_rel_linf_after_steps": traj}
+        p64.destroy()
+    rec = {
+        "metric": "grid-point-steps/s (per field) at rel-L2 <=1e-6 vs FP64 oracle",
+        "value": pts * K / (ms * 1e-3), "unit": "grid-point-steps/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": ms / K, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16x3->f32 (split), state c64",
+        "data": "synthetic (the paper's soliton datum, computed by the library)",
+        "config": {"workload": "t5_coupled_cq2d_700x350_periodic: coupled cubic-quintic CGL, "
+                               f"Lawson4, tau={tau:.6g}", "grid": list(n), "fields": 2,
+                   "method": "lawson4", "parallelism": "single-gpu"},
+        "replays_ms": times,
+        "roofline": {"bound": "mfma", "achieved": 6 * alg / (ms / K * 1e-3) / 1e12,
+                     "peak": MI355X_PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": 6 * alg / (ms / K * 1e-3) / 1e12 / MI355X_PEAK_BF16_TFLOPS,
+                     "traffic": None,
+                     "kernel": "whole step: dense circulant mu-mode products (n = 700, 350) "
+                               "and the coupled pointwise kernels"},
+        "accuracy": {"one_step_rel_l2_vs_fp64_oracle": gate[0],
+                     "one_step_rel_linf_vs_fp64_oracle": gate[1], "gate": 1e-6},
+        "fp64_form": fp64, "paper_context": PAPER_TABLE5,
+    }
+    print(json.dumps(rec))
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -671,6 +781,8 @@ def main():
         return bench_batched(args)
     if args.workload == "c4":
         return bench_surrogate(args)
+    if args.workload == "t5":
+        return bench_coupled(args)
     if args.workload == "t4":
         return bench_fourier(args)
     p, method = workload(args.workload)

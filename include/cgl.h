@@ -280,6 +280,44 @@ int cgl_set_instance_operators(cgl_plan_t p, int j, int mu, const double* A);
 /* FP64 exponential (which = CGL_E / CGL_H) of direction mu of instance j */
 int cgl_get_instance_operator(cgl_plan_t p, int j, int mu, int which, double* out_host);
 
+/* ---- the coupled two-field system (Section 4.4, eq. coupled) ----
+ * Two fields u, v on one 2-D grid with periodic boundaries:
+ *   u_t =  a0 d_1 u + (a1 + i b1) Lap u + a2 u + (a3 + i b3)|u|^2 u
+ *          + (a4 + i b4)|u|^4 u + a5 |v|^2 u,
+ *   v_t = -a0 d_1 v + ... + a5 |u|^2 v   (the same terms with u and v swapped).
+ * K is block diagonal: each field's exponential is that of its own Kronecker
+ * sum (the Fourier route of Section 3.2; the first derivative's symbol is
+ * i k, 0 for the Nyquist mode of an even n), applied by the mu-mode product
+ * or Fourier kernels of a single-field plan per field.  The nonlinear part
+ * couples the fields pointwise; its sub-flow is one classical RK4 step.
+ * A state is 2 N elements, u then v (N = n1 n2, index 1 fastest), complex128
+ * for CGL_FP64 and complex64 for CGL_SPLIT_BF16. */
+typedef struct {
+  double a0, a1, b1, a2, a3, b3, a4, b4, a5;
+} cgl_coupled_coeffs;
+typedef struct cgl_coupled_s* cgl_coupled_t;
+
+/* Plan for an n[0] x n[1] grid (3 <= n_mu <= 4096), step tau, precision
+ * CGL_FP64 or CGL_SPLIT_BF16, on the caller's HIP stream; allocates five
+ * stage tensors of 2 N elements.  CGL_EINVAL, CGL_ENOMEM. */
+int cgl_coupled_plan(cgl_coupled_t* out, const int64_t* n, const cgl_coupled_coeffs* c,
+                     double tau, int precision, void* hip_stream);
+/* Periodic direction mu on (a, b) for both fields (u with +a0 d_1 and v with
+ * -a0 d_1 in direction 0).  Both directions must be set before a step. */
+int cgl_coupled_set_periodic(cgl_coupled_t p, int mu, double a, double b);
+/* The diagonal of exp(t A_mu) of field 0 (u) or 1 (v), t = tau (CGL_E) or
+ * tau/2 (CGL_H): 2 n_mu doubles (complex128, the transform's order). */
+int cgl_coupled_get_factor(cgl_coupled_t p, int field, int mu, int which, double* out_host);
+/* nsteps steps of CGL_STRANG, CGL_LAWSON4, CGL_SPLIT4 or CGL_LAWSON2
+ * (asynchronous, on the plan's stream).  CGL_ENOTREADY before both
+ * directions are set. */
+int cgl_coupled_step(cgl_coupled_t p, int method, void* w_dev, int64_t nsteps);
+/* Synchronise; CGL_ENONFINITE if a step produced a non-finite value since
+ * the last call (then cleared), else CGL_OK. */
+int cgl_coupled_status(cgl_coupled_t p);
+/* Synchronise and free.  NULL is accepted. */
+void cgl_coupled_destroy(cgl_coupled_t p);
+
 /* ---- learned surrogate of the stepper (no counterpart in the paper) ----
  * A residual convolutional network on a 2-D grid n1 x n2 that maps a state
  * u(t) to an estimate of u(t + M tau) in one jump:

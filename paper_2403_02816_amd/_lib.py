@@ -29,6 +29,10 @@ class Coeffs(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("a1", "b1", "a2", "a3", "b3", "a4", "b4")]
 
 
+class CoupledCoeffs(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("a0", "a1", "b1", "a2", "a3", "b3", "a4", "b4", "a5")]
+
+
 _P = C.c_void_p
 _I64 = C.c_int64
 _D = C.c_double
@@ -76,6 +80,12 @@ SIGNATURES = {
     "cgl_sur_take_loss": (_I, [_P, _DP]),
     "cgl_sur_destroy": (None, [_P]),
     "cgl_run_surrogate": (_I, [_P, _P, _P, _DP, _I64, _I64, _I64, _D, _P, _I, C.POINTER(_I64)]),
+    "cgl_coupled_plan": (_I, [C.POINTER(_P), C.POINTER(_I64), C.POINTER(CoupledCoeffs), _D, _I, _P]),
+    "cgl_coupled_set_periodic": (_I, [_P, _I, _D, _D]),
+    "cgl_coupled_get_factor": (_I, [_P, _I, _I, _I, _DP]),
+    "cgl_coupled_step": (_I, [_P, _I, _P, _I64]),
+    "cgl_coupled_status": (_I, [_P]),
+    "cgl_coupled_destroy": (None, [_P]),
 }
 
 _lib = None

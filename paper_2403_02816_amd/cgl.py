@@ -386,3 +386,69 @@ def run_surrogate(plan: Plan, sur: Surrogate, u, cstd, njumps: int, steps_per_ju
         raise CGLError(st, "cgl_run_surrogate")
     return st, {"accepted": stats[0], "rejected": stats[1], "checks": stats[2],
                 "plain_steps": stats[3]}
+
+
+class CoupledPlan:
+    """cgl_coupled_*: the two-field system of Section 4.4 on a periodic 2-D
+    grid.  ``c`` has the fields a0, a1, b1, a2, a3, b3, a4, b4, a5; states are
+    1-D complex torch tensors of 2 N elements (u then v, each column-stacked)."""
+
+    def __init__(self, n: Sequence[int], c, tau: float, precision: str = "fp64",
+                 stream: Optional[int] = None):
+        self.n = tuple(int(v) for v in n)
+        self.N = self.n[0] * self.n[1]
+        self.precision = precision
+        if stream is None:
+            stream = current_stream_handle()
+        cc = L.CoupledCoeffs(*(float(getattr(c, k)) for k in
+                               ("a0", "a1", "b1", "a2", "a3", "b3", "a4", "b4", "a5")))
+        nn = (C.c_int64 * 2)(*self.n)
+        h = C.c_void_p()
+        check(L.lib().cgl_coupled_plan(C.byref(h), nn, C.byref(cc), float(tau),
+                                       L.FP64 if precision == "fp64" else L.SPLIT_BF16,
+                                       C.c_void_p(stream)), "cgl_coupled_plan")
+        self._h = h
+
+    @property
+    def dtype(self):
+        torch = _torch()
+        return torch.complex128 if self.precision == "fp64" else torch.complex64
+
+    def set_periodic(self, mu: int, a: float, b: float) -> None:
+        check(L.lib().cgl_coupled_set_periodic(self._h, int(mu), float(a), float(b)),
+              "cgl_coupled_set_periodic")
+
+    def get_factor(self, field: int, mu: int, which: int) -> np.ndarray:
+        out = np.zeros(2 * self.n[mu], dtype=np.float64)
+        check(L.lib().cgl_coupled_get_factor(self._h, int(field), int(mu), int(which), _dptr(out)),
+              "cgl_coupled_get_factor")
+        return out[0::2] + 1j * out[1::2]
+
+    def to_device(self, W: np.ndarray):
+        """W (2, n1, n2) -> device state (u then v, index 1 fastest)."""
+        torch = _torch()
+        flat = np.concatenate([np.asarray(W[k]).reshape(-1, order="F") for k in range(2)])
+        return torch.from_numpy(flat.astype(np.complex128)).to(device="cuda", dtype=self.dtype)
+
+    def to_host(self, t) -> np.ndarray:
+        a = t.detach().to("cpu").numpy().astype(np.complex128)
+        return np.stack([a[k * self.N:(k + 1) * self.N].reshape(self.n, order="F")
+                         for k in range(2)])
+
+    def step(self, method: str, w, nsteps: int = 1) -> None:
+        check(L.lib().cgl_coupled_step(self._h, METHODS[method], C.c_void_p(w.data_ptr()),
+                                       int(nsteps)), "cgl_coupled_step")
+
+    def status(self) -> int:
+        return L.lib().cgl_coupled_status(self._h)
+
+    def destroy(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.lib().cgl_coupled_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -1113,13 +1113,21 @@ int cgl_set_operators(cgl_plan_t p, int mu, const double* A) {
 }
 
 int cgl_set_periodic(cgl_plan_t p, int mu, double a, double b) {
+  return set_periodic_adv(p, mu, a, b, 0.0);
+}
+
+}  // extern "C"
+
+// cgl_set_periodic with an advection term adv d_mu in A_mu (the coupled
+// system of Section 4.4 carries +-a0 d_1)
+int cgl::set_periodic_adv(cgl_plan_t p, int mu, double a, double b, double adv) {
   if (!p || mu < 0 || mu >= p->d || p->batch > 0 || !(b > a) || !std::isfinite(a) ||
-      !std::isfinite(b))
+      !std::isfinite(b) || !std::isfinite(adv))
     return CGL_EINVAL;
   const int64_t n = p->n[mu];
   const cgl_coeffs& c = p->c;
-  fourier_factors(n, a, b, c.a1, c.b1, c.a2, p->d, p->tau, p->fac[mu][0]);
-  fourier_factors(n, a, b, c.a1, c.b1, c.a2, p->d, 0.5 * p->tau, p->fac[mu][1]);
+  fourier_factors(n, a, b, c.a1, c.b1, c.a2, p->d, p->tau, p->fac[mu][0], adv);
+  fourier_factors(n, a, b, c.a1, c.b1, c.a2, p->d, 0.5 * p->tau, p->fac[mu][1], adv);
   // the dense exponentials: returned by cgl_get_operator, and applied by the
   // mu-mode product kernels when n has no Fourier pass
   p->E[mu] = circulant_from_factors(n, p->fac[mu][0]);
@@ -1157,6 +1165,8 @@ int cgl_set_periodic(cgl_plan_t p, int mu, double a, double b) {
   p->have_ops[mu] = true;
   return CGL_OK;
 }
+
+extern "C" {
 
 int cgl_get_periodic_factor(cgl_plan_t p, int mu, int which, double* out_host) {
   if (!p || !out_host || mu < 0 || mu >= p->d || (which != CGL_E && which != CGL_H) ||

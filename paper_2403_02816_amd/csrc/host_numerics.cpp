@@ -302,14 +302,15 @@ bool fd_operator(int64_t n, double a, double b, int bc_lo, int bc_hi, int order,
 }
 
 void fourier_factors(int64_t n, double a, double b, double a1, double b1, double a2, int d,
-                     double t, std::vector<double>& fac) {
+                     double t, std::vector<double>& fac, double adv) {
   const double two_pi = 6.283185307179586476925286766559;
   fac.assign(static_cast<size_t>(2 * n), 0.0);
   for (int64_t q = 0; q < n; ++q) {
     const double wave = two_pi * static_cast<double>(q <= n / 2 ? q : q - n) / (b - a);
     const double k2 = wave * wave;
-    // t ((a1 + i b1)(-k^2) + a2/d)
-    const double re = t * (-a1 * k2 + a2 / d), im = t * (-b1 * k2);
+    const double k1 = (n % 2 == 0 && q == n / 2) ? 0.0 : wave;
+    // t ((a1 + i b1)(-k^2) + adv i k' + a2/d)
+    const double re = t * (-a1 * k2 + a2 / d), im = t * (-b1 * k2 + adv * k1);
     const double m = std::exp(re);
     fac[2 * q] = m * std::cos(im);
     fac[2 * q + 1] = m * std::sin(im);

@@ -39,11 +39,13 @@ bool fd_operator(int64_t n, double a, double b, int bc_lo, int bc_hi, int order,
                  double b1, double a2, int d, CMat& A);
 
 // Periodic direction on (a, b) with n equispaced nodes (Section 3.2): the
-// diagonal of exp(t A_mu), A_mu = (a1 + i b1)(-k^2) + a2/d over the wave
-// numbers k = 2 pi q / (b - a), q = 0, 1, .., n/2, -n/2 + 1, .., -1 in the
-// transform's coefficient order; interleaved complex128 (2n doubles).
+// diagonal of exp(t A_mu), A_mu = (a1 + i b1)(-k^2) + adv (i k') + a2/d over
+// the wave numbers k = 2 pi q / (b - a), q = 0, 1, .., n/2, -n/2 + 1, .., -1
+// in the transform's coefficient order; k' = k except k' = 0 for the Nyquist
+// mode of an even n (the first derivative of the coupled system's advection
+// term, Section 4.4); interleaved complex128 (2n doubles).
 void fourier_factors(int64_t n, double a, double b, double a1, double b1, double a2, int d,
-                     double t, std::vector<double>& fac);
+                     double t, std::vector<double>& fac, double adv = 0.0);
 // The same exponential as a dense circulant matrix on grid values,
 // F^{-1} diag(fac) F.
 CMat circulant_from_factors(int64_t n, const std::vector<double>& fac);

@@ -26,4 +26,8 @@ int plan_info(cgl_plan_t p, PlanInfo* out);
 int tucker_with_scratch(cgl_plan_t p, int which, const void* in_dev, void* out_dev, void* tmp0,
                         void* tmp1);
 
+// cgl_set_periodic with A_mu = (a1 + i b1) d_mu^2 + adv d_mu + a2/d (the
+// first derivative's symbol i k, 0 for the Nyquist mode of an even n).
+int set_periodic_adv(cgl_plan_t p, int mu, double a, double b, double adv);
+
 }  // namespace cgl

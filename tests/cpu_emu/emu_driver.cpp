@@ -185,6 +185,52 @@ static void fourier_parity(std::vector<int64_t> n, int precision, unsigned seed,
   cgl_destroy(p);
 }
 
+// The coupled two-field system: every method on Fourier and dense-circulant
+// directions; checks that the state stays finite and that with a0 = a5 = 0
+// that mirrored fields stay each other's mirror image (the system is
+// symmetric under x1 -> L - x1 with u and v swapped), which checks the
+// per-field indexing (u at [0, N), v at [N, 2N)) and the advection signs.
+static void coupled(std::vector<int64_t> n, int precision, unsigned seed) {
+  const int64_t N = n[0] * n[1];
+  cgl_coupled_coeffs c{-0.4, 0.125, 0.5, -0.9, 1.0, 0.8, -0.1, -0.6, 0.5};
+  cgl_coupled_t p = nullptr;
+  expect(cgl_coupled_plan(&p, n.data(), &c, 0.01, precision, nullptr) == CGL_OK, "coupled plan");
+  std::vector<double> fac(2 * n[0]);
+  expect(cgl_coupled_get_factor(p, 0, 0, CGL_E, fac.data()) == CGL_ENOTREADY ||
+             cgl_coupled_step(p, CGL_STRANG, fac.data(), 1) == CGL_ENOTREADY,
+         "coupled not ready");
+  for (int mu = 0; mu < 2; ++mu)
+    expect(cgl_coupled_set_periodic(p, mu, 0.0, 7.0 * (2 - mu)) == CGL_OK, "coupled periodic");
+  expect(cgl_coupled_get_factor(p, 1, 0, CGL_H, fac.data()) == CGL_OK, "coupled factor");
+  // u and its mirror image x1 -> L - x1 (node j -> -j mod n1) as v
+  auto U = rnd(N, seed, 0.5);
+  std::vector<cd> W(2 * N);
+  for (int64_t j2 = 0; j2 < n[1]; ++j2)
+    for (int64_t j1 = 0; j1 < n[0]; ++j1) {
+      W[j1 + n[0] * j2] = U[j1 + n[0] * j2];
+      W[N + j1 + n[0] * j2] = U[(n[0] - j1) % n[0] + n[0] * j2];
+    }
+  std::vector<std::complex<float>> W32 = cast<float>(W);
+  void* w = precision == CGL_FP64 ? static_cast<void*>(W.data()) : static_cast<void*>(W32.data());
+  for (int m : {CGL_STRANG, CGL_LAWSON4, CGL_SPLIT4, CGL_LAWSON2})
+    expect(cgl_coupled_step(p, m, w, 1) == CGL_OK, "coupled step");
+  expect(cgl_coupled_status(p) == CGL_OK, "coupled status");
+  expect(cgl_coupled_step(p, 7, w, 1) == CGL_EINVAL, "coupled bad method");
+  std::vector<cd> out = precision == CGL_FP64 ? W : back(W32);
+  double worst = 0.0, mx = 0.0;
+  for (int64_t j2 = 0; j2 < n[1]; ++j2)
+    for (int64_t j1 = 0; j1 < n[0]; ++j1) {
+      const cd u = out[j1 + n[0] * j2], v = out[N + (n[0] - j1) % n[0] + n[0] * j2];
+      worst = std::max(worst, std::abs(u - v));
+      mx = std::max(mx, std::abs(u));
+    }
+  std::printf("  coupled prec=%d n=%lldx%lld mirror %.2e (max %.2e)\n", precision,
+              static_cast<long long>(n[0]), static_cast<long long>(n[1]), worst, mx);
+  expect(std::isfinite(mx) && mx > 0.0, "coupled finite");
+  expect(worst < (precision == CGL_FP64 ? 1e-12 : 1e-5) * mx, "coupled mirror symmetry");
+  cgl_coupled_destroy(p);
+}
+
 static void steppers(std::vector<int64_t> n, int precision, unsigned flags, cgl_coeffs c,
                      double a, double b, int bc) {
   const int d = static_cast<int>(n.size());
@@ -598,6 +644,10 @@ int main(int argc, char** argv) {
     }
     fourier_parity({32, 16}, CGL_SPLIT_BF16, 26, CGL_FLAG_FP64_MASTER);
     fourier_parity({64, 12}, CGL_SPLIT_BF16, 27, CGL_FLAG_FP64_MASTER);
+    for (int prec : {CGL_FP64, CGL_SPLIT_BF16}) {
+      coupled({16, 8}, prec, 28);   // Fourier passes
+      coupled({12, 6}, prec, 29);   // dense circulant exponentials
+    }
     std::printf("%s (%d failures)\n", failures ? "FAILED" : "PASSED", failures);
     return failures ? 1 : 0;
   }
