@@ -40,10 +40,10 @@ MI355X_PEAK_HBM_GBS = 8000.0
 # (profiles/split_pass_c1_128_lawson4.md, profiles/split_pass_c2_256_lawson4.md).
 SPLIT_TRAFFIC = {
     # mean over the six paired launches of a step (128-row tiles, the shape the
-    # autotuner picks): (FETCH_SIZE x 2 + WRITE_SIZE) KiB = (15889 x 2 + 30037) KiB
-    "c1": {"bytes_per_launch": 63299584.0, "sources_sha256_16": "4e739ce4f8d7156f"},
-    # (144820 x 2 + 240299) KiB = 1.011 x the algorithmic 536870912 bytes
-    "c2_lawson4": {"bytes_per_launch": 542657835.0, "sources_sha256_16": "4e739ce4f8d7156f"},
+    # autotuner picks): (FETCH_SIZE x 2 + WRITE_SIZE) KiB = (15895 x 2 + 30037) KiB
+    "c1": {"bytes_per_launch": 63310165.0, "sources_sha256_16": "d2f5d89c985d52b6"},
+    # (144833 x 2 + 240299) KiB = 1.011 x the algorithmic 536870912 bytes
+    "c2_lawson4": {"bytes_per_launch": 542682965.0, "sources_sha256_16": "d2f5d89c985d52b6"},
 }
 SPLIT_SOURCES = ("kernels_split.hip", "kernels.hpp", "pointwise.hpp", "split_layout.cpp",
                  "split_layout.hpp")
@@ -771,8 +771,9 @@ def bench_coupled(args):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: there is no multi-GPU path "
+              "(a grid would be slab-decomposed along its slowest axis, one all-to-all "
+              "transpose per exponential action)", file=sys.stderr)
         sys.exit(2)
     import torch
     import cgl_inputs as ci

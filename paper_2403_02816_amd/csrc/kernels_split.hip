@@ -719,55 +719,72 @@ __device__ __forceinline__ void pair_epilogue(const PassSplit& a, int pt, int64_
   }
 }
 
-// SAMEG: both products read in0; the second applies g first (P = H u and
-// Q = H g(u)).  Otherwise the inputs are in0 and in1 (complex64).  Staging
-// of a stage's state tile (64 fibres x 16 indices of both tensors): with 4
-// waves every thread stages its 4 indices of one fibre of both tensors;
-// with 8 waves threads 0..255 stage the first tensor and 256..511 the second.
+// One work item of the paired pass (a row tile x fibre tile of one
+// direction).  SAMEG: both products read in0; the second applies g first
+// (P = H u and Q = H g(u)).  Otherwise the inputs are in0 and in1
+// (complex64).  Staging of a stage's state tile (64 fibres x 16 indices of
+// both tensors): with 4 waves every thread stages its 4 indices of one fibre
+// of both tensors; with 8 waves threads 0..255 stage the first tensor and
+// 256..511 the second.  prefetch() issues the item's first loads (operator
+// stage 0 to LDS buffer 0, the state of stages 0 and 1 to registers); run()
+// multiplies every stage and returns with both LDS buffers free (the last
+// copies landed, every wave past its last read), so a persistent workgroup
+// can issue the next item's first loads before this item's epilogue.
 template <bool SAMEG, bool IN64, int PT>
-__device__ __forceinline__ void split_tile_pair(const PassSplit& a, int pt, int64_t f0,
-                                                LdsP<PT, 16>& lds) {
+struct PairItem {
   using G = PairGeom<PT>;
-  constexpr int KS = 16;
-  constexpr int KJ = KS / 4;
-  constexpr int ABYTES = 12 * PT * KS;
-  constexpr int NDMA = ABYTES / (G::NW * 1024);  // 1 KB copies per wave and stage
+  static constexpr int KS = 16;
+  static constexpr int KJ = KS / 4;
+  static constexpr int ABYTES = 12 * PT * KS;
+  static constexpr int NDMA = ABYTES / (G::NW * 1024);  // 1 KB copies per wave and stage
   static_assert(NDMA * G::NW * 1024 == ABYTES, "operator stage must split evenly");
-  constexpr int ESZ = IN64 ? 16 : 8;
+  static constexpr int ESZ = IN64 ? 16 : 8;
   // state tensors this thread loads: both inputs (or u once) with 4 waves,
   // its own tensor's input with 8
-  constexpr int NL = G::TPT == 2 ? (SAMEG ? 1 : 2) : 1;
-  constexpr unsigned OOR = 0x80000000u;
+  static constexpr int NL = G::TPT == 2 ? (SAMEG ? 1 : 2) : 1;
+  static constexpr unsigned OOR = 0x80000000u;
   static_assert(!IN64 || SAMEG, "a complex128 input occurs only in the first pass");
+  using SV = f32x4[NL][KJ / 2];
+  using Lds = LdsP<PT, 16>;
 
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wp = wave % G::RB;
-  const int wf = wave / G::RB;
-  const int nKS = a.Kp / KS;
-  const __amdgpu_buffer_rsrc_t ors = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<uint16_t*>(a.op + static_cast<size_t>(pt) * nKS * (6 * PT * KS)), 0,
-      nKS * ABYTES, 0x00020000);
-  const int sid = tid & 255;                 // position within a 256-thread staging group
-  const int ts0 = G::TPT == 2 ? 0 : (tid >> 8);  // first tensor this thread stages
-  const int fl = (sid & 7) + 8 * (sid >> 5);
-  const int k0t = KJ * ((sid >> 3) & 3);
-  const int64_t srem = (a.F - f0) * static_cast<int64_t>(a.n) * ESZ;
-  const int rnum = static_cast<int>(srem < 0x7fffffffll ? srem : 0x7fffffffll);
-  const int64_t tile0 = f0 * static_cast<int64_t>(a.n) * ESZ;
+  PassSplit a;
+  int pt;
+  int64_t f0;
+  int nKS;
+  __amdgpu_buffer_rsrc_t ors;
   __amdgpu_buffer_rsrc_t srs[NL];
-#pragma unroll
-  for (int i = 0; i < NL; ++i) {
-    // load i reads in1 for the second tensor of a pair of distinct inputs
-    const bool second = !SAMEG && (G::TPT == 2 ? i == 1 : ts0 == 1);
-    srs[i] = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<char*>(reinterpret_cast<const char*>(second ? a.in1 : a.in0) + tile0), 0, rnum,
-        0x00020000);
-  }
-  const unsigned svo = static_cast<unsigned>((fl * a.n + k0t) * ESZ);
+  unsigned svo;
+  int fl, k0t, ts0;
 
-  auto copy_op = [&](int ks, int buf) __attribute__((always_inline)) {
+  __device__ __forceinline__ PairItem(const PassSplit& a_, int pt_, int64_t f0_)
+      : a(a_), pt(pt_), f0(f0_) {
+    const int tid = threadIdx.x;
+    nKS = a.Kp / KS;
+    ors = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint16_t*>(a.op + static_cast<size_t>(pt) * nKS * (6 * PT * KS)), 0,
+        nKS * ABYTES, 0x00020000);
+    const int sid = tid & 255;                 // position within a 256-thread staging group
+    ts0 = G::TPT == 2 ? 0 : (tid >> 8);        // first tensor this thread stages
+    fl = (sid & 7) + 8 * (sid >> 5);
+    k0t = KJ * ((sid >> 3) & 3);
+    const int64_t srem = (a.F - f0) * static_cast<int64_t>(a.n) * ESZ;
+    const int rnum = static_cast<int>(srem < 0x7fffffffll ? srem : 0x7fffffffll);
+    const int64_t tile0 = f0 * static_cast<int64_t>(a.n) * ESZ;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      // load i reads in1 for the second tensor of a pair of distinct inputs
+      const bool second = !SAMEG && (G::TPT == 2 ? i == 1 : ts0 == 1);
+      srs[i] = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<char*>(reinterpret_cast<const char*>(second ? a.in1 : a.in0) + tile0), 0,
+          rnum, 0x00020000);
+    }
+    svo = static_cast<unsigned>((fl * a.n + k0t) * ESZ);
+  }
+
+  __device__ __forceinline__ void copy_op(int ks, int buf, Lds& lds) const {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
     const unsigned o = ks < nKS ? static_cast<unsigned>(ks * ABYTES) : OOR;
 #pragma unroll
     for (int j = 0; j < NDMA; ++j) {
@@ -776,8 +793,9 @@ __device__ __forceinline__ void split_tile_pair(const PassSplit& a, int pt, int6
           ors, (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(lds.A[buf]) + blk * 1024),
           16, o + static_cast<unsigned>(blk * 1024 + lane * 16), 0, 0, 0);
     }
-  };
-  auto load_state = [&](int ks, f32x4 (&v)[NL][KJ / 2]) __attribute__((always_inline)) {
+  }
+
+  __device__ __forceinline__ void load_state(int ks, SV& v) const {
     const unsigned o = ks < nKS ? svo + static_cast<unsigned>(ks * KS * ESZ) : OOR;
 #pragma unroll
     for (int i = 0; i < NL; ++i)
@@ -795,14 +813,14 @@ __device__ __forceinline__ void split_tile_pair(const PassSplit& a, int pt, int6
               __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(srs[i], o + j * 8, 0, 0));
         }
       }
-  };
-  unsigned flag = 0;
-  auto store_state = [&](int ks, const f32x4 (&v)[NL][KJ / 2], int buf) __attribute__((always_inline)) {
+  }
+
+  __device__ __forceinline__ void store_state(int ks, const SV& v, int buf, Lds& lds) const {
     const int off = fl * KS + dma_chunk(fl, k0t / 8) * 8 + k0t % 8;
 #pragma unroll
     for (int t = 0; t < G::TPT; ++t) {
-      const int tt = ts0 + t;                       // tensor staged
-      const int li = G::TPT == 2 ? (SAMEG ? 0 : t) : 0;  // its load
+      const int tt = ts0 + t;                             // tensor staged
+      const int li = G::TPT == 2 ? (SAMEG ? 0 : t) : 0;   // its load
       cf w[KJ];
 #pragma unroll
       for (int j = 0; j < KJ; ++j) {
@@ -827,21 +845,17 @@ __device__ __forceinline__ void split_tile_pair(const PassSplit& a, int pt, int6
         store_terms<KJ>(&lds.B[buf][tt][(3 + q) * FT * KS + off], ti[q]);
       }
     }
-  };
+  }
 
-  f32x16 accr[2], acci[2];
-#pragma unroll
-  for (int t = 0; t < 2; ++t)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      accr[t][r] = 0.0f;
-      acci[t][r] = 0.0f;
-    }
-  const int row = lane & 31;
-  const int ch = lane >> 5;
-
-  auto stage = [&](int ks, f32x4 (&vload)[NL][KJ / 2], const f32x4 (&vstore)[NL][KJ / 2])
-      __attribute__((always_inline)) {
+  __device__ __forceinline__ void stage(int ks, SV& vload, const SV& vstore, f32x16 (&accr)[2],
+                                        f32x16 (&acci)[2], Lds& lds) const {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wp = wave % G::RB;
+    const int wf = wave / G::RB;
+    const int row = lane & 31;
+    const int ch = lane >> 5;
     const int cur = ks & 1;
     bf16x8 br[2][3], bi[2][3], ar[3], ai[3];
     {
@@ -865,7 +879,7 @@ __device__ __forceinline__ void split_tile_pair(const PassSplit& a, int pt, int6
       }
     }
     load_state(ks + 2, vload);
-    copy_op(ks + 1, cur ^ 1);
+    copy_op(ks + 1, cur ^ 1, lds);
     __builtin_amdgcn_sched_barrier(0);
     bf16x8 an[3];
 #pragma unroll
@@ -882,24 +896,48 @@ __device__ __forceinline__ void split_tile_pair(const PassSplit& a, int pt, int6
         accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an[ti_], bi[t][tj], accr[t], 0, 0, 0);
         acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ti_], bi[t][tj], acci[t], 0, 0, 0);
       }
-    store_state(ks + 1, vstore, cur ^ 1);
+    store_state(ks + 1, vstore, cur ^ 1, lds);
     __syncthreads();
-  };
-
-  f32x4 sv[2][NL][KJ / 2];
-  copy_op(0, 0);
-  load_state(0, sv[0]);
-  load_state(1, sv[1]);
-  store_state(0, sv[0], 0);
-  __syncthreads();
-  int ks = 0;
-  for (; ks + 1 < nKS; ks += 2) {
-    stage(ks, sv[0], sv[1]);
-    stage(ks + 1, sv[1], sv[0]);
   }
-  if (ks < nKS) stage(ks, sv[0], sv[1]);
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the last copies write the other buffer
-  __syncthreads();
+
+  __device__ __forceinline__ void prefetch(SV (&sv)[2], Lds& lds) const {
+    copy_op(0, 0, lds);
+    load_state(0, sv[0]);
+    load_state(1, sv[1]);
+  }
+
+  __device__ __forceinline__ void run(SV (&sv)[2], f32x16 (&accr)[2], f32x16 (&acci)[2],
+                                      Lds& lds) const {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        accr[t][r] = 0.0f;
+        acci[t][r] = 0.0f;
+      }
+    store_state(0, sv[0], 0, lds);
+    __syncthreads();
+    int ks = 0;
+    for (; ks + 1 < nKS; ks += 2) {
+      stage(ks, sv[0], sv[1], accr, acci, lds);
+      stage(ks + 1, sv[1], sv[0], accr, acci, lds);
+    }
+    if (ks < nKS) stage(ks, sv[0], sv[1], accr, acci, lds);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the last copies write the other buffer
+    __syncthreads();
+  }
+};
+
+template <bool SAMEG, bool IN64, int PT>
+__device__ __forceinline__ void split_tile_pair(const PassSplit& a, int pt, int64_t f0,
+                                                LdsP<PT, 16>& lds) {
+  using It = PairItem<SAMEG, IN64, PT>;
+  const It it(a, pt, f0);
+  typename It::SV sv[2];
+  it.prefetch(sv, lds);
+  f32x16 accr[2], acci[2];
+  it.run(sv, accr, acci, lds);
+  unsigned flag = 0;
   pair_epilogue<PT>(a, pt, f0, accr, acci, flag);
   if (flag) atomicOr(a.flag, flag);
 }
@@ -962,36 +1000,87 @@ __global__ __launch_bounds__(256, 2) void k_pass_split_batched(PassBatch b) {
   }
 }
 
-// Paired pass over every instance of a batched plan (persistent grid).
+// The pass arguments of one work item of a batched paired pass.
+template <bool SAMEG, bool IN64>
+__device__ __forceinline__ PassSplit batch_pair_item(const PassBatch& b, const BatchTile& tl) {
+  const BatchInstance& in = b.inst[tl.inst];
+  PassSplit a{};
+  const size_t esz_in = IN64 ? 16 : 8, esz_out = b.out_f64 ? 16 : 8;
+  a.in0 = static_cast<const char*>(b.in0) + in.off * esz_in;
+  a.in1 = b.in1 ? static_cast<const char*>(b.in1) + in.off * 8 : nullptr;
+  a.out0 = static_cast<char*>(b.out0) + in.off * esz_out;
+  a.out1 = b.out1 ? static_cast<char*>(b.out1) + in.off * 8 : nullptr;
+  a.op = b.which == 0 ? in.opE[b.tile] : in.opH[b.tile];
+  a.R = 1;
+  a.R_out = in.F;
+  a.F = in.F;
+  a.n = in.n;
+  a.Pp = in.Pp[b.tile];
+  a.Kp = in.Kp[b.tile];
+  a.pro = SAMEG ? PRO_G : PRO_NONE;
+  a.epi = b.epi;
+  a.in_f64 = IN64 ? 1 : 0;
+  a.out_f64 = b.out_f64;
+  a.tile = b.tile;
+  a.nl = in.nl;
+  a.nl.tf = b.tf;
+  a.flag = b.flag;
+  return a;
+}
+
+// the next entry of the table this workgroup walks (entries t, t + G, ...),
+// skipping padding; b.ntiles when there is none
+__device__ __forceinline__ int next_batch_item(const PassBatch& b, int t) {
+  while (t < b.ntiles && b.tiles[t].inst < 0) t += gridDim.x;
+  return t;
+}
+
+// Paired pass over every instance of a batched plan (persistent grid).  The
+// items are short (4-12 stages at the sweep's sizes), so with 64-row tiles
+// the next item's first loads are issued before the current item's
+// epilogue: its operator stage and state tiles are in flight while the
+// epilogue computes and stores.  The first pass of a round (SAMEG) and the
+// 128-row tile run their items one after the other: their registers would
+// not hold both (the compiler spills).
 template <bool SAMEG, bool IN64, int PT>
 __global__ __launch_bounds__(PT * 4, PT == 64 ? 2 : 1) void k_pass_split_batched_pair(PassBatch b) {
+  using It = PairItem<SAMEG, IN64, PT>;
   __shared__ __attribute__((aligned(16))) LdsP<PT, 16> lds;
-  for (int t = blockIdx.x; t < b.ntiles; t += gridDim.x) {
-    const BatchTile tl = b.tiles[t];
-    if (tl.inst < 0) continue;  // padding entry of the table
-    const BatchInstance& in = b.inst[tl.inst];
-    PassSplit a{};
-    const size_t esz_in = IN64 ? 16 : 8, esz_out = b.out_f64 ? 16 : 8;
-    a.in0 = static_cast<const char*>(b.in0) + in.off * esz_in;
-    a.in1 = b.in1 ? static_cast<const char*>(b.in1) + in.off * 8 : nullptr;
-    a.out0 = static_cast<char*>(b.out0) + in.off * esz_out;
-    a.out1 = b.out1 ? static_cast<char*>(b.out1) + in.off * 8 : nullptr;
-    a.op = b.which == 0 ? in.opE[b.tile] : in.opH[b.tile];
-    a.R = 1;
-    a.R_out = in.F;
-    a.F = in.F;
-    a.n = in.n;
-    a.Pp = in.Pp[b.tile];
-    a.Kp = in.Kp[b.tile];
-    a.pro = SAMEG ? PRO_G : PRO_NONE;
-    a.epi = b.epi;
-    a.in_f64 = IN64 ? 1 : 0;
-    a.out_f64 = b.out_f64;
-    a.tile = b.tile;
-    a.nl = in.nl;
-    a.nl.tf = b.tf;
-    a.flag = b.flag;
-    split_tile_pair<SAMEG, IN64, PT>(a, tl.pt, static_cast<int64_t>(tl.ft) * FT, lds);
+  if constexpr (SAMEG || PT != 64) {
+    for (int t = blockIdx.x; t < b.ntiles; t += gridDim.x) {
+      const BatchTile tl = b.tiles[t];
+      if (tl.inst < 0) continue;  // padding entry of the table
+      split_tile_pair<SAMEG, IN64, PT>(batch_pair_item<SAMEG, IN64>(b, tl), tl.pt,
+                                       static_cast<int64_t>(tl.ft) * FT, lds);
+    }
+  } else {
+    int t = next_batch_item(b, blockIdx.x);
+    if (t >= b.ntiles) return;
+    BatchTile tl = b.tiles[t];
+    It cur(batch_pair_item<SAMEG, IN64>(b, tl), tl.pt, static_cast<int64_t>(tl.ft) * FT);
+    typename It::SV sv[2];
+    cur.prefetch(sv, lds);
+    for (;;) {
+      f32x16 accr[2], acci[2];
+      cur.run(sv, accr, acci, lds);
+      // both LDS buffers are free: start the next item before this epilogue
+      t = next_batch_item(b, t + gridDim.x);
+      const bool more = t < b.ntiles;
+      if (more) {
+        tl = b.tiles[t];
+        const It nxt(batch_pair_item<SAMEG, IN64>(b, tl), tl.pt, static_cast<int64_t>(tl.ft) * FT);
+        nxt.prefetch(sv, lds);
+        unsigned flag = 0;
+        pair_epilogue<PT>(cur.a, cur.pt, cur.f0, accr, acci, flag);
+        if (flag) atomicOr(cur.a.flag, flag);
+        cur = nxt;
+      } else {
+        unsigned flag = 0;
+        pair_epilogue<PT>(cur.a, cur.pt, cur.f0, accr, acci, flag);
+        if (flag) atomicOr(cur.a.flag, flag);
+        break;
+      }
+    }
   }
 }
 
