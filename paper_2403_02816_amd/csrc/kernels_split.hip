@@ -730,7 +730,10 @@ __device__ __forceinline__ void pair_epilogue(const PassSplit& a, int pt, int64_
 // multiplies every stage and returns with both LDS buffers free (the last
 // copies landed, every wave past its last read), so a persistent workgroup
 // can issue the next item's first loads before this item's epilogue.
-template <bool SAMEG, bool IN64, int PT>
+// SKIP: a wave whose 32 x 32 block lies wholly in the padding skips its
+// products (the batched pass, whose small grids pad often; on the large
+// grids of a single-instance pass the branch costs more than it saves).
+template <bool SAMEG, bool IN64, int PT, bool SKIP = false>
 struct PairItem {
   using G = PairGeom<PT>;
   static constexpr int KS = 16;
@@ -755,10 +758,15 @@ struct PairItem {
   __amdgpu_buffer_rsrc_t srs[NL];
   unsigned svo;
   int fl, k0t, ts0;
+  bool live;  // this wave's 32 x 32 block has a row below n and a fibre below F
 
   __device__ __forceinline__ PairItem(const PassSplit& a_, int pt_, int64_t f0_)
       : a(a_), pt(pt_), f0(f0_) {
     const int tid = threadIdx.x;
+    {
+      const int wave = tid >> 6;
+      live = pt * PT + (wave % G::RB) * 32 < a.n && f0 + (wave / G::RB) * 32 < a.F;
+    }
     nKS = a.Kp / KS;
     ors = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint16_t*>(a.op + static_cast<size_t>(pt) * nKS * (6 * PT * KS)), 0,
@@ -881,21 +889,25 @@ struct PairItem {
     load_state(ks + 2, vload);
     copy_op(ks + 1, cur ^ 1, lds);
     __builtin_amdgcn_sched_barrier(0);
-    bf16x8 an[3];
+    // a wave whose block lies wholly in the padding (rows past n or fibres
+    // past F) skips its products: the matrix cores go to the other waves
+    if (!SKIP || live) {
+      bf16x8 an[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) an[q] = neg8(ai[q]);
-    constexpr int PI[6] = {2, 1, 0, 1, 0, 0};
-    constexpr int PJ[6] = {0, 1, 2, 0, 1, 0};
+      for (int q = 0; q < 3; ++q) an[q] = neg8(ai[q]);
+      constexpr int PI[6] = {2, 1, 0, 1, 0, 0};
+      constexpr int PJ[6] = {0, 1, 2, 0, 1, 0};
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+      for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        const int ti_ = PI[q], tj = PJ[q];
-        accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ti_], br[t][tj], accr[t], 0, 0, 0);
-        acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ai[ti_], br[t][tj], acci[t], 0, 0, 0);
-        accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an[ti_], bi[t][tj], accr[t], 0, 0, 0);
-        acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ti_], bi[t][tj], acci[t], 0, 0, 0);
-      }
+        for (int q = 0; q < 6; ++q) {
+          const int ti_ = PI[q], tj = PJ[q];
+          accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ti_], br[t][tj], accr[t], 0, 0, 0);
+          acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ai[ti_], br[t][tj], acci[t], 0, 0, 0);
+          accr[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an[ti_], bi[t][tj], accr[t], 0, 0, 0);
+          acci[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar[ti_], bi[t][tj], acci[t], 0, 0, 0);
+        }
+    }
     store_state(ks + 1, vstore, cur ^ 1, lds);
     __syncthreads();
   }
@@ -928,10 +940,10 @@ struct PairItem {
   }
 };
 
-template <bool SAMEG, bool IN64, int PT>
+template <bool SAMEG, bool IN64, int PT, bool SKIP = false>
 __device__ __forceinline__ void split_tile_pair(const PassSplit& a, int pt, int64_t f0,
                                                 LdsP<PT, 16>& lds) {
-  using It = PairItem<SAMEG, IN64, PT>;
+  using It = PairItem<SAMEG, IN64, PT, SKIP>;
   const It it(a, pt, f0);
   typename It::SV sv[2];
   it.prefetch(sv, lds);
@@ -1044,14 +1056,14 @@ __device__ __forceinline__ int next_batch_item(const PassBatch& b, int t) {
 // not hold both (the compiler spills).
 template <bool SAMEG, bool IN64, int PT>
 __global__ __launch_bounds__(PT * 4, PT == 64 ? 2 : 1) void k_pass_split_batched_pair(PassBatch b) {
-  using It = PairItem<SAMEG, IN64, PT>;
+  using It = PairItem<SAMEG, IN64, PT, true>;
   __shared__ __attribute__((aligned(16))) LdsP<PT, 16> lds;
   if constexpr (SAMEG || PT != 64) {
     for (int t = blockIdx.x; t < b.ntiles; t += gridDim.x) {
       const BatchTile tl = b.tiles[t];
       if (tl.inst < 0) continue;  // padding entry of the table
-      split_tile_pair<SAMEG, IN64, PT>(batch_pair_item<SAMEG, IN64>(b, tl), tl.pt,
-                                       static_cast<int64_t>(tl.ft) * FT, lds);
+      split_tile_pair<SAMEG, IN64, PT, true>(batch_pair_item<SAMEG, IN64>(b, tl), tl.pt,
+                                             static_cast<int64_t>(tl.ft) * FT, lds);
     }
   } else {
     int t = next_batch_item(b, blockIdx.x);
