@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <chrono>
 #include <cmath>
 #include <random>
 #include <string>
@@ -366,8 +367,9 @@ static void run_steps(std::vector<int64_t> n, int precision, unsigned flags, cgl
 
 // Batched plan vs one plain plan per instance with the same exponentials:
 // the same kernels run on the same data, so the states must agree bitwise.
-static void batched_vs_single(int precision) {
-  const std::vector<std::vector<int64_t>> grids = {{32, 48}, {20, 33}, {64, 32}, {9, 7}};
+static void batched_vs_single(int precision,
+                              const std::vector<std::vector<int64_t>>& grids = {
+                                  {32, 48}, {20, 33}, {64, 32}, {9, 7}}) {
   const int B = static_cast<int>(grids.size()), d = 2;
   std::vector<int64_t> flat;
   std::vector<cgl_coeffs> cs;
@@ -631,6 +633,41 @@ int main(int argc, char** argv) {
     cgl_coeffs c0{1.0, 1.5, 0.5, -1.0, 1.0, 0.0, 0.0};
     run_steps({64, 64}, CGL_FP64, 0, c0, -10, 10, CGL_DIRICHLET, 0.01, CGL_STRANG, 100);
     run_steps({64, 64}, CGL_FP64, 0, c0, -10, 10, CGL_DIRICHLET, 0.01, CGL_LAWSON4, 50);
+    std::printf("%s (%d failures)\n", failures ? "FAILED" : "PASSED", failures);
+    return failures ? 1 : 0;
+  }
+  if (argc > 1 && std::string(argv[1]) == "smoke") {
+    // one case of every kernel family (the default of the CPU suite; the
+    // quick, split and fft modes are the full sweep)
+    const cgl_coeffs cub{1.0, 1.5, 0.5, -1.0, 1.0, 0.0, 0.0};
+    const cgl_coeffs cq{1.0, 0.8, -0.1, 1.2, 1.0, -0.1, -0.5};
+    auto t0 = std::chrono::steady_clock::now();
+    auto lap = [&](const char* what) {
+      const auto t1 = std::chrono::steady_clock::now();
+      std::printf("  [%s: %.1f s]\n", what, std::chrono::duration<double>(t1 - t0).count());
+      std::fflush(stdout);
+      t0 = t1;
+    };
+    for (int prec : {CGL_FP64, CGL_SPLIT_BF16}) kernel_parity({20, 9, 7}, prec, 3);
+    lap("kernel parity");
+    steppers({12, 10, 6}, CGL_FP64, 0, cq, -15, 15, CGL_NEUMANN);
+    lap("fp64 steppers");
+    steppers({16, 12}, CGL_SPLIT_BF16, 0, cub, -10, 10, CGL_DIRICHLET);
+    lap("split steppers");
+    steppers({7, 6, 5}, CGL_SPLIT_BF16, CGL_FLAG_FP64_MASTER, cq, -15, 15, CGL_NEUMANN);
+    lap("master steppers");
+    paired_bitwise({7, 6, 5}, 0, cq, -15, 15, CGL_NEUMANN);
+    lap("paired 64");
+    setenv("CGL_PAIR_TILE", "3", 1);
+    paired_bitwise({7, 6, 5}, CGL_FLAG_FP64_MASTER, cq, -15, 15, CGL_NEUMANN);
+    unsetenv("CGL_PAIR_TILE");
+    lap("paired 128");
+    batched_vs_single(CGL_SPLIT_BF16, {{16, 24}, {9, 7}});
+    lap("batched");
+    fourier_parity({16, 8, 32}, CGL_SPLIT_BF16, 21);
+    lap("fourier");
+    coupled({16, 8}, CGL_FP64, 28);
+    lap("coupled");
     std::printf("%s (%d failures)\n", failures ? "FAILED" : "PASSED", failures);
     return failures ? 1 : 0;
   }

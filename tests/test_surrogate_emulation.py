@@ -37,6 +37,9 @@ def rel(a, b):
 
 
 @pytest.mark.skipif(not os.path.exists("/opt/rocm/llvm/bin/clang++"), reason="needs ROCm clang++")
+@pytest.mark.skipif(os.environ.get("CGL_EMU_FULL") != "1",
+                    reason="about 6 minutes: part of the full emulation sweep (CGL_EMU_FULL=1); "
+                           "the GPU tests check the same kernels against the oracle")
 def test_surrogate_kernels_under_cpu_emulation(tmp_path):
     from tests.cpu_emu import build as emu_build
     exe = emu_build.build()
