@@ -205,3 +205,40 @@ def test_table4_errors_match_the_paper():
         assert all(1 / 1.5 < r < 1.5 for r in ratios), (name, ratios)
         assert all(abs(orders[i] - pord[ms[i + 1]]) < 0.1 for i in range(4)), (name, orders)
     log(f"Table 4: worst error ratio to the paper {worst:.3f}")
+
+
+def test_table2_split4_errors_match_the_paper():
+    """Section 4.1.2, Table 2: 2-D cubic CGL on (0,100)^2, periodic, 256^2
+    Fourier grid, T = 6, split4 at 200 ... 400 steps, relative max-norm errors
+    against split4 with 1600 steps (the paper does not say how its reference
+    was made).  The paper's datum is MATLAB randn / 5000 and ours a seeded
+    datum of the same distribution, so the errors are compared statistically:
+    within a factor 1.5, orders within 0.3 (the oracle gives 1.72e-10 ...
+    1.86e-11, 0.88-0.93 of the printed errors; orders 2.76, 3.23, 3.55, 3.51
+    against the printed 2.695, 3.108, 3.440, 3.705)."""
+    torch = require_gpu()
+    p = ci.T2
+    T = 6.0
+    u0 = ci.initial_state(p)
+
+    def run(m):
+        q = ci.Problem(p.name, p.n, p.bc, p.a, p.b, p.coeffs, T / m, m, "split4", p.seed,
+                       init=p.init)
+        plan = _plan(q, "fp64")
+        u = plan.to_device(u0)
+        assert plan.run("split4", u, m, m) == 0
+        torch.cuda.synchronize()
+        out = plan.to_host(u)
+        plan.destroy()
+        return out
+
+    ref = run(1600)
+    ms = (200, 250, 300, 350, 400)
+    errs = [metrics.rel_linf(run(m), ref) for m in ms]
+    orders = [metrics.observed_order(ms[i], errs[i], ms[i + 1], errs[i + 1]) for i in range(4)]
+    perr, pord = _paper_column("table2", "split4")
+    log(f"Table 2 split4: errors {['%.3e' % e for e in errs]} (paper "
+        f"{['%.3e' % perr[m] for m in ms]}), orders {['%.3f' % o for o in orders]} (paper "
+        f"{['%.3f' % pord[m] for m in ms[1:]]})")
+    assert all(1 / 1.5 < errs[i] / perr[m] < 1.5 for i, m in enumerate(ms)), errs
+    assert all(abs(orders[i] - pord[ms[i + 1]]) < 0.3 for i in range(4)), orders
