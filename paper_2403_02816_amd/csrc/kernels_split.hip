@@ -43,6 +43,19 @@ namespace {
 
 constexpr int FT = SP_FT;  // 64 fibres
 
+// Wave-uniform values read from the first lane: a buffer resource built from
+// them is scalar.  (Fields of a work item loaded from memory the kernel also
+// writes come back in vector registers; a buffer resource built from those
+// turns every load through it into a waterfall loop.)
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+template <typename P>
+__device__ __forceinline__ P* uniform_ptr(P* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+  return reinterpret_cast<P*>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
 __device__ __forceinline__ int64_t fibre_base(int64_t f, int64_t R, int n) {
   return (R == 1) ? f * (int64_t)n : (f % R) + (f / R) * R * (int64_t)n;
 }
@@ -452,18 +465,19 @@ __device__ __forceinline__ void split_tile_dma(const PassSplit& a, int pt, int64
   const int wave = tid >> 6;
   const int wp = wave & 1;
   const int wf = wave >> 1;
-  const int nKS = a.Kp / KS;
+  const int nKS = uniform_i32(a.Kp / KS);
   const __amdgpu_buffer_rsrc_t ors = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<uint16_t*>(a.op + static_cast<size_t>(pt) * nKS * (6 * PT * KS)), 0,
-      nKS * ABYTES, 0x00020000);
+      uniform_ptr(const_cast<uint16_t*>(a.op + static_cast<size_t>(pt) * nKS * (6 * PT * KS))),
+      0, nKS * ABYTES, 0x00020000);
   // state: 8 consecutive lanes take 8 fibres at one index chunk; the buffer
   // range ends at the end of the tensor (fibres past F read zero)
   const int fl = (tid & 7) + 8 * (tid >> 5);
   const int k0t = KJ * ((tid >> 3) & 3);
   const int64_t srem = (a.F - f0) * static_cast<int64_t>(a.n) * ESZ;
   const __amdgpu_buffer_rsrc_t srs = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<char*>(reinterpret_cast<const char*>(a.in0) + f0 * static_cast<int64_t>(a.n) * ESZ),
-      0, static_cast<int>(srem < 0x7fffffffll ? srem : 0x7fffffffll), 0x00020000);
+      uniform_ptr(const_cast<char*>(reinterpret_cast<const char*>(a.in0) +
+                                    f0 * static_cast<int64_t>(a.n) * ESZ)),
+      0, uniform_i32(static_cast<int>(srem < 0x7fffffffll ? srem : 0x7fffffffll)), 0x00020000);
   const unsigned svo = static_cast<unsigned>((fl * a.n + k0t) * ESZ);
 
   auto copy_op = [&](int ks, int buf) __attribute__((always_inline)) {
@@ -767,24 +781,27 @@ struct PairItem {
       const int wave = tid >> 6;
       live = pt * PT + (wave % G::RB) * 32 < a.n && f0 + (wave / G::RB) * 32 < a.F;
     }
-    nKS = a.Kp / KS;
+    nKS = uniform_i32(a.Kp / KS);
     ors = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<uint16_t*>(a.op + static_cast<size_t>(pt) * nKS * (6 * PT * KS)), 0,
-        nKS * ABYTES, 0x00020000);
+        uniform_ptr(const_cast<uint16_t*>(a.op + static_cast<size_t>(pt) * nKS * (6 * PT * KS))),
+        0, nKS * ABYTES, 0x00020000);
     const int sid = tid & 255;                 // position within a 256-thread staging group
-    ts0 = G::TPT == 2 ? 0 : (tid >> 8);        // first tensor this thread stages
+    // first tensor this thread stages; wave-uniform, and read from the first
+    // lane so that the state buffer resource it selects stays scalar (a
+    // per-lane resource makes every state load a waterfall loop)
+    ts0 = G::TPT == 2 ? 0 : __builtin_amdgcn_readfirstlane(tid >> 8);
     fl = (sid & 7) + 8 * (sid >> 5);
     k0t = KJ * ((sid >> 3) & 3);
     const int64_t srem = (a.F - f0) * static_cast<int64_t>(a.n) * ESZ;
-    const int rnum = static_cast<int>(srem < 0x7fffffffll ? srem : 0x7fffffffll);
+    const int rnum = uniform_i32(static_cast<int>(srem < 0x7fffffffll ? srem : 0x7fffffffll));
     const int64_t tile0 = f0 * static_cast<int64_t>(a.n) * ESZ;
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
       // load i reads in1 for the second tensor of a pair of distinct inputs
       const bool second = !SAMEG && (G::TPT == 2 ? i == 1 : ts0 == 1);
       srs[i] = __builtin_amdgcn_make_buffer_rsrc(
-          const_cast<char*>(reinterpret_cast<const char*>(second ? a.in1 : a.in0) + tile0), 0,
-          rnum, 0x00020000);
+          uniform_ptr(const_cast<char*>(reinterpret_cast<const char*>(second ? a.in1 : a.in0) + tile0)),
+          0, rnum, 0x00020000);
     }
     svo = static_cast<unsigned>((fl * a.n + k0t) * ESZ);
   }

@@ -10,6 +10,7 @@
 #include <barrier>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <functional>
@@ -203,7 +204,22 @@ inline void __builtin_amdgcn_raw_ptr_buffer_load_lds(emu_buffer_rsrc r,
     std::memcpy(d + i, &w, 4);
   }
 }
+// v_readfirstlane: lane 0's value to every lane of the wave.  The library
+// applies it to wave-uniform values only; the emulation checks that they are.
+inline unsigned emu_readfirstlane(unsigned v) {
+  emu::exchange(v, v);
+  const unsigned r = emu::get<unsigned>(emu::xa[emu::wave()], 0);
+  emu::wave_barriers[emu::wave()]->arrive_and_wait();
+  if (r != v) {
+    std::fprintf(stderr, "readfirstlane of a value that differs across the wave\n");
+    std::abort();
+  }
+  return r;
+}
+#define __builtin_amdgcn_readfirstlane(v) emu_readfirstlane(static_cast<unsigned>(v))
+
 #define __builtin_amdgcn_sched_barrier(x) ((void)0)
+#define __builtin_amdgcn_sched_group_barrier(m, n, id) ((void)0)
 #define __builtin_amdgcn_s_waitcnt(x) ((void)0)
 
 #define __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, x, y, z) emu_mfma_f64((a), (b), (c))
