@@ -56,6 +56,21 @@ __device__ __forceinline__ P* uniform_ptr(P* p) {
   return reinterpret_cast<P*>((static_cast<uint64_t>(hi) << 32) | lo);
 }
 
+// Barrier between the stages of a pipelined product.  A wave waits for its
+// LDS accesses and for every vector-memory operation but the last NV: the
+// operator copies to LDS are issued before the state loads of a later stage,
+// so the copies have landed while those NV loads stay in flight across the
+// barrier (the release fence of __syncthreads() would wait for them too and
+// cut their prefetch distance to one stage).  The fences order LDS only.
+template <int NV>
+__device__ __forceinline__ void stage_barrier() {
+  static_assert(NV >= 0 && NV < 16, "vmcnt field");
+  __builtin_amdgcn_s_waitcnt(0x0070 | NV);  // vmcnt(NV) expcnt(7) lgkmcnt(0)
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ int64_t fibre_base(int64_t f, int64_t R, int n) {
   return (R == 1) ? f * (int64_t)n : (f % R) + (f / R) * R * (int64_t)n;
 }
@@ -458,6 +473,7 @@ __device__ __forceinline__ void split_tile_dma(const PassSplit& a, int pt, int64
   constexpr int NDMA = ABYTES / 4096;      // 1 KB copies per wave and stage
   static_assert(NDMA * 4096 == ABYTES, "operator stage must split evenly");
   constexpr int ESZ = IN64 ? 16 : 8;
+  constexpr int NV = IN64 ? KJ : KJ / 2;   // buffer loads of one stage's state
   constexpr unsigned OOR = 0x80000000u;    // out of range of both buffers
 
   const int tid = threadIdx.x;
@@ -572,11 +588,12 @@ __device__ __forceinline__ void split_tile_dma(const PassSplit& a, int pt, int64
         ai[b][t] = *reinterpret_cast<const bf16x8*>(&lds.A[cur][(3 + t) * PT * KS + o]);
       }
     }
-    load_state(ks + 2, vload);
-    copy_op(ks + 1, cur ^ 1);
     // the copies and loads go out before the MFMAs (the scheduler would sink
-    // them behind the math; the barrier at the end of the stage waits for
-    // them, so they get the whole stage to arrive)
+    // them behind the math), the copies first: the barrier at the end of the
+    // stage waits for them, the state loads get two stages to arrive
+    copy_op(ks + 1, cur ^ 1);
+    __builtin_amdgcn_sched_barrier(0);
+    load_state(ks + 2, vload);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int b = 0; b < PB; ++b) {
@@ -595,7 +612,7 @@ __device__ __forceinline__ void split_tile_dma(const PassSplit& a, int pt, int64
       }
     }
     store_state(ks + 1, vstore, cur ^ 1);
-    __syncthreads();
+    stage_barrier<NV>();
   };
 
   f32x4 sv[2][KJ / 2];
@@ -603,7 +620,7 @@ __device__ __forceinline__ void split_tile_dma(const PassSplit& a, int pt, int64
   load_state(0, sv[0]);
   load_state(1, sv[1]);
   store_state(0, sv[0], 0);
-  __syncthreads();
+  stage_barrier<NV>();
   int ks = 0;
   for (; ks + 1 < nKS; ks += 2) {
     stage(ks, sv[0], sv[1]);
