@@ -7,9 +7,9 @@
 // on the staged input, its epilogue before the store, contiguous or strided
 // fibres, rotated or in-place output.
 //
-// A workgroup stages FPW whole fibres in LDS (each as an N1 x N2 array with
-// padded rows, element j = N2 j1 + j2 at row j1, column j2, N = N1 N2,
-// N1 >= N2) and runs the four-step transform on them:
+// A workgroup stages FPW whole fibres in LDS (each as an N1 x N2 array,
+// element j = N2 j1 + j2 at row j1, column j2, N = N1 N2, N1 >= N2) and runs
+// the four-step transform on them:
 //   forward:  for each column j2, a length-N1 DFT over j1, times w_N^{j2 k1};
 //             for each row k1, a length-N2 DFT over j2 -> X[k1 + N1 k2];
 //   product:  X[k] *= e_k;
@@ -52,6 +52,17 @@ constexpr int bitrev(int v, int bits) {
   return r;
 }
 
+// x times w_N^q (forward) or its conjugate (inverse).  In FP32 the table
+// entries w = 1 (q = 0) and w = -i (q = N/4) are applied exactly, without a
+// product (in FP64, at its register bound, this measured slower)
+template <int N, bool INV, typename T>
+__device__ __forceinline__ cx<T> twiddle(cx<T> x, int q, const cx<T>* tw) {
+  if (sizeof(T) == 4 && q == 0) return x;
+  if (sizeof(T) == 4 && q == N / 4) return INV ? cx<T>{-x.im, x.re} : cx<T>{x.im, -x.re};
+  const cx<T> w = tw[q];
+  return INV ? cmulc(x, w) : cmul(x, w);
+}
+
 // Length-M DFT of x in natural order (M a power of two <= 32), forward
 // (sum_j x_j w_M^{jk}) or inverse (sum_k x_k w_M^{-jk}, unscaled).  tw holds
 // w_N^q, q < N, and w_M = w_N^S with S = N / M.
@@ -73,8 +84,8 @@ __device__ __forceinline__ void dft(cx<T> (&x)[M], const cx<T>* tw) {
     for (int i = 0; i < M; i += len)
 #pragma unroll
       for (int j = 0; j < len / 2; ++j) {
-        const cx<T> w = tw[j * (M / len) * S];
-        const cx<T> v = INV ? cmulc(x[i + j + len / 2], w) : cmul(x[i + j + len / 2], w);
+        // the loops unroll completely, so the table index is a constant
+        const cx<T> v = twiddle<M * S, INV>(x[i + j + len / 2], j * (M / len) * S, tw);
         const cx<T> u = x[i + j];
         x[i + j] = {u.re + v.re, u.im + v.im};
         x[i + j + len / 2] = {u.re - v.re, u.im - v.im};
@@ -87,22 +98,65 @@ struct FftGeom {
   static constexpr int B = ilog2(N);
   static constexpr int N1 = 1 << ((B + 1) / 2);  // rows
   static constexpr int N2 = N / N1;              // columns (N2 <= N1)
-  static constexpr int P = N2 + 1;               // padded row pitch (complex)
   static_assert((1 << B) == N && N >= 8 && N <= 1024, "power-of-two lengths 8 .. 1024");
 };
 
+// Fibres per workgroup and the LDS layout of the staged fibres: element
+// (j1, j2) of fibre fl at fl * FS + j1 * P + j2 (complex units).
+// complex64 (FF): in the transform phases consecutive threads take
+// consecutive fibres, so the 16 lanes that share an LDS cycle (8-byte
+// accesses, 32 banks) cover FPW fibres x G = 16 / FPW rows or columns:
+// FS = G mod 16 spreads the fibres and, when G > 1, a row pitch P = 1 mod 16
+// spreads the rows.  With G = 1 the rows stay unpadded, so a contiguous run of
+// 16 elements of one fibre (the staging of a contiguous fibre) is
+// conflict-free as well.  complex128: consecutive threads take consecutive
+// columns (rows) of one fibre, rows padded by one element (measured faster
+// for 16-byte elements, whose kernel is at its register bound).
 template <typename T, int N>
 struct FftTile {
-  static constexpr int FPW_MAX = 256 / FftGeom<N>::N1;
+  using Gm = FftGeom<N>;
+  static constexpr int FPW_MAX = 256 / Gm::N1;
   static constexpr int FPW_LDS = (sizeof(T) == 8 ? 2048 : 4096) / N;
   static constexpr int FPW = FPW_MAX < FPW_LDS ? FPW_MAX : (FPW_LDS > 0 ? FPW_LDS : 1);
   static constexpr int EPT = FPW * N / 256;  // tensor elements per thread
   static_assert(EPT * 256 == FPW * N, "a workgroup's fibres fill its threads evenly");
+  static constexpr bool FF = sizeof(T) == 4;
+  static constexpr int G = FPW >= 16 ? 1 : 16 / FPW;
+  static constexpr int P = FF && G == 1 ? Gm::N2 : Gm::N2 + 1;
+  static constexpr int FS = FF ? Gm::N1 * P + (((G - Gm::N1 * P) % 16) + 16) % 16 : Gm::N1 * P;
+  static_assert(!FF || (FS % 16 == G % 16 && FS >= Gm::N1 * P), "fibre stride");
 };
 
-__device__ __forceinline__ int64_t fibre_base(int64_t f, int64_t R, int n) {
-  return (R == 1) ? f * (int64_t)n : (f % R) + (f / R) * R * (int64_t)n;
-}
+// Offsets of a workgroup's elements in a tensor whose fibres have stride R
+// (fibre f starts at (f mod R) + (f div R) R n).  Element i of a thread is
+// e = tid + 256 i: with R = 1 (contiguous fibres) fibre e / n, index e mod n;
+// otherwise fibre e mod FPW, index e / FPW, so all elements of a thread lie
+// on one fibre, whose start is computed once.  The first fibre f0 is a
+// multiple of FPW: when R is one too, the workgroup's fibres share f div R,
+// a division of uniform values.
+template <int N, int FPW>
+struct ElemAddr {
+  static_assert(256 % FPW == 0, "a thread keeps one fibre when R > 1");
+  bool contig;
+  int64_t R, fst;  // fst: start of the thread's fibre (R > 1)
+  __device__ __forceinline__ ElemAddr(int64_t f0, int64_t R_, int tid) : contig(R_ == 1), R(R_), fst(0) {
+    if (!contig) {
+      const int fl = tid % FPW;
+      if (R % FPW == 0) {
+        const int64_t q = f0 / R;
+        fst = (f0 - q * R) + fl + q * R * N;
+      } else {
+        const int64_t f = f0 + fl;
+        fst = (f % R) + (f / R) * R * N;
+      }
+    }
+  }
+  __device__ __forceinline__ int fl(int e) const { return contig ? e / N : e % FPW; }
+  __device__ __forceinline__ int k(int e) const { return contig ? e % N : e / FPW; }
+  __device__ __forceinline__ int64_t off(int64_t f0, int e) const {
+    return contig ? f0 * N + e : fst + R * static_cast<int64_t>(e / FPW);
+  }
+};
 
 // raw element of a complex64 (float2) or complex128 (double2) tensor
 template <bool F64>
@@ -142,10 +196,11 @@ __device__ __forceinline__ void store_out(void* p, int64_t off, bool f64, cd v) 
 template <typename T, int N, bool IN64>
 __global__ __launch_bounds__(256, N <= 128 ? 4 : 1) void k_pass_fft(PassFFT a) {
   using G = FftGeom<N>;
-  constexpr int N1 = G::N1, N2 = G::N2, P = G::P;
-  constexpr int FPW = FftTile<T, N>::FPW;
-  constexpr int EPT = FftTile<T, N>::EPT;
-  constexpr int FS = N1 * P;  // LDS stride between fibres (complex)
+  using Tl = FftTile<T, N>;
+  constexpr int N1 = G::N1, N2 = G::N2;
+  constexpr int FPW = Tl::FPW, EPT = Tl::EPT;
+  constexpr int P = Tl::P, FS = Tl::FS;  // LDS row pitch and fibre stride (complex)
+  constexpr bool FF = Tl::FF;            // fibres across consecutive threads
   __shared__ cx<T> tile[FPW * FS];
   __shared__ cx<T> tw[N];
   __shared__ cx<T> efac[N];  // the direction's factors e_k
@@ -158,15 +213,13 @@ __global__ __launch_bounds__(256, N <= 128 ? 4 : 1) void k_pass_fft(PassFFT a) {
   // contiguous fibre, or consecutive fibres of one index when strided): every
   // load of the thread is issued before the first is used, then the
   // prologue and the LDS stores
+  const ElemAddr<N, FPW> ain(f0, a.R, tid);
   Raw<IN64> raw[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = tid + 256 * i;
-    const int fl = a.R == 1 ? e / N : e % FPW;
-    const int k = a.R == 1 ? e % N : e / FPW;
-    const int64_t f = f0 + fl;
     raw[i] = Raw<IN64>{0, 0};
-    if (f < a.F) raw[i] = load_raw<IN64>(a.in0, fibre_base(f, a.R, N) + a.R * static_cast<int64_t>(k));
+    if (f0 + ain.fl(e) < a.F) raw[i] = load_raw<IN64>(a.in0, ain.off(f0, e));
   }
   // the twiddle table and the factors, loaded behind the tensor's elements
   for (int q = tid; q < N; q += 256) {
@@ -177,21 +230,22 @@ __global__ __launch_bounds__(256, N <= 128 ? 4 : 1) void k_pass_fft(PassFFT a) {
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = tid + 256 * i;
-    const int fl = a.R == 1 ? e / N : e % FPW;
-    const int k = a.R == 1 ? e % N : e / FPW;
-    cd v = to_cd(raw[i]);
-    if (f0 + fl < a.F) {
+    const int fl = ain.fl(e), k = ain.k(e);
+    cx<T> w = {static_cast<T>(raw[i].x), static_cast<T>(raw[i].y)};
+    if (a.pro != PRO_NONE && f0 + fl < a.F) {  // the prologue in FP64
+      cd v = to_cd(raw[i]);
       if (a.pro == PRO_FLOW)
         v = flow_in(v, a.nl.tf, a.nl, flag);
-      else if (a.pro == PRO_G)
+      else
         v = g_cgl(v, a.nl);
+      w = {static_cast<T>(v.re), static_cast<T>(v.im)};
     }
-    tile[fl * FS + (k / N2) * P + (k % N2)] = {static_cast<T>(v.re), static_cast<T>(v.im)};
+    tile[fl * FS + (k / N2) * P + (k % N2)] = w;
   }
   __syncthreads();
   // forward, columns: length-N1 DFTs over j1, twiddle w_N^{j2 k1}
   if (tid < FPW * N2) {
-    const int fl = tid / N2, j2 = tid % N2;
+    const int fl = FF ? tid % FPW : tid / N2, j2 = FF ? tid / FPW : tid % N2;
     cx<T>* t = tile + fl * FS + j2;
     cx<T> x[N1];
 #pragma unroll
@@ -204,7 +258,7 @@ __global__ __launch_bounds__(256, N <= 128 ? 4 : 1) void k_pass_fft(PassFFT a) {
   // rows: length-N2 DFT over j2 (X[k1 + N1 k2]), the factors, the inverse
   // length-N2 DFT over k2 and the twiddle w_N^{-j2 k1}
   if (tid < FPW * N1) {
-    const int fl = tid / N1, k1 = tid % N1;
+    const int fl = FF ? tid % FPW : tid / N1, k1 = FF ? tid / FPW : tid % N1;
     cx<T>* t = tile + fl * FS + k1 * P;
     cx<T> y[N2];
 #pragma unroll
@@ -218,16 +272,16 @@ __global__ __launch_bounds__(256, N <= 128 ? 4 : 1) void k_pass_fft(PassFFT a) {
   }
   __syncthreads();
   // inverse, columns: length-N1 inverse DFTs over k1, scaled by 1/N
+  const T sc = static_cast<T>(1.0 / N);
   if (tid < FPW * N2) {
-    const int fl = tid / N2, j2 = tid % N2;
+    const int fl = FF ? tid % FPW : tid / N2, j2 = FF ? tid / FPW : tid % N2;
     cx<T>* t = tile + fl * FS + j2;
     cx<T> x[N1];
 #pragma unroll
     for (int k1 = 0; k1 < N1; ++k1) x[k1] = t[k1 * P];
     dft<N1, N2, true>(x, tw);
-    const T s = static_cast<T>(1.0 / N);
 #pragma unroll
-    for (int j1 = 0; j1 < N1; ++j1) t[j1 * P] = {x[j1].re * s, x[j1].im * s};
+    for (int j1 = 0; j1 < N1; ++j1) t[j1 * P] = {x[j1].re * sc, x[j1].im * sc};
   }
   __syncthreads();
   // store with the epilogue (consecutive threads take consecutive output
@@ -236,32 +290,29 @@ __global__ __launch_bounds__(256, N <= 128 ? 4 : 1) void k_pass_fft(PassFFT a) {
   // thread's auxiliary loads first
   const bool has_aux = a.epi == EPI_L4_R1 || a.epi == EPI_L4_R2 || a.epi == EPI_RICH ||
                        a.epi == EPI_L2;
+  const ElemAddr<N, FPW> aout(f0, a.R_out, tid);
   cd xa[EPT];
   if (has_aux) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int e = tid + 256 * i;
-      const int fl = a.R_out == 1 ? e / N : e % FPW;
-      const int m = a.R_out == 1 ? e % N : e / FPW;
-      const int64_t f = f0 + fl;
       xa[i] = cd{0.0, 0.0};
-      if (f < a.F)
-        xa[i] = load_in<T>(a.aux, fibre_base(f, a.R_out, N) + a.R_out * static_cast<int64_t>(m),
-                           a.aux_f64 != 0);
+      if (f0 + aout.fl(e) < a.F) xa[i] = load_in<T>(a.aux, aout.off(f0, e), a.aux_f64 != 0);
     }
   }
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = tid + 256 * i;
-    const int fl = a.R_out == 1 ? e / N : e % FPW;
-    const int m = a.R_out == 1 ? e % N : e / FPW;
-    const int64_t f = f0 + fl;
-    if (f >= a.F) continue;
-    const int64_t off = fibre_base(f, a.R_out, N) + a.R_out * static_cast<int64_t>(m);
+    const int fl = aout.fl(e), m = aout.k(e);
+    if (f0 + fl >= a.F) continue;
+    const int64_t off = aout.off(f0, e);
     const cx<T> c = tile[fl * FS + (m / N2) * P + (m % N2)];
     const cd y = {static_cast<double>(c.re), static_cast<double>(c.im)};
     if (a.epi == EPI_NONE) {
-      store_out(a.out0, off, out64, y);
+      if (out64)
+        reinterpret_cast<double2*>(a.out0)[off] = double2{static_cast<double>(c.re), static_cast<double>(c.im)};
+      else
+        reinterpret_cast<float2*>(a.out0)[off] = float2{static_cast<float>(c.re), static_cast<float>(c.im)};
     } else if (a.epi == EPI_FLOW || a.epi == EPI_MID) {
       const cd z = a.epi == EPI_FLOW ? flow_out(y, a.nl.tf, a.nl, flag)
                                      : flow_mid(y, a.nl.tf, a.nl, flag);

@@ -678,6 +678,8 @@ int main(int argc, char** argv) {
       fourier_parity({16, 8, 32}, prec, 21);
       fourier_parity({128, 4}, prec, 24);
       fourier_parity({256, 4}, prec, 25);
+      fourier_parity({512, 3}, prec, 30);    // fewer than 16 fibres per workgroup:
+      fourier_parity({1024, 3}, prec, 31);   // padded rows, spread fibres
     }
     fourier_parity({32, 16}, CGL_SPLIT_BF16, 26, CGL_FLAG_FP64_MASTER);
     fourier_parity({64, 12}, CGL_SPLIT_BF16, 27, CGL_FLAG_FP64_MASTER);
