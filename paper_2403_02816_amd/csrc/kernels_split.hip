@@ -75,6 +75,12 @@ __device__ __forceinline__ int64_t fibre_base(int64_t f, int64_t R, int n) {
   return (R == 1) ? f * (int64_t)n : (f % R) + (f / R) * R * (int64_t)n;
 }
 
+// start of fibre f < F in an output of stride R; a stride of at least F (the
+// rotated layouts, R = F) leaves f as it is, without a 64-bit division
+__device__ __forceinline__ int64_t fibre_start(int64_t f, int64_t R, int n, int64_t F) {
+  return R >= F ? f : fibre_base(f, R, n);
+}
+
 __device__ __forceinline__ unsigned xcd_remap(unsigned h, unsigned G) {
   return ((G & 7u) == 0u) ? (h & 7u) * (G >> 3) + (h >> 3) : h;
 }
@@ -187,7 +193,7 @@ __device__ __forceinline__ void split_epilogue(const PassSplit& a, int pt, int64
   if (a.epi == EPI_NONE) {
     const int64_t f = f0 + wf * 32 + (lane & 31);
     if (f < a.F) {
-      const int64_t base = fibre_base(f, a.R_out, a.n);
+      const int64_t base = fibre_start(f, a.R_out, a.n, a.F);
 #pragma unroll
       for (int b = 0; b < PB; ++b)
 #pragma unroll
@@ -209,6 +215,11 @@ __device__ __forceinline__ void split_epilogue(const PassSplit& a, int pt, int64
     // consecutive fibres of one row)
     constexpr int EP = FT + 1;  // row pitch in float2
     float2* sE = reinterpret_cast<float2*>(lds_mem);
+    // a thread keeps one fibre (column fc = tid mod FT) in the loops below
+    static_assert(256 % FT == 0, "one fibre per thread");
+    const int fc = tid % FT;
+    const int64_t f = f0 + fc;
+    const int64_t fst = f < a.F ? fibre_start(f, a.R_out, a.n, a.F) : 0;
 #pragma unroll
     for (int b = 0; b < PB; ++b) {
       // rows wp * (PT / 2) + b * 32 + [0, 32) of the tile -> LDS rows wp * 32 + [0, 32)
@@ -220,11 +231,10 @@ __device__ __forceinline__ void split_epilogue(const PassSplit& a, int pt, int64
       __syncthreads();
 #pragma unroll 1
       for (int e = tid; e < 64 * FT; e += 256) {
-        const int lr = e / FT, fc = e % FT;
+        const int lr = e / FT;
         const int m = pt * PT + (lr / 32) * (PT / 2) + b * 32 + (lr % 32);
-        const int64_t f = f0 + fc;
         if (m >= a.n || f >= a.F) continue;
-        const int64_t off = fibre_base(f, a.R_out, a.n) + a.R_out * (int64_t)m;
+        const int64_t off = fst + a.R_out * (int64_t)m;
         const float2 v = sE[lr * EP + fc];
         const cd y = {static_cast<double>(v.x), static_cast<double>(v.y)};
         if (a.epi == EPI_FLOW || a.epi == EPI_MID) {
@@ -694,7 +704,7 @@ __device__ __forceinline__ void pair_epilogue(const PassSplit& a, int pt, int64_
   // accumulator entry r holds row m1 + dm(r); its output element is o0 + R_out dm(r)
   const int m1 = pt * PT + wp * 32 + 4 * (lane >> 5);
   const int64_t Ro = a.R_out;
-  const int64_t o0 = fibre_base(f, a.R_out, a.n) + Ro * m1;
+  const int64_t o0 = fibre_start(f, a.R_out, a.n, a.F) + Ro * m1;
   const bool full = pt * PT + PT <= a.n;  // uniform: the tile has no rows past n
   auto each = [&](auto&& fn) __attribute__((always_inline)) {
     if (full) {
