@@ -40,10 +40,10 @@ MI355X_PEAK_HBM_GBS = 8000.0
 # (profiles/split_pass_c1_128_lawson4.md, profiles/split_pass_c2_256_lawson4.md).
 SPLIT_TRAFFIC = {
     # mean over the six paired launches of a step (128-row tiles, the shape the
-    # autotuner picks): (FETCH_SIZE x 2 + WRITE_SIZE) KiB = (15880 x 2 + 30037) KiB
-    "c1": {"bytes_per_launch": 63279445.0, "sources_sha256_16": "6d20cfcdfcecc63b"},
-    # (144803 x 2 + 240299) KiB = 1.011 x the algorithmic 536870912 bytes
-    "c2_lawson4": {"bytes_per_launch": 542622805.0, "sources_sha256_16": "6d20cfcdfcecc63b"},
+    # autotuner picks): (FETCH_SIZE x 2 + WRITE_SIZE) KiB = (15895 x 2 + 30037) KiB
+    "c1": {"bytes_per_launch": 63311616.0, "sources_sha256_16": "582f170e7c4d78e6"},
+    # (144817 x 2 + 240299) KiB = 1.011 x the algorithmic 536870912 bytes
+    "c2_lawson4": {"bytes_per_launch": 542650453.0, "sources_sha256_16": "582f170e7c4d78e6"},
 }
 SPLIT_SOURCES = ("kernels_split.hip", "kernels.hpp", "pointwise.hpp", "split_layout.cpp",
                  "split_layout.hpp")
