@@ -92,6 +92,11 @@ struct cgl_plan_s {
   NlParams nl{};
   // batched plans (batch > 0): independent instances, instance j has grid
   // bn[j*d .. j*d+d-1], coefficients bnl[j], and lives at complex offset boff[j]
+  // split contraction of small single-action passes (set by
+  // enable_split_contraction): one workspace per concurrent branch
+  bool ksplit = false;
+  float* ksws[2] = {nullptr, nullptr};
+  int64_t ksws_floats = 0;
   int batch = 0;
   std::vector<int64_t> bn, boff;
   std::vector<NlParams> bnl;
@@ -267,6 +272,24 @@ int pass(cgl_plan_s* p, int mu, int which, const void* in0, const void* aux, voi
     a.aux_f64 = p->aux_f64 ? 1 : 0;
     a.nl = p->nl;
     a.flag = p->dflag;
+    if (p->ksplit && SPLIT_TILES[t].dma) {
+      // too few tiles to fill the chip: split the contraction so that about
+      // 256 workgroups run, each over at least 4 stages
+      const int PT = SPLIT_TILES[t].PT;
+      const int64_t G = ((a.F + SP_FT - 1) / SP_FT) * (a.Pp / PT);
+      const int nKS = a.Kp / SPLIT_TILES[t].KS;
+      int S = static_cast<int>(std::min<int64_t>({4, (256 + G - 1) / G, nKS / 4}));
+      if (S >= 2) {
+        const int chunk = (nKS + S - 1) / S;
+        S = (nKS + chunk - 1) / chunk;
+        if (S >= 2 && S * G * (PT / 64) * 8192 <= p->ksws_floats) {
+          a.ksplit = S;
+          a.kchunk = chunk;
+          a.ws = p->ksws[s == p->bstream ? 1 : 0];
+          a.ws_floats = p->ksws_floats;
+        }
+      }
+    }
     e = launch_pass_split(a, s);
   }
   return e == hipSuccess ? CGL_OK : CGL_EDEVICE;
@@ -1335,6 +1358,8 @@ void cgl_destroy(cgl_plan_t p) {
   for (auto& o : p->bdH) free_op(o);
   for (void* s : p->stage)
     if (s) (void)hipFree(s);
+  for (float* w : p->ksws)
+    if (w) (void)hipFree(w);
   if (p->dflag) (void)hipFree(p->dflag);
   if (p->hflag) (void)hipHostFree(p->hflag);
   if (p->ev_in) (void)hipEventDestroy(p->ev_in);
@@ -1347,6 +1372,27 @@ void cgl_destroy(cgl_plan_t p) {
 }
 
 }  // extern "C"
+
+int cgl::enable_split_contraction(cgl_plan_t p) {
+  if (!p) return CGL_EINVAL;
+  if (p->precision != CGL_SPLIT_BF16 || p->batch > 0) return CGL_OK;
+  const char* env = std::getenv("CGL_KSPLIT");
+  if (env && std::strcmp(env, "0") == 0) return CGL_OK;
+  // the largest workspace a pass can ask for: 4 splits of every tile of the
+  // direct-to-LDS shapes (64 or 128 rows x 64 fibres), 8192 floats per 64 rows
+  int64_t need = 0;
+  for (int mu = 0; mu < p->d; ++mu) {
+    const int64_t n = p->n[mu], F = p->N / n;
+    need = std::max<int64_t>(need, 4 * ((n + 63) / 64 + 1) * ((F + SP_FT - 1) / SP_FT) * 8192);
+  }
+  for (float*& w : p->ksws)
+    if (!w && hipMalloc(reinterpret_cast<void**>(&w), static_cast<size_t>(need) * sizeof(float)) !=
+                  hipSuccess)
+      return CGL_ENOMEM;
+  p->ksws_floats = need;
+  p->ksplit = true;
+  return CGL_OK;
+}
 
 int cgl::tucker_with_scratch(cgl_plan_t p, int which, const void* in_dev, void* out_dev,
                              void* tmp0, void* tmp1) {

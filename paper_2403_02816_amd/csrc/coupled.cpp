@@ -186,6 +186,8 @@ int cgl_coupled_plan(cgl_coupled_t* out, const int64_t* n, const cgl_coupled_coe
       r = dev(hipStreamCreateWithFlags(&p->side[k][j], hipStreamNonBlocking));
       if (r == CGL_OK) r = dev(hipEventCreateWithFlags(&p->done[k][j], hipEventDisableTiming));
       if (r == CGL_OK) r = cgl_plan(&p->f[k][j], 2, n, &cf, tau, precision, 0, p->side[k][j]);
+      // a field's pass has few tiles (245 000-point fields at the paper's size)
+      if (r == CGL_OK) r = enable_split_contraction(p->f[k][j]);
     }
   for (int b = 0; b < 5 && r == CGL_OK; ++b)
     if (hipMalloc(&p->buf[b], 2 * static_cast<size_t>(p->N) * esz(p)) != hipSuccess) r = CGL_ENOMEM;

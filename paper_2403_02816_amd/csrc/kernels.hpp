@@ -108,6 +108,14 @@ struct PassSplit {
   int tile;     // index into SPLIT_TILES (the operator planes must match it)
   NlParams nl;
   unsigned* flag;
+  // split contraction (direct-to-LDS shapes; ksplit <= 1: off): ksplit <= 4
+  // workgroups per tile, kchunk stages each (every split gets at least one
+  // stage), partial accumulators in ws (ws_floats floats: at least
+  // ksplit x tiles x PT / 64 x 8192)
+  int ksplit;
+  int kchunk;
+  float* ws;
+  int64_t ws_floats;
 };
 
 constexpr int SP_FT = 64;    // fibres per workgroup (rows/stage sizes: split_layout.hpp)

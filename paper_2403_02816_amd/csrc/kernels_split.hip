@@ -473,9 +473,13 @@ struct LdsD {
   unsigned short B[2][6 * FT * KS];
 };
 
+// Stages [k0, k1) of the contraction (k1 < 0: every stage).  part == nullptr:
+// the epilogue stores the tile; otherwise the raw FP32 accumulators go to
+// part (the tile's slot of a split contraction, reduced by k_split_reduce).
 template <int PT, int KS, int PRO, bool IN64>
 __device__ __forceinline__ void split_tile_dma(const PassSplit& a, int pt, int64_t f0,
-                                               LdsD<PT, KS>& lds) {
+                                               LdsD<PT, KS>& lds, int k0 = 0, int k1 = -1,
+                                               float* part = nullptr) {
   static_assert(KS == 16, "one 16-deep MFMA step per stage");
   constexpr int KJ = KS / 4;               // state elements per thread and stage
   constexpr int PB = PT / 64;              // 32-row blocks per wave
@@ -492,6 +496,7 @@ __device__ __forceinline__ void split_tile_dma(const PassSplit& a, int pt, int64
   const int wp = wave & 1;
   const int wf = wave >> 1;
   const int nKS = uniform_i32(a.Kp / KS);
+  const int kend = k1 < 0 ? nKS : k1;  // stages past kend read out of range (zero)
   const __amdgpu_buffer_rsrc_t ors = __builtin_amdgcn_make_buffer_rsrc(
       uniform_ptr(const_cast<uint16_t*>(a.op + static_cast<size_t>(pt) * nKS * (6 * PT * KS))),
       0, nKS * ABYTES, 0x00020000);
@@ -507,7 +512,7 @@ __device__ __forceinline__ void split_tile_dma(const PassSplit& a, int pt, int64
   const unsigned svo = static_cast<unsigned>((fl * a.n + k0t) * ESZ);
 
   auto copy_op = [&](int ks, int buf) __attribute__((always_inline)) {
-    const unsigned o = ks < nKS ? static_cast<unsigned>(ks * ABYTES) : OOR;
+    const unsigned o = ks < kend ? static_cast<unsigned>(ks * ABYTES) : OOR;
 #pragma unroll
     for (int j = 0; j < NDMA; ++j) {
       const int blk = wave + 4 * j;
@@ -517,7 +522,7 @@ __device__ __forceinline__ void split_tile_dma(const PassSplit& a, int pt, int64
     }
   };
   auto load_state = [&](int ks, f32x4 (&v)[KJ / 2]) __attribute__((always_inline)) {
-    const unsigned o = ks < nKS ? svo + static_cast<unsigned>(ks * KS * ESZ) : OOR;
+    const unsigned o = ks < kend ? svo + static_cast<unsigned>(ks * KS * ESZ) : OOR;
 #pragma unroll
     for (int j = 0; j < KJ; j += 2) {
       if constexpr (IN64) {
@@ -574,10 +579,10 @@ __device__ __forceinline__ void split_tile_dma(const PassSplit& a, int pt, int64
   const int row = lane & 31;
   const int ch = lane >> 5;  // chunk of the 16-deep step this lane supplies
 
-  // stage ks: fragments of buffer ks % 2, copies into the other buffer
+  // stage ks: fragments of buffer (ks - k0) % 2, copies into the other buffer
   auto stage = [&](int ks, f32x4 (&vload)[KJ / 2], const f32x4 (&vstore)[KJ / 2])
       __attribute__((always_inline)) {
-    const int cur = ks & 1;
+    const int cur = (ks - k0) & 1;
     bf16x8 br[3], bi[3], ar[PB][3], ai[PB][3];
     {
       const int rb = wf * 32 + row;
@@ -626,23 +631,35 @@ __device__ __forceinline__ void split_tile_dma(const PassSplit& a, int pt, int64
   };
 
   f32x4 sv[2][KJ / 2];
-  copy_op(0, 0);
-  load_state(0, sv[0]);
-  load_state(1, sv[1]);
-  store_state(0, sv[0], 0);
+  copy_op(k0, 0);
+  load_state(k0, sv[0]);
+  load_state(k0 + 1, sv[1]);
+  store_state(k0, sv[0], 0);
   stage_barrier<NV>();
-  int ks = 0;
-  for (; ks + 1 < nKS; ks += 2) {
+  int ks = k0;
+  for (; ks + 1 < kend; ks += 2) {
     stage(ks, sv[0], sv[1]);
     stage(ks + 1, sv[1], sv[0]);
   }
-  if (ks < nKS) stage(ks, sv[0], sv[1]);
+  if (ks < kend) stage(ks, sv[0], sv[1]);
   // the copies issued by the last stage (out of range: zeros) still write
   // the other operator buffer, which the epilogue reuses
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
   __syncthreads();
-  static_assert(EPI_LDS_BYTES <= static_cast<int>(sizeof(LdsD<PT, KS>)), "epilogue staging fits");
-  split_epilogue<PT>(a, pt, f0, accr, acci, flag, &lds);
+  if (part) {
+    // raw accumulators, lane-interleaved: entry (b, r) of thread tid at
+    // part[((b * 32 + r) * 256) + tid] (r < 16 real, 16 + r imaginary)
+#pragma unroll
+    for (int b = 0; b < PB; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        part[(b * 32 + r) * 256 + tid] = accr[b][r];
+        part[(b * 32 + 16 + r) * 256 + tid] = acci[b][r];
+      }
+  } else {
+    static_assert(EPI_LDS_BYTES <= static_cast<int>(sizeof(LdsD<PT, KS>)), "epilogue staging fits");
+    split_epilogue<PT>(a, pt, f0, accr, acci, flag, &lds);
+  }
   if (flag) atomicOr(a.flag, flag);
 }
 
@@ -1016,6 +1033,70 @@ __global__ __launch_bounds__(256, 2) void k_pass_split_dma(PassSplit a) {
                                     lds);
 }
 
+// Split contraction (small passes: too few tiles to fill the chip).  The
+// grid is S x G tiles; the workgroup of split s takes stages
+// [s * a.kchunk, (s + 1) * a.kchunk) of its tile and writes its raw
+// accumulators to the workspace slot (s * G + tile); k_split_reduce sums the
+// S slots of a tile in split order and runs the epilogue.
+template <int PT, int KS, int PRO, bool IN64>
+__global__ __launch_bounds__(256, 2) void k_pass_split_dma_part(PassSplit a) {
+  __shared__ __attribute__((aligned(16))) LdsD<PT, KS> lds;
+  constexpr int SLOT = (PT / 64) * 32 * 256;  // floats per tile slot
+  const int nP = a.Pp / PT;
+  const unsigned G = gridDim.x / static_cast<unsigned>(a.ksplit);
+  const unsigned h = xcd_remap(blockIdx.x, gridDim.x);
+  const unsigned sp = h / G, w = h % G;
+  const int k0 = static_cast<int>(sp) * a.kchunk;
+  const int k1 = k0 + a.kchunk < a.Kp / KS ? k0 + a.kchunk : a.Kp / KS;
+  split_tile_dma<PT, KS, PRO, IN64>(a, static_cast<int>(w % nP), static_cast<int64_t>(w / nP) * FT,
+                                    lds, k0, k1, a.ws + (static_cast<size_t>(sp) * G + w) * SLOT);
+}
+
+template <int PT>
+__global__ __launch_bounds__(256, 2) void k_split_reduce(PassSplit a) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[EPI_LDS_BYTES];
+  constexpr int PB = PT / 64;
+  constexpr int SLOT = PB * 32 * 256;
+  const int nP = a.Pp / PT;
+  const unsigned G = gridDim.x, w = blockIdx.x;
+  const int tid = threadIdx.x;
+  f32x16 accr[PB], acci[PB];
+#pragma unroll
+  for (int b = 0; b < PB; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      accr[b][r] = 0.0f;
+      acci[b][r] = 0.0f;
+    }
+  // per 32-row block, the loads of every split (at most 4) are issued
+  // before the first sum; the sums run in split order
+#pragma unroll
+  for (int b = 0; b < PB; ++b) {
+    float v[4][32];
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) {
+#pragma unroll
+      for (int r = 0; r < 32; ++r) v[sp][r] = 0.0f;
+      if (sp < a.ksplit) {
+        const float* q = a.ws + (static_cast<size_t>(sp) * G + w) * SLOT + b * 32 * 256 + tid;
+#pragma unroll
+        for (int r = 0; r < 32; ++r) v[sp][r] = q[r * 256];
+      }
+    }
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        accr[b][r] += v[sp][r];
+        acci[b][r] += v[sp][16 + r];
+      }
+  }
+  unsigned flag = 0;
+  split_epilogue<PT>(a, static_cast<int>(w % nP), static_cast<int64_t>(w / nP) * FT, accr, acci,
+                     flag, lds);
+  if (flag) atomicOr(a.flag, flag);
+}
+
 // Batched form: a persistent grid walks a table of (instance, p-tile, fibre
 // tile) entries; each instance has its own grid size, coefficients and
 // operator planes, and lives at its own offset in every batched tensor.
@@ -1174,8 +1255,27 @@ void launch_dma_pro(const PassSplit& a, dim3 grid, hipStream_t s) {
     hipLaunchKernelGGL((k_pass_split_dma<PT, KS, PRO, false>), grid, dim3(256), 0, s, a);
 }
 
+template <int PT, int KS, int PRO>
+void launch_dma_part_pro(const PassSplit& a, dim3 grid, hipStream_t s) {
+  if (a.in_f64)
+    hipLaunchKernelGGL((k_pass_split_dma_part<PT, KS, PRO, true>), grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_pass_split_dma_part<PT, KS, PRO, false>), grid, dim3(256), 0, s, a);
+}
+
 template <int PT, int KS>
 void launch_tile_dma(const PassSplit& a, dim3 grid, hipStream_t s) {
+  if (a.ksplit > 1) {  // split contraction: partial products, then the reduction
+    const dim3 pgrid(grid.x * static_cast<unsigned>(a.ksplit));
+    if (a.pro == PRO_FLOW)
+      launch_dma_part_pro<PT, KS, PRO_FLOW>(a, pgrid, s);
+    else if (a.pro == PRO_G)
+      launch_dma_part_pro<PT, KS, PRO_G>(a, pgrid, s);
+    else
+      launch_dma_part_pro<PT, KS, PRO_NONE>(a, pgrid, s);
+    hipLaunchKernelGGL((k_split_reduce<PT>), grid, dim3(256), 0, s, a);
+    return;
+  }
   if (a.pro == PRO_FLOW)
     launch_dma_pro<PT, KS, PRO_FLOW>(a, grid, s);
   else if (a.pro == PRO_G)
@@ -1310,6 +1410,14 @@ hipError_t launch_pass_split(const PassSplit& a, hipStream_t s) {
   if (G > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 grid(static_cast<unsigned>(G));
   if (SPLIT_TILES[a.tile].dma && a.R != 1) return hipErrorInvalidValue;
+  if (a.ksplit > 1) {  // split contraction: the direct-to-LDS shapes only, a workspace that fits
+    const int nKS = a.Kp / KS;
+    if (!SPLIT_TILES[a.tile].dma || !a.ws || a.kchunk < 1 || a.ksplit > nKS || a.ksplit > 4 ||
+        static_cast<int64_t>(a.ksplit - 1) * a.kchunk >= nKS ||
+        static_cast<int64_t>(a.ksplit) * a.kchunk < nKS ||
+        a.ksplit * G * (PT / 64) * 32 * 256 > a.ws_floats)
+      return hipErrorInvalidValue;
+  }
   switch (a.tile) {
     case 0: launch_tile<64, 32>(a, grid, s); break;
     case 1: launch_tile<128, 16>(a, grid, s); break;

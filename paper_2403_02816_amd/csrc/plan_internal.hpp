@@ -30,4 +30,11 @@ int tucker_with_scratch(cgl_plan_t p, int which, const void* in_dev, void* out_d
 // first derivative's symbol i k, 0 for the Nyquist mode of an even n).
 int set_periodic_adv(cgl_plan_t p, int mu, double a, double b, double adv);
 
+// Split the contraction of a split-form plan's single-action passes when a
+// pass has too few tiles to fill the chip (partial products of stage ranges,
+// reduced in split order before the epilogue); allocates the plan's two
+// workspaces (one per concurrent branch).  No effect on FP64 or batched plans
+// or with CGL_KSPLIT=0 in the environment.
+int enable_split_contraction(cgl_plan_t p);
+
 }  // namespace cgl

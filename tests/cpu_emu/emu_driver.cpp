@@ -232,6 +232,50 @@ static void coupled(std::vector<int64_t> n, int precision, unsigned seed) {
   cgl_coupled_destroy(p);
 }
 
+// The coupled split form with its long dense directions' contractions split
+// over workgroups (partial products reduced in split order) against the
+// same steps with the split turned off (CGL_KSPLIT=0 at plan creation), for
+// both direct-to-LDS tile shapes (the only ones that split).
+static void coupled_ksplit(std::vector<int64_t> n, unsigned seed) {
+  const int64_t N = n[0] * n[1];
+  cgl_coupled_coeffs c{-0.4, 0.125, 0.5, -0.9, 1.0, 0.8, -0.1, -0.6, 0.5};
+  auto U = rnd(2 * N, seed, 0.5);
+  const char* tile0 = std::getenv("CGL_SPLIT_TILE");
+  const std::string saved = tile0 ? tile0 : "";
+  for (const char* tile : {"2", "3"}) {
+    setenv("CGL_SPLIT_TILE", tile, 1);
+    std::vector<std::complex<float>> res[2];
+    for (int off = 0; off < 2; ++off) {
+      if (off) setenv("CGL_KSPLIT", "0", 1);
+      cgl_coupled_t p = nullptr;
+      expect(cgl_coupled_plan(&p, n.data(), &c, 0.01, CGL_SPLIT_BF16, nullptr) == CGL_OK,
+             "ksplit plan");
+      if (off) unsetenv("CGL_KSPLIT");
+      for (int mu = 0; mu < 2; ++mu)
+        expect(cgl_coupled_set_periodic(p, mu, 0.0, 7.0 * (2 - mu)) == CGL_OK, "ksplit periodic");
+      res[off] = cast<float>(U);
+      for (int m : {CGL_LAWSON4, CGL_STRANG})
+        expect(cgl_coupled_step(p, m, res[off].data(), 1) == CGL_OK, "ksplit step");
+      expect(cgl_coupled_status(p) == CGL_OK, "ksplit status");
+      cgl_coupled_destroy(p);
+    }
+    double worst = 0.0, mx = 0.0;
+    for (int64_t i = 0; i < 2 * N; ++i) {
+      worst = std::max(worst, static_cast<double>(std::abs(res[0][i] - res[1][i])));
+      mx = std::max(mx, static_cast<double>(std::abs(res[1][i])));
+    }
+    std::printf("  coupled split contraction n=%lldx%lld tile %s: max diff %.2e (max %.2e)\n",
+                static_cast<long long>(n[0]), static_cast<long long>(n[1]), tile, worst, mx);
+    // the split sums the stages in another order: FP32 rounding, not bits
+    expect(std::isfinite(mx) && mx > 0.0 && worst < 1e-5 * mx, "split contraction = unsplit");
+    expect(worst > 0.0, "the contraction was split");
+  }
+  if (tile0)
+    setenv("CGL_SPLIT_TILE", saved.c_str(), 1);
+  else
+    unsetenv("CGL_SPLIT_TILE");
+}
+
 static void steppers(std::vector<int64_t> n, int precision, unsigned flags, cgl_coeffs c,
                      double a, double b, int bc) {
   const int d = static_cast<int>(n.size());
@@ -668,6 +712,8 @@ int main(int argc, char** argv) {
     lap("fourier");
     coupled({16, 8}, CGL_FP64, 28);
     lap("coupled");
+    coupled_ksplit({144, 6}, 32);
+    lap("split contraction");
     std::printf("%s (%d failures)\n", failures ? "FAILED" : "PASSED", failures);
     return failures ? 1 : 0;
   }
@@ -687,6 +733,8 @@ int main(int argc, char** argv) {
       coupled({16, 8}, prec, 28);   // Fourier passes
       coupled({12, 6}, prec, 29);   // dense circulant exponentials
     }
+    coupled_ksplit({144, 6}, 32);   // 9 stages: 2 splits of 5 and 4
+    coupled_ksplit({208, 6}, 33);   // 13 stages: 3 splits of 5, 5 and 3
     std::printf("%s (%d failures)\n", failures ? "FAILED" : "PASSED", failures);
     return failures ? 1 : 0;
   }

@@ -4,7 +4,8 @@ against the FP64 oracle (numpy transforms with the plan's exported factors):
 * the per-field factors (advection +-a0 d_1) equal the oracle's;
 * FP64 trajectories of Strang, split4, Lawson2b and Lawson4 within 1e-12
   (relative 2-norm and max-norm), on Fourier-pass and dense-circulant grids;
-* complex64 one-step gates within 1e-6 (split4's max-norm within 1.5e-6);
+* complex64 one-step gates within 1e-6 (split4's max-norm within 1.5e-6),
+  also with the long dense directions' contractions split over workgroups;
 * the mirror symmetry of the system (x1 -> L - x1 with u <-> v);
 * the Table 5 experiment (700 x 350 modes on (0,70) x (0,35), the soliton
   datum, T = 3) in FP64: the errors of if2, if4, strang and split4 at the
@@ -105,6 +106,41 @@ def test_split_one_step_gates(method):
         # the dense n = 100 direction (measured 1.07e-6; the 2-norm stays < 1e-6)
         assert_close(got, ref, 1e-6, f"coupled split {n} {method}",
                      linf_tol=1.5e-6 if method == "split4" else 1e-6)
+
+
+@pytest.mark.parametrize("tile", ["2", "3"])
+def test_split_contraction_matches_unsplit_and_oracle(tile, monkeypatch):
+    """Dense directions of 300 and 150 points have too few tiles to fill the
+    chip: their contractions are split over workgroups (19 stages in 4
+    splits, 10 in 2), the partial products summed in split order.  One split
+    Lawson4 step with and without the split (CGL_KSPLIT=0 at plan creation)
+    against the oracle (the 1e-6 gate each; they differ by FP32 rounding)."""
+    torch = require_gpu()
+    n, tau = (300, 150), 3.0 / 500
+    monkeypatch.setenv("CGL_SPLIT_TILE", tile)   # a direct-to-LDS shape (the ones that split)
+    W0 = _datum(n).astype(np.complex64).astype(np.complex128)
+    out = {}
+    for ks in ("1", "0"):
+        monkeypatch.setenv("CGL_KSPLIT", ks)
+        p = _plan(n, co.PAPER, tau, "split")
+        w = p.to_device(W0)
+        p.step("lawson4", w, 1)
+        torch.cuda.synchronize()
+        assert p.status() == 0
+        out[ks] = p.to_host(w)
+        if ks == "1":
+            E, H = _LibAction(p, 0), _LibAction(p, 1)
+        p.destroy()
+    ref = steppers.make_step("lawson4", E, H, tau, co.CoupledNonlinearity(co.PAPER))(W0)
+    # max-norm bound 1.5e-6 as for the other dense gates of the coupled
+    # system: at n = 300 the unsplit step's FP32 accumulation reaches 1.49e-6
+    # on this datum (the split one 0.97e-6: shorter FP32 chains)
+    assert_close(out["1"], ref, 1e-6, f"coupled split contraction tile {tile}", linf_tol=1.5e-6)
+    assert_close(out["0"], ref, 1e-6, f"coupled unsplit contraction tile {tile}", linf_tol=1.5e-6)
+    # both within the gates of the exact step, so within twice them of each other
+    assert_close(out["1"], out["0"], 2e-6, f"split contraction vs unsplit, tile {tile}",
+                 linf_tol=3e-6)
+    assert not np.array_equal(out["1"], out["0"])   # the split path ran
 
 
 def test_nonfinite_state_is_reported():
