@@ -40,10 +40,10 @@ MI355X_PEAK_HBM_GBS = 8000.0
 # (profiles/split_pass_c1_128_lawson4.md, profiles/split_pass_c2_256_lawson4.md).
 SPLIT_TRAFFIC = {
     # mean over the six paired launches of a step (128-row tiles, the shape the
-    # autotuner picks): (FETCH_SIZE x 2 + WRITE_SIZE) KiB = (15895 x 2 + 30037) KiB
-    "c1": {"bytes_per_launch": 63311616.0, "sources_sha256_16": "582f170e7c4d78e6"},
-    # (144817 x 2 + 240299) KiB = 1.011 x the algorithmic 536870912 bytes
-    "c2_lawson4": {"bytes_per_launch": 542650453.0, "sources_sha256_16": "582f170e7c4d78e6"},
+    # autotuner picks): (FETCH_SIZE x 2 + WRITE_SIZE) KiB = (15888 x 2 + 30037) KiB
+    "c1": {"bytes_per_launch": 63296683.0, "sources_sha256_16": "c15fdcc26ffd29a0"},
+    # (144818 x 2 + 240299) KiB = 1.011 x the algorithmic 536870912 bytes
+    "c2_lawson4": {"bytes_per_launch": 542652224.0, "sources_sha256_16": "c15fdcc26ffd29a0"},
 }
 SPLIT_SOURCES = ("kernels_split.hip", "kernels.hpp", "pointwise.hpp", "split_layout.cpp",
                  "split_layout.hpp")
