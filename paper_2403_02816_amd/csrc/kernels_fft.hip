@@ -112,14 +112,20 @@ struct FftGeom {
 // conflict-free as well.  complex128: consecutive threads take consecutive
 // columns (rows) of one fibre, rows padded by one element (measured faster
 // for 16-byte elements, whose kernel is at its register bound).
+// threads per workgroup: 512 for the complex64 length-128 pass (32 fibres:
+// 256-byte runs of a strided tensor per index), 256 otherwise
+template <typename T, int N>
+constexpr int fft_threads() { return sizeof(T) == 4 && N == 128 ? 512 : 256; }
+
 template <typename T, int N>
 struct FftTile {
   using Gm = FftGeom<N>;
-  static constexpr int FPW_MAX = 256 / Gm::N1;
-  static constexpr int FPW_LDS = (sizeof(T) == 8 ? 2048 : 4096) / N;
+  static constexpr int NT = fft_threads<T, N>();
+  static constexpr int FPW_MAX = NT / Gm::N1;
+  static constexpr int FPW_LDS = (sizeof(T) == 8 ? 2048 : 4096) * (NT / 256) / N;
   static constexpr int FPW = FPW_MAX < FPW_LDS ? FPW_MAX : (FPW_LDS > 0 ? FPW_LDS : 1);
-  static constexpr int EPT = FPW * N / 256;  // tensor elements per thread
-  static_assert(EPT * 256 == FPW * N, "a workgroup's fibres fill its threads evenly");
+  static constexpr int EPT = FPW * N / NT;  // tensor elements per thread
+  static_assert(EPT * NT == FPW * N, "a workgroup's fibres fill its threads evenly");
   static constexpr bool FF = sizeof(T) == 4;
   static constexpr int G = FPW >= 16 ? 1 : 16 / FPW;
   static constexpr int P = FF && G == 1 ? Gm::N2 : Gm::N2 + 1;
@@ -129,14 +135,14 @@ struct FftTile {
 
 // Offsets of a workgroup's elements in a tensor whose fibres have stride R
 // (fibre f starts at (f mod R) + (f div R) R n).  Element i of a thread is
-// e = tid + 256 i: with R = 1 (contiguous fibres) fibre e / n, index e mod n;
+// e = tid + NT i: with R = 1 (contiguous fibres) fibre e / n, index e mod n;
 // otherwise fibre e mod FPW, index e / FPW, so all elements of a thread lie
 // on one fibre, whose start is computed once.  The first fibre f0 is a
 // multiple of FPW: when R is one too, the workgroup's fibres share f div R,
 // a division of uniform values.
-template <int N, int FPW>
+template <int N, int FPW, int NT>
 struct ElemAddr {
-  static_assert(256 % FPW == 0, "a thread keeps one fibre when R > 1");
+  static_assert(NT % FPW == 0, "a thread keeps one fibre when R > 1");
   bool contig;
   int64_t R, fst;  // fst: start of the thread's fibre (R > 1)
   __device__ __forceinline__ ElemAddr(int64_t f0, int64_t R_, int tid) : contig(R_ == 1), R(R_), fst(0) {
@@ -194,11 +200,11 @@ __device__ __forceinline__ void store_out(void* p, int64_t off, bool f64, cd v) 
 // Lengths up to 128 keep four workgroups (16 waves) per CU resident (at most
 // 128 VGPRs): a 128^3 pass is then one round of workgroups.
 template <typename T, int N, bool IN64>
-__global__ __launch_bounds__(256, N <= 128 ? 4 : 1) void k_pass_fft(PassFFT a) {
+__global__ __launch_bounds__((fft_threads<T, N>()), N <= 128 ? 4 : 1) void k_pass_fft(PassFFT a) {
   using G = FftGeom<N>;
   using Tl = FftTile<T, N>;
   constexpr int N1 = G::N1, N2 = G::N2;
-  constexpr int FPW = Tl::FPW, EPT = Tl::EPT;
+  constexpr int FPW = Tl::FPW, EPT = Tl::EPT, NT = Tl::NT;
   constexpr int P = Tl::P, FS = Tl::FS;  // LDS row pitch and fibre stride (complex)
   constexpr bool FF = Tl::FF;            // fibres across consecutive threads
   __shared__ cx<T> tile[FPW * FS];
@@ -213,23 +219,23 @@ __global__ __launch_bounds__(256, N <= 128 ? 4 : 1) void k_pass_fft(PassFFT a) {
   // contiguous fibre, or consecutive fibres of one index when strided): every
   // load of the thread is issued before the first is used, then the
   // prologue and the LDS stores
-  const ElemAddr<N, FPW> ain(f0, a.R, tid);
+  const ElemAddr<N, FPW, NT> ain(f0, a.R, tid);
   Raw<IN64> raw[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int e = tid + 256 * i;
+    const int e = tid + NT * i;
     raw[i] = Raw<IN64>{0, 0};
     if (f0 + ain.fl(e) < a.F) raw[i] = load_raw<IN64>(a.in0, ain.off(f0, e));
   }
   // the twiddle table and the factors, loaded behind the tensor's elements
-  for (int q = tid; q < N; q += 256) {
+  for (int q = tid; q < N; q += NT) {
     const double2 w = reinterpret_cast<const double2*>(a.tw)[q];
     tw[q] = {static_cast<T>(w.x), static_cast<T>(w.y)};
     efac[q] = reinterpret_cast<const cx<T>*>(a.fac)[q];
   }
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int e = tid + 256 * i;
+    const int e = tid + NT * i;
     const int fl = ain.fl(e), k = ain.k(e);
     cx<T> w = {static_cast<T>(raw[i].x), static_cast<T>(raw[i].y)};
     if (a.pro != PRO_NONE && f0 + fl < a.F) {  // the prologue in FP64
@@ -290,19 +296,19 @@ __global__ __launch_bounds__(256, N <= 128 ? 4 : 1) void k_pass_fft(PassFFT a) {
   // thread's auxiliary loads first
   const bool has_aux = a.epi == EPI_L4_R1 || a.epi == EPI_L4_R2 || a.epi == EPI_RICH ||
                        a.epi == EPI_L2;
-  const ElemAddr<N, FPW> aout(f0, a.R_out, tid);
+  const ElemAddr<N, FPW, NT> aout(f0, a.R_out, tid);
   cd xa[EPT];
   if (has_aux) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + NT * i;
       xa[i] = cd{0.0, 0.0};
       if (f0 + aout.fl(e) < a.F) xa[i] = load_in<T>(a.aux, aout.off(f0, e), a.aux_f64 != 0);
     }
   }
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int e = tid + 256 * i;
+    const int e = tid + NT * i;
     const int fl = aout.fl(e), m = aout.k(e);
     if (f0 + fl >= a.F) continue;
     const int64_t off = aout.off(f0, e);
@@ -344,11 +350,11 @@ hipError_t launch_n(const PassFFT& a, hipStream_t s) {
   if (G > 0x7fffffffLL) return hipErrorInvalidValue;
   if constexpr (sizeof(T) == 8) {
     if (!a.in_f64) return hipErrorInvalidValue;  // FP64 passes read complex128
-    hipLaunchKernelGGL((k_pass_fft<T, N, true>), dim3(static_cast<unsigned>(G)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_pass_fft<T, N, true>), dim3(static_cast<unsigned>(G)), dim3(fft_threads<T, N>()), 0, s, a);
   } else if (a.in_f64) {
-    hipLaunchKernelGGL((k_pass_fft<T, N, true>), dim3(static_cast<unsigned>(G)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_pass_fft<T, N, true>), dim3(static_cast<unsigned>(G)), dim3(fft_threads<T, N>()), 0, s, a);
   } else {
-    hipLaunchKernelGGL((k_pass_fft<T, N, false>), dim3(static_cast<unsigned>(G)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_pass_fft<T, N, false>), dim3(static_cast<unsigned>(G)), dim3(fft_threads<T, N>()), 0, s, a);
   }
   return hipGetLastError();
 }
